@@ -1,0 +1,250 @@
+/*
+ * gsplat_mi355x.h -- C ABI of the MI355X (gfx950) differentiable tile rasterizer of
+ * 3D Gaussians, following the gsplat mathematical supplement (arXiv 2312.02121).
+ *
+ * Pipeline (forward, Sec. 2):   gs_project -> gs_bin_and_sort -> gs_rasterize_fwd
+ * Pipeline (backward, Sec. 3):  gs_rasterize_bwd -> gs_project_bwd
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array argument is a DEVICE pointer to caller-owned memory, except the
+ *   descriptor structs themselves (gs_gaussians, gs_splats, gs_bins, gs_params),
+ *   which are read on the host during the call and may live anywhere. The camera
+ *   array `cams` is a device array of gs_camera.
+ * - Layouts are structure-of-arrays, component-major float32 planes: a [3][n]
+ *   array holds the x plane (n floats), then the y plane, then the z plane.
+ * - Every call is stream-ordered and asynchronous on `stream` (a hipStream_t;
+ *   NULL = the null stream). No call allocates device memory, synchronises the
+ *   host, or writes with hipMemset, so a sequence of calls may be captured in a
+ *   HIP graph.
+ * - Calls never throw, print or abort. They return a gs_status. On GS_ERR_HIP
+ *   the HIP error code is kept for gs_last_hip_error(). gs_last_error_message()
+ *   gives a short text for the last failure of the calling thread.
+ * - Gradient outputs are ACCUMULATED (+=): zero them first (gs_zero is graph-safe).
+ *
+ * Readings of the paper that fix the conventions (each is pinned by a CPU test of the
+ * FP64 oracle):
+ * - quaternions are (w, x, y, z) (Sec. 3.2.1); R(q) is the polynomial of eq. (5) with
+ *   R11 = 1 - 2(x^2 + z^2); q is not renormalised.
+ * - mu' follows eq. (2) literally, so a point on the optical axis lands at
+ *   (c_x + 1/2, c_y + 1/2); pixel (row i, col j) has centre (j + 1/2, i + 1/2) and
+ *   Delta = mu' - pixel centre.
+ * - a Gaussian is culled unless near < t_z < far, Sigma' has positive determinant
+ *   and its 3-sigma tile box meets the image.
+ * - the 3-sigma box has half extents 3 sqrt(Sigma'_00), 3 sqrt(Sigma'_11); tile k
+ *   covers pixel coordinates [16k, 16k + 16).
+ * - alpha = min(alpha_max, o exp(-sigma)); entries with alpha < alpha_min are
+ *   skipped; compositing stops before the first entry whose T (1 - alpha) would drop
+ *   below T_min (that entry is not composited).
+ */
+#ifndef GSPLAT_MI355X_H
+#define GSPLAT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_TILE 16
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = -1,   /* null pointer, negative size, inconsistent descriptor */
+    GS_ERR_CAPACITY = -2,  /* a caller buffer is too small (host-checkable sizes only) */
+    GS_ERR_HIP = -3,       /* a HIP call failed; see gs_last_hip_error() */
+    GS_ERR_DEVICE = -4     /* the current device is not a gfx950 GPU */
+} gs_status;
+
+/*
+ * One camera (eq. 1: extrinsics T_cw = [R_cw t_cw; 0 1], intrinsics f, c, image size
+ * w x h, clipping planes n, f) plus its place in a batch. 128 bytes; the library
+ * reads an array of them from device memory.
+ */
+typedef struct gs_camera {
+    float R[9];             /* R_cw, row-major: camera = R_cw * world + t_cw */
+    float t[3];             /* t_cw */
+    float fx, fy, cx, cy;   /* focal lengths and principal point, pixels */
+    int32_t width, height;  /* w, h */
+    float near_plane;       /* n: Gaussians with t_z <= n are culled */
+    float far_plane;        /* f: Gaussians with t_z >= f are culled */
+    int64_t gauss_offset;   /* first Gaussian of this camera's scene in the gs_gaussians planes */
+    int64_t gauss_count;    /* number of Gaussians in that scene */
+    int64_t proj_offset;    /* first projected slot: slot = proj_offset + (gaussian - gauss_offset) */
+    int64_t pixel_offset;   /* first pixel in the image planes: pixel = offset + row * width + col */
+    int32_t tile_offset;    /* first global tile id: tile = offset + ty * tiles_x + tx */
+    int32_t tiles_x;        /* ceil(width / 16) */
+    int32_t tiles_y;        /* ceil(height / 16) */
+    int32_t reserved;
+} gs_camera;
+
+/*
+ * Gaussian parameters (Sec. 2: mean mu, covariance via scale s and rotation q,
+ * colour c, opacity o). Several scenes are concatenated along n; a camera names its
+ * scene by (gauss_offset, gauss_count). Read-only device planes.
+ */
+typedef struct gs_gaussians {
+    const float *means;      /* [3][n] */
+    const float *quats;      /* [4][n], (w, x, y, z) planes */
+    const float *scales;     /* [3][n], linear scales s (eq. 6) */
+    const float *colors;     /* [3][n] */
+    const float *opacities;  /* [n] */
+    int64_t n;
+} gs_gaussians;
+
+/*
+ * Projected 2D Gaussians ("splats"), one slot per (camera, Gaussian of its scene):
+ * P = sum over cameras of gauss_count. Written by gs_project.
+ *   rec[p*12 + 0..1]  mu' (eq. 2), pixels
+ *   rec[p*12 + 2..4]  conic Y = Sigma'^{-1} (eq. 4 inverted): Y00, Y01, Y11
+ *   rec[p*12 + 5]     opacity o
+ *   rec[p*12 + 6..8]  colour c
+ *   rec[p*12 + 9]     depth t_z
+ *   rec[p*12 + 10]    scene Gaussian index (int32 bits)
+ *   rec[p*12 + 11]    camera index (int32 bits)
+ * mu', Y and depth are computed in float64 and rounded once to float32.
+ */
+typedef struct gs_splats {
+    float *rec;              /* [P][12], 16-byte aligned */
+    float *depth;            /* [P] t_z, 0 when culled */
+    int32_t *rect;           /* [P][4] tile box x0, y0, x1, y1, inclusive, camera-local */
+    int32_t *tiles_touched;  /* [P] tiles in the box; 0 = culled */
+    int64_t capacity;        /* P */
+} gs_splats;
+
+/* Compositing thresholds (see the readings above). Defaults: 1/255, 0.99, 1e-4. */
+typedef struct gs_params {
+    float alpha_min;
+    float alpha_max;
+    float T_min;
+    int32_t reserved;
+} gs_params;
+
+/*
+ * Tile-intersection list (Sec. 2.2): one entry per (splat, tile of its box), sorted by
+ * key = (global tile << 32) | float32 bits of depth, equal keys in splat order.
+ */
+typedef struct gs_bins {
+    uint64_t *keys;          /* [capacity] */
+    int32_t *ids;            /* [capacity] splat slot of each entry */
+    int32_t *ranges;         /* [n_tiles][2] start, end of each tile's run; empty tile = (0, 0) */
+    int64_t *counters;       /* [2]: K = total intersections (may exceed capacity), overflow flag */
+    int64_t capacity;        /* K_cap, at most 2^31 - 1 */
+    int32_t n_tiles;         /* sum over cameras of tiles_x * tiles_y */
+    int32_t reserved;
+} gs_bins;
+
+/* ------------------------------------------------------------------------- utilities */
+
+/* Returns GS_OK if the current HIP device is a gfx950 GPU, GS_ERR_DEVICE otherwise. */
+int gs_device_check(void);
+
+/* HIP error code of the last GS_ERR_HIP returned on this thread (0 if none). */
+int gs_last_hip_error(void);
+
+/* Static text describing the last failure on this thread ("" if none). */
+const char *gs_last_error_message(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int gs_version(void);
+
+/* Zeroes `bytes` bytes at device pointer `ptr` with a kernel (graph-capturable). */
+int gs_zero(void *ptr, size_t bytes, void *stream);
+
+/*
+ * Host-only query of the ABI struct layout, for bindings that mirror the structs:
+ * writes up to n int64 values (sizeof and selected offsetof of gs_camera,
+ * gs_gaussians, gs_splats, gs_params, gs_bins, in the order of the implementation)
+ * to out and returns how many values exist. Touches no device.
+ */
+int gs_abi_layout(int64_t *out, int n);
+
+/* --------------------------------------------------------------------- forward (Sec. 2) */
+
+/*
+ * Sec. 2.1 (eqs. 1-6) and the 3-sigma box of Sec. 2.2, for every (camera, Gaussian)
+ * pair: R(q), Sigma = R S S^T R^T, t = T_cw [mu; 1], t' = P t, mu', J, Sigma' =
+ * J R_cw Sigma R_cw^T J^T, Y = Sigma'^{-1}, box and tile count.
+ * g: Gaussian planes. cams: device array of n_cams cameras whose proj_offset ranges
+ * tile [0, n_splats). out: splat buffers of capacity >= n_splats.
+ * Errors: GS_ERR_INVALID for null pointers, n_cams < 1, n_splats < 0 or
+ * n_splats > out->capacity.
+ */
+int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
+               gs_splats *out, void *stream);
+
+/* Bytes of workspace gs_bin_and_sort needs for n_splats splats and a list capacity. */
+size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles);
+
+/*
+ * Sec. 2.2: duplicate each splat once per tile of its box, sort the entries by
+ * (tile, depth) with a stable LSD radix sort (ties keep splat order), and find each
+ * tile's [start, end). K is written to bins->counters[0]; if K exceeds
+ * bins->capacity only the first `capacity` entries (in splat order) are emitted,
+ * counters[1] is set to 1 and the list is incomplete: the caller reads the flag,
+ * regrows and calls again. workspace: device memory of at least
+ * gs_bin_and_sort_workspace_size() bytes. cams: as for gs_project.
+ * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1]),
+ * GS_ERR_CAPACITY (workspace too small).
+ */
+int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                    gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Sec. 2.2, eq. (7): per pixel, composite its tile's list front to back with online
+ * transmittance. One workgroup per 16x16 tile.
+ * Outputs over the packed pixels of all cameras (n_pixels = sum of width * height):
+ *   image   [3][n_pixels]  C
+ *   T_final [n_pixels]     T after the last composited entry
+ *   last    [n_pixels]     1 + list position (within the tile's run) of the last
+ *                          composited entry, 0 if none: where the backward starts
+ *   visited [n_pixels]     optional (NULL to skip): entries whose alpha was evaluated,
+ *                          including a terminating entry
+ * Errors: GS_ERR_INVALID for null pointers or inconsistent sizes.
+ */
+int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const gs_camera *cams, int32_t n_cams,
+                     const gs_params *prm, int64_t n_pixels, float *image, float *T_final,
+                     int32_t *last, int32_t *visited, void *stream);
+
+/* -------------------------------------------------------------------- backward (Sec. 3) */
+
+/*
+ * Sec. 3.1 (eqs. 16-21): walk each pixel's list back to front from `last`, recover
+ * T by division from T_final (eq. 17), recompute sigma and alpha, and accumulate:
+ *   dL_dmean2d [2][n_splats]    dL/dmu'
+ *   dL_dconic  [3][n_splats]    dL/dY as the (0,0), (0,1), (1,1) entries of the
+ *                               full-matrix gradient (the off-diagonal is not doubled)
+ *   dL_dcolors [3][n_gaussians] dL/dc per scene Gaussian
+ *   dL_dopac   [n_gaussians]    dL/do per scene Gaussian
+ * dL_dimage [3][n_pixels]; T_final and last from gs_rasterize_fwd with the same
+ * inputs. Gradients of clamped alphas (o exp(-sigma) > alpha_max) reach only c.
+ * Outputs are accumulated; zero them first.
+ * Errors: GS_ERR_INVALID for null pointers, bad sizes, or alpha_max >= 1 (the
+ * division of eq. 17 needs 1 - alpha > 0).
+ */
+int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
+                     int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *dL_dimage,
+                     const float *T_final, const int32_t *last, float *dL_dmean2d, float *dL_dconic,
+                     int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream);
+
+/*
+ * Sec. 3.2 and 3.2.1 (eqs. 22-31): from dL/dmu' and dL/dY of each visible splat,
+ * dL/dSigma' = -Y dL/dY Y, the mean route of eq. (23) (second row with h), the
+ * covariance route through T = J R_cw and dJ/dt, then dL/dmu = R_cw^T dL/dt,
+ * dL/dSigma = T^T dL/dSigma' T, dL/dM = 2 dL/dSigma M, dL/dR = dL/dM S^T,
+ * dL/dS = R^T dL/dM, dL/dq = <dL/dR, dR/dq>, dL/ds_j = (dL/dS)_jj.
+ * Scene gradients [3][n] means, [3][n] scales, [4][n] quats are accumulated over
+ * cameras. dL_dcampose: optional (NULL to skip) [n_cams][12] row-major 3x4 gradient of
+ * [R_cw | t_cw] per camera (eq. 28 plus the R_cw term through T = J R_cw).
+ */
+int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, const gs_splats *s,
+                   int64_t n_splats, const float *dL_dmean2d, const float *dL_dconic,
+                   float *dL_dmeans, float *dL_dscales, float *dL_dquats, float *dL_dcampose,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSPLAT_MI355X_H */

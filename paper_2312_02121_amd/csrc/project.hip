@@ -1,0 +1,142 @@
+// gs_project: projection of 3D Gaussians (Sec. 2.1, eqs. 1-6) and their 3-sigma tile
+// boxes (Sec. 2.2). One thread per (camera, Gaussian) slot.
+//
+// The arithmetic runs in float64 without FMA contraction and every sum is evaluated
+// left to right in the order the equations are written (matrix products row by
+// column). mu', Y = Sigma'^{-1} and t_z are rounded once to float32 when stored, and
+// the tile box is decided on the float64 values. Projection is HBM-bound (40 bytes in,
+// ~84 bytes out per slot), so the float64 arithmetic costs nothing measurable and
+// makes the discrete outputs (box, tile count) reproducible.
+#include "common.h"
+
+namespace gsx {
+
+__global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
+                                                      int n_cams, int64_t n_splats, float4 *__restrict__ rec,
+                                                      float *__restrict__ depth_out, int4 *__restrict__ rect_out,
+                                                      int32_t *__restrict__ tiles_out)
+{
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_splats) return;
+    const int c = camera_of_splat(cams, n_cams, p);
+    const gs_camera &cam = cams[c];
+    const int64_t n = g.n;
+    const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
+
+    const double mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
+    const double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    const double s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
+
+    int visible = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(qw) && isfinite(qx) &&
+                  isfinite(qy) && isfinite(qz) && isfinite(s0) && isfinite(s1) && isfinite(s2);
+
+    // t = T_cw [mu; 1]
+    const double R00 = cam.R[0], R01 = cam.R[1], R02 = cam.R[2];
+    const double R10 = cam.R[3], R11 = cam.R[4], R12 = cam.R[5];
+    const double R20 = cam.R[6], R21 = cam.R[7], R22 = cam.R[8];
+    const double tx = R00 * mx + R01 * my + R02 * mz + (double)cam.t[0];
+    const double ty = R10 * mx + R11 * my + R12 * mz + (double)cam.t[1];
+    const double tz = R20 * mx + R21 * my + R22 * mz + (double)cam.t[2];
+    visible = visible && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz < (double)cam.far_plane;
+
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    int4 box = make_int4(0, 0, 0, 0);
+    int32_t tiles = 0;
+    float dep = 0.f;
+
+    if (visible) {
+        // R(q), eq. (5) with R11 = 1 - 2(x^2 + z^2); M = R S; Sigma = M M^T (eq. 6)
+        const double q00 = 1.0 - 2.0 * (qy * qy + qz * qz), q01 = 2.0 * (qx * qy - qw * qz), q02 = 2.0 * (qx * qz + qw * qy);
+        const double q10 = 2.0 * (qx * qy + qw * qz), q11 = 1.0 - 2.0 * (qx * qx + qz * qz), q12 = 2.0 * (qy * qz - qw * qx);
+        const double q20 = 2.0 * (qx * qz - qw * qy), q21 = 2.0 * (qy * qz + qw * qx), q22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+        const double M00 = q00 * s0, M01 = q01 * s1, M02 = q02 * s2;
+        const double M10 = q10 * s0, M11 = q11 * s1, M12 = q12 * s2;
+        const double M20 = q20 * s0, M21 = q21 * s1, M22 = q22 * s2;
+        const double S00 = M00 * M00 + M01 * M01 + M02 * M02;
+        const double S01 = M00 * M10 + M01 * M11 + M02 * M12;
+        const double S02 = M00 * M20 + M01 * M21 + M02 * M22;
+        const double S11 = M10 * M10 + M11 * M11 + M12 * M12;
+        const double S12 = M10 * M20 + M11 * M21 + M12 * M22;
+        const double S22 = M20 * M20 + M21 * M21 + M22 * M22;
+
+        // t' = P t with P of eq. (1); mu' of eq. (2)
+        const double w = (double)cam.width, h = (double)cam.height;
+        const double fx = cam.fx, fy = cam.fy;
+        const double tpx = (2.0 * fx / w) * tx;
+        const double tpy = (2.0 * fy / h) * ty;
+        const double mu0 = (w * tpx / tz + 1.0) / 2.0 + (double)cam.cx;
+        const double mu1 = (h * tpy / tz + 1.0) / 2.0 + (double)cam.cy;
+
+        // J of eq. (3) and T = J R_cw
+        const double J00 = fx / tz, J02 = -(fx * tx) / (tz * tz);
+        const double J11 = fy / tz, J12 = -(fy * ty) / (tz * tz);
+        const double T00 = J00 * R00 + J02 * R20, T01 = J00 * R01 + J02 * R21, T02 = J00 * R02 + J02 * R22;
+        const double T10 = J11 * R10 + J12 * R20, T11 = J11 * R11 + J12 * R21, T12 = J11 * R12 + J12 * R22;
+
+        // Sigma' = (T Sigma) T^T, eq. (4)
+        const double U00 = T00 * S00 + T01 * S01 + T02 * S02;
+        const double U01 = T00 * S01 + T01 * S11 + T02 * S12;
+        const double U02 = T00 * S02 + T01 * S12 + T02 * S22;
+        const double U10 = T10 * S00 + T11 * S01 + T12 * S02;
+        const double U11 = T10 * S01 + T11 * S11 + T12 * S12;
+        const double U12 = T10 * S02 + T11 * S12 + T12 * S22;
+        const double C00 = U00 * T00 + U01 * T01 + U02 * T02;
+        const double C01 = U00 * T10 + U01 * T11 + U02 * T12;
+        const double C11 = U10 * T10 + U11 * T11 + U12 * T12;
+        const double det = C00 * C11 - C01 * C01;
+
+        visible = isfinite(C00) && isfinite(C01) && isfinite(C11) && det > 0.0 && C00 > 0.0 && C11 > 0.0;
+        const double Y00 = C11 / det, Y01 = -C01 / det, Y11 = C00 / det;
+        visible = visible && isfinite(mu0) && isfinite(mu1) && isfinite(Y00) && isfinite(Y01) && isfinite(Y11);
+
+        if (visible) {
+            // axis-aligned box of the 3-sigma ellipse on the 16x16 tile grid
+            const double ex = 3.0 * sqrt(C00), ey = 3.0 * sqrt(C11);
+            const double TX = (double)cam.tiles_x, TY = (double)cam.tiles_y;
+            double x0 = floor((mu0 - ex) / 16.0), x1 = floor((mu0 + ex) / 16.0);
+            double y0 = floor((mu1 - ey) / 16.0), y1 = floor((mu1 + ey) / 16.0);
+            visible = x1 >= 0.0 && y1 >= 0.0 && x0 <= TX - 1.0 && y0 <= TY - 1.0;
+            if (visible) {
+                x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+                x1 = fmin(x1, TX - 1.0); y1 = fmin(y1, TY - 1.0);
+                box = make_int4((int)x0, (int)y0, (int)x1, (int)y1);
+                tiles = (box.z - box.x + 1) * (box.w - box.y + 1);
+                dep = (float)tz;
+                r0 = make_float4((float)mu0, (float)mu1, (float)Y00, (float)Y01);
+                r1 = make_float4((float)Y11, g.opacities[i], g.colors[i], g.colors[n + i]);
+                r2 = make_float4(g.colors[2 * n + i], dep, __int_as_float((int)i), __int_as_float(c));
+            }
+        }
+    }
+    rec[3 * p + 0] = r0;
+    rec[3 * p + 1] = r1;
+    rec[3 * p + 2] = r2;
+    depth_out[p] = dep;
+    rect_out[p] = box;
+    tiles_out[p] = tiles;
+}
+
+}  // namespace gsx
+
+using namespace gsx;
+
+extern "C" int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
+                          gs_splats *out, void *stream)
+{
+    clear_error();
+    if (!g || !cams || !out || n_cams < 1 || n_splats < 0)
+        return set_error(GS_ERR_INVALID, "gs_project: null argument or bad size");
+    if (n_splats > out->capacity)
+        return set_error(GS_ERR_INVALID, "gs_project: n_splats exceeds splat capacity");
+    if (n_splats == 0) return GS_OK;
+    if (!g->means || !g->quats || !g->scales || !g->colors || !g->opacities || g->n < 1 || !out->rec ||
+        !out->depth || !out->rect || !out->tiles_touched)
+        return set_error(GS_ERR_INVALID, "gs_project: null plane");
+    if ((((uintptr_t)out->rec) & 15) || (((uintptr_t)out->rect) & 15))
+        return set_error(GS_ERR_INVALID, "gs_project: rec and rect must be 16-byte aligned");
+    hipLaunchKernelGGL(project_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream, *g, cams,
+                       (int)n_cams, n_splats, (float4 *)out->rec, out->depth, (int4 *)out->rect,
+                       out->tiles_touched);
+    return check_launch("gs_project");
+}

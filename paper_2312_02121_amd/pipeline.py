@@ -1,0 +1,274 @@
+"""Host-side orchestration of the five C-ABI calls.
+
+PyTorch supplies device memory and the stream; every computation runs in the HIP
+library. The classes here pack cameras into the device ``gs_camera`` array, hold the
+Gaussian planes, size the intermediate buffers, and call
+
+    gs_project -> gs_bin_and_sort -> gs_rasterize_fwd            (forward)
+    gs_rasterize_bwd -> gs_project_bwd                          (backward)
+
+The tile-intersection count K is only known on the device. The forward passes a
+capacity; if gs_bin_and_sort reports overflow (its device flag), the buffers are
+regrown to K and binning is redone. A fixed-capacity caller (a captured graph) reads
+the flag after the fact instead.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import abi
+
+STANDARD_PARAMS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4)
+
+
+def make_params(alpha_min: float = STANDARD_PARAMS["alpha_min"], alpha_max: float = STANDARD_PARAMS["alpha_max"],
+                T_min: float = STANDARD_PARAMS["T_min"]) -> abi.GsParams:
+    return abi.GsParams(float(np.float32(alpha_min)), float(np.float32(alpha_max)), float(np.float32(T_min)), 0)
+
+
+def current_stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class CameraSet:
+    """A batch of cameras, each viewing one scene, packed into the device gs_camera array.
+
+    ``cameras`` are objects with R, t, fx, fy, cx, cy, width, height, near, far and
+    ``scene`` (index into ``scene_sizes``, the Gaussian count of each scene).
+    """
+
+    def __init__(self, cameras: Sequence, scene_sizes: Sequence[int], device="cuda"):
+        n = len(cameras)
+        if n < 1:
+            raise ValueError("need at least one camera")
+        scene_off = np.concatenate([[0], np.cumsum(np.asarray(scene_sizes, dtype=np.int64))])
+        arr = np.zeros(n, dtype=abi.CAMERA_DTYPE)
+        proj = pix = tile = 0
+        for k, c in enumerate(cameras):
+            s = int(getattr(c, "scene", 0))
+            W, H = int(c.width), int(c.height)
+            if W < 1 or H < 1:
+                raise ValueError("camera size must be positive")
+            arr[k]["R"] = np.asarray(c.R, dtype=np.float32).reshape(9)
+            arr[k]["t"] = np.asarray(c.t, dtype=np.float32).reshape(3)
+            arr[k]["fx"], arr[k]["fy"], arr[k]["cx"], arr[k]["cy"] = c.fx, c.fy, c.cx, c.cy
+            arr[k]["width"], arr[k]["height"] = W, H
+            arr[k]["near_plane"], arr[k]["far_plane"] = c.near, c.far
+            arr[k]["gauss_offset"] = scene_off[s]
+            arr[k]["gauss_count"] = scene_sizes[s]
+            arr[k]["proj_offset"] = proj
+            arr[k]["pixel_offset"] = pix
+            arr[k]["tile_offset"] = tile
+            tx, ty = (W + 15) // 16, (H + 15) // 16
+            arr[k]["tiles_x"], arr[k]["tiles_y"] = tx, ty
+            proj += int(scene_sizes[s])
+            pix += W * H
+            tile += tx * ty
+        if tile > 0x7FFFFFFF:
+            raise ValueError("too many tiles for 32-bit tile ids")
+        self.cameras = list(cameras)
+        self.host = arr
+        self.n_cams = n
+        self.n_splats = proj
+        self.n_pixels = pix
+        self.n_tiles = tile
+        self.device = torch.device(device)
+        self.dev = torch.from_numpy(arr.view(np.uint8).copy()).to(self.device)
+
+    @property
+    def ptr(self) -> int:
+        return self.dev.data_ptr()
+
+    def image_slice(self, k: int):
+        """(pixel_offset, height, width) of camera k inside the packed image planes."""
+        c = self.host[k]
+        return int(c["pixel_offset"]), int(c["height"]), int(c["width"])
+
+    def unpack(self, planes: torch.Tensor, k: int) -> torch.Tensor:
+        """[C, n_pixels] packed planes -> [C, H, W] view of camera k."""
+        off, H, W = self.image_slice(k)
+        return planes[:, off:off + H * W].view(planes.shape[0], H, W)
+
+
+class GaussianSet:
+    """Concatenated Gaussian planes of one or more scenes, float32 on the device."""
+
+    KEYS = ("means", "quats", "scales", "colors", "opacities")
+
+    def __init__(self, scenes: Sequence[dict] | dict, device="cuda", requires_grad: bool = False):
+        if isinstance(scenes, dict):
+            scenes = [scenes]
+        self.sizes = [int(s["opacities"].shape[-1]) for s in scenes]
+        self.n = sum(self.sizes)
+        self.t = {}
+        for k in self.KEYS:
+            parts = [torch.as_tensor(np.asarray(s[k]), dtype=torch.float32) for s in scenes]
+            self.t[k] = torch.cat(parts, dim=-1).contiguous().to(device).requires_grad_(requires_grad)
+
+    @staticmethod
+    def from_tensors(means, quats, scales, colors, opacities, sizes=None) -> "GaussianSet":
+        obj = GaussianSet.__new__(GaussianSet)
+        obj.t = {"means": means, "quats": quats, "scales": scales, "colors": colors, "opacities": opacities}
+        obj.n = int(opacities.shape[-1])
+        obj.sizes = list(sizes) if sizes is not None else [obj.n]
+        return obj
+
+    def struct(self) -> abi.GsGaussians:
+        t = self.t
+        for k in self.KEYS:
+            if not (t[k].is_contiguous() and t[k].dtype == torch.float32 and t[k].is_cuda):
+                raise ValueError(f"{k} must be a contiguous float32 device tensor")
+        return abi.GsGaussians(_ptr(t["means"]), _ptr(t["quats"]), _ptr(t["scales"]), _ptr(t["colors"]),
+                               _ptr(t["opacities"]), self.n)
+
+
+@dataclass
+class Splats:
+    rec: torch.Tensor
+    depth: torch.Tensor
+    rect: torch.Tensor
+    tiles: torch.Tensor
+
+    @staticmethod
+    def alloc(P: int, device) -> "Splats":
+        P1 = max(P, 1)
+        return Splats(torch.empty(P1 * abi.REC_FLOATS, dtype=torch.float32, device=device),
+                      torch.empty(P1, dtype=torch.float32, device=device),
+                      torch.empty(P1 * 4, dtype=torch.int32, device=device),
+                      torch.empty(P1, dtype=torch.int32, device=device))
+
+    def struct(self, P: int) -> abi.GsSplats:
+        return abi.GsSplats(_ptr(self.rec), _ptr(self.depth), _ptr(self.rect), _ptr(self.tiles), P)
+
+
+@dataclass
+class Bins:
+    keys: torch.Tensor
+    ids: torch.Tensor
+    ranges: torch.Tensor
+    counters: torch.Tensor
+    workspace: torch.Tensor
+    capacity: int
+    n_tiles: int
+
+    @staticmethod
+    def alloc(P: int, capacity: int, n_tiles: int, device) -> "Bins":
+        capacity = int(min(max(capacity, 1), 0x7FFFFFFF))
+        ws = abi.gs_bin_and_sort_workspace_size(P, capacity, n_tiles)
+        return Bins(torch.empty(capacity, dtype=torch.int64, device=device),
+                    torch.empty(capacity, dtype=torch.int32, device=device),
+                    torch.empty(2 * max(n_tiles, 1), dtype=torch.int32, device=device),
+                    torch.zeros(2, dtype=torch.int64, device=device),
+                    torch.empty(max(ws, 1), dtype=torch.uint8, device=device), capacity, n_tiles)
+
+    def struct(self) -> abi.GsBins:
+        return abi.GsBins(_ptr(self.keys), _ptr(self.ids), _ptr(self.ranges), _ptr(self.counters), self.capacity,
+                          self.n_tiles, 0)
+
+
+@dataclass
+class ForwardState:
+    gaussians: GaussianSet
+    cams: CameraSet
+    params: abi.GsParams
+    splats: Splats
+    bins: Bins
+    image: torch.Tensor        # [3, n_pixels]
+    T_final: torch.Tensor      # [n_pixels]
+    last: torch.Tensor         # [n_pixels] int32
+    visited: Optional[torch.Tensor] = None
+    K: int = -1
+    extra: dict = field(default_factory=dict)
+
+
+class Rasterizer:
+    """Reusable buffers for one (GaussianSet layout, CameraSet) pair."""
+
+    def __init__(self, cams: CameraSet, params: abi.GsParams | None = None, capacity: int | None = None,
+                 keep_visited: bool = False):
+        self.cams = cams
+        self.params = params or make_params()
+        self.device = cams.device
+        P = cams.n_splats
+        self.splats = Splats.alloc(P, self.device)
+        self.capacity = int(capacity) if capacity else max(4 * P, 1024)
+        self.bins = Bins.alloc(P, self.capacity, cams.n_tiles, self.device)
+        npx = cams.n_pixels
+        self.image = torch.empty(3, npx, dtype=torch.float32, device=self.device)
+        self.T_final = torch.empty(npx, dtype=torch.float32, device=self.device)
+        self.last = torch.empty(npx, dtype=torch.int32, device=self.device)
+        self.visited = torch.empty(npx, dtype=torch.int32, device=self.device) if keep_visited else None
+
+    # ---------------------------------------------------------------- forward pieces
+    def project(self, g: GaussianSet, stream: int | None = None):
+        stream = current_stream() if stream is None else stream
+        P = self.cams.n_splats
+        abi.gs_project(g.struct(), self.cams.ptr, self.cams.n_cams, P, self.splats.struct(P), stream)
+
+    def bin_and_sort(self, stream: int | None = None):
+        stream = current_stream() if stream is None else stream
+        P = self.cams.n_splats
+        b = self.bins
+        abi.gs_bin_and_sort(self.splats.struct(P), P, self.cams.ptr, self.cams.n_cams, b.struct(),
+                            _ptr(b.workspace), b.workspace.numel(), stream)
+
+    def rasterize_fwd(self, stream: int | None = None):
+        stream = current_stream() if stream is None else stream
+        P = self.cams.n_splats
+        abi.gs_rasterize_fwd(self.splats.struct(P), self.bins.struct(), self.cams.ptr, self.cams.n_cams,
+                             self.params, self.cams.n_pixels, _ptr(self.image), _ptr(self.T_final), _ptr(self.last),
+                             _ptr(self.visited), stream)
+
+    def read_count(self) -> tuple[int, bool]:
+        c = self.bins.counters.cpu()
+        return int(c[0]), bool(c[1])
+
+    def forward(self, g: GaussianSet, check_overflow: bool = True) -> ForwardState:
+        self.project(g)
+        self.bin_and_sort()
+        K = -1
+        if check_overflow:
+            K, over = self.read_count()
+            if over:
+                self.capacity = int(K * 1.25) + 1024
+                self.bins = Bins.alloc(self.cams.n_splats, self.capacity, self.cams.n_tiles, self.device)
+                self.bin_and_sort()
+                K, over = self.read_count()
+                assert not over
+        self.rasterize_fwd()
+        return ForwardState(g, self.cams, self.params, self.splats, self.bins, self.image, self.T_final,
+                            self.last, self.visited, K)
+
+    # ---------------------------------------------------------------------- backward
+    def backward(self, state: ForwardState, dL_dimage: torch.Tensor, with_pose: bool = False,
+                 stream: int | None = None) -> dict:
+        stream = current_stream() if stream is None else stream
+        g, cams, P = state.gaussians, self.cams, self.cams.n_splats
+        dev = self.device
+        dL_dimage = dL_dimage.contiguous().to(torch.float32)
+        grads = {
+            "mean2d": torch.empty(2, max(P, 1), device=dev), "conic": torch.empty(3, max(P, 1), device=dev),
+            "colors": torch.empty(3, g.n, device=dev), "opacities": torch.empty(g.n, device=dev),
+            "means": torch.empty(3, g.n, device=dev), "scales": torch.empty(3, g.n, device=dev),
+            "quats": torch.empty(4, g.n, device=dev),
+        }
+        if with_pose:
+            grads["campose"] = torch.empty(cams.n_cams, 12, device=dev)
+        for t in grads.values():
+            abi.gs_zero(t.data_ptr(), t.numel() * 4, stream)
+        sp = state.splats.struct(P)
+        abi.gs_rasterize_bwd(sp, P, state.bins.struct(), cams.ptr, cams.n_cams, state.params, cams.n_pixels,
+                             _ptr(dL_dimage), _ptr(state.T_final), _ptr(state.last), _ptr(grads["mean2d"]),
+                             _ptr(grads["conic"]), g.n, _ptr(grads["colors"]), _ptr(grads["opacities"]), stream)
+        abi.gs_project_bwd(g.struct(), cams.ptr, cams.n_cams, sp, P, _ptr(grads["mean2d"]), _ptr(grads["conic"]),
+                           _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]),
+                           _ptr(grads.get("campose")), stream)
+        return grads

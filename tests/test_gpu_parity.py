@@ -1,0 +1,215 @@
+"""HIP path against the FP64 oracle, element by element, on seeded synthetic inputs.
+
+Bars: splat fields, tile lists and sort order bit-exact; image within 1e-5 abs;
+gradients within 1e-3 relative (per tensor norm and elementwise against
+|g*| + rms(g*)). Pixels whose float decisions sit within the stated margins of a
+threshold are excluded and counted (gpu_helpers.MARGIN_*), and receive zero upstream
+gradient on both sides so that the backward comparison is exact in its inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_02121_amd import synth
+
+from gpu_helpers import (IMAGE_ATOL, GRAD_REL, bins_arrays, camera_images, elementwise_ok, gpu_forward,
+                         oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _workloads():
+    return {
+        "c1": synth.make_config(1),
+        "tiny_tilted": synth.tilted_camera_scene(40, n=200, width=70, height=45),
+        "c2_20k": synth.make_config(2, n_override=20_000),
+        "dense_small": synth.tiny_scene(41, n=600, width=100, height=77, log_scale=(-1.5, 0.6), opac_sd=2.5),
+    }
+
+
+WL = None
+
+
+def wl_cache():
+    global WL
+    if WL is None:
+        WL = _workloads()
+    return WL
+
+
+def _check_projection(wl, r):
+    s = splat_arrays(r)
+    for k, cam in enumerate(wl.cameras):
+        off = int(r.cams.host[k]["proj_offset"])
+        n = int(r.cams.host[k]["gauss_count"])
+        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
+        sl = slice(off, off + n)
+        assert np.array_equal(s["tiles"][sl], o["tiles"]), "tiles_touched"
+        vis = o["tiles"] > 0
+        assert np.array_equal(s["rect"][:, sl][:, vis], o["rect"][:, vis]), "rect"
+        assert np.array_equal(s["mean2d"][:, sl][:, vis].astype(np.float64), o["mean2d"][:, vis]), "mean2d"
+        assert np.array_equal(s["conic"][:, sl][:, vis].astype(np.float64), o["conic"][:, vis]), "conic"
+        assert np.array_equal(s["depth"][sl][vis].astype(np.float64), o["depth"][vis]), "depth"
+        sc = wl.scenes[cam.scene]
+        assert np.array_equal(s["opacity"][sl][vis], sc["opacities"][vis])
+        assert np.array_equal(s["color"][:, sl][:, vis], sc["colors"][:, vis])
+        assert np.array_equal(s["src"][sl][vis], np.nonzero(vis)[0] + (sum(wl.scenes[j]["opacities"].shape[0]
+                                                                          for j in range(cam.scene))))
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
+def test_projection_bit_exact(name):
+    _print_case("projection", wl=name)
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl)
+    _check_projection(wl, r)
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
+def test_bins_bit_exact(name):
+    _print_case("bins", wl=name)
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl)
+    toffs = tile_offsets(wl)
+    okeys, oids, oranges = [], [], []
+    for k, cam in enumerate(wl.cameras):
+        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
+        b = oracle.bin_and_sort(o, cam, tile_offset=toffs[k])
+        poff = int(r.cams.host[k]["proj_offset"])
+        okeys.append(b["keys"])
+        oids.append(b["ids"] + poff)
+        oranges.append(np.where(b["ranges"][:, 1:] > b["ranges"][:, :1], b["ranges"] + sum(map(len, okeys[:-1])), 0))
+    okeys, oids = np.concatenate(okeys), np.concatenate(oids)
+    assert st.K == okeys.size
+    g = bins_arrays(r, st.K)
+    assert np.array_equal(g["keys"], okeys)
+    assert np.array_equal(g["ids"], oids.astype(np.int32))
+    assert np.array_equal(g["ranges"], np.concatenate(oranges).astype(np.int32))
+
+
+def _forward_compare(wl, r, st):
+    flagged_total, pixels = 0, 0
+    for k in range(len(wl.cameras)):
+        orc, scene, cam, prm = oracle_camera(wl, k)
+        g = camera_images(r, st, k)
+        ok = orc["flags"] == 0
+        flagged_total += int((~ok).sum())
+        pixels += ok.size
+        err = np.abs(g["C"] - orc["C"])[:, ok]
+        assert err.max(initial=0.0) <= IMAGE_ATOL, f"cam {k}: image err {err.max()}"
+        assert np.abs(g["T_final"] - orc["T_final"])[ok].max(initial=0.0) <= IMAGE_ATOL
+        assert np.array_equal(g["last"][ok], orc["last"][ok])
+        assert np.array_equal(g["visited"][ok], orc["visited"][ok])
+    return flagged_total, pixels
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
+def test_forward_image(name):
+    _print_case("forward", wl=name)
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl)
+    flagged, pixels = _forward_compare(wl, r, st)
+    print(f"flagged pixels {flagged} / {pixels}")
+    assert flagged <= max(3, 1e-3 * pixels)
+
+
+def _backward_compare(wl, r, st, seed=0, with_pose=False):
+    rng = np.random.default_rng(seed)
+    cams = r.cams
+    g_img = np.zeros((3, cams.n_pixels), dtype=np.float32)
+    og = {k: np.zeros_like(v, dtype=np.float64) for k, v in wl.scenes[0].items()}
+    ograds = [{key: np.zeros(np.asarray(s[key]).shape) for key in ("means", "quats", "scales", "colors", "opacities")}
+              for s in wl.scenes]
+    for k, cam in enumerate(wl.cameras):
+        orc, scene, _, prm = oracle_camera(wl, k)
+        g = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+        g[:, orc["flags"] != 0] = 0.0
+        off = int(cams.host[k]["pixel_offset"])
+        g_img[:, off:off + cam.width * cam.height] = g.reshape(3, -1)
+        og = oracle.render_backward(scene, cam, prm, g.astype(np.float64), state=orc)
+        for key in ograds[cam.scene]:
+            ograds[cam.scene][key] += og[key]
+    grads = r.backward(st, torch.from_numpy(g_img).cuda(), with_pose=with_pose)
+    torch.cuda.synchronize()
+    out = {}
+    for key in ("means", "quats", "scales", "colors", "opacities"):
+        gpu = grads[key].cpu().numpy().astype(np.float64)
+        ref = np.concatenate([o[key] for o in ograds], axis=-1)
+        out[key] = (rel_err(gpu, ref), elementwise_ok(gpu, ref))
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
+def test_backward_gradients(name):
+    _print_case("backward", wl=name)
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl)
+    res = _backward_compare(wl, r, st)
+    print(res)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
+
+
+def test_multi_scene_multi_camera():
+    _print_case("multi", wl="c5_small")
+    wl = synth.make_config(5, n_override=3000)
+    # keep the test small: shrink every camera to at most 256 x 256
+    for c in wl.cameras:
+        s = min(1.0, 256.0 / max(c.width, c.height))
+        c.width, c.height = max(1, int(c.width * s)), max(1, int(c.height * s))
+        c.fx, c.fy, c.cx, c.cy = c.fx * s, c.fy * s, c.width / 2, c.height / 2
+    r, st = gpu_forward(wl)
+    _check_projection(wl, r)
+    flagged, pixels = _forward_compare(wl, r, st)
+    assert flagged <= max(3, 1e-3 * pixels)
+    res = _backward_compare(wl, r, st, seed=3)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
+
+
+def test_capacity_overflow_regrows():
+    _print_case("overflow", wl="c1")
+    wl = synth.make_config(1)
+    r, st = gpu_forward(wl, capacity=16)
+    assert r.bins.capacity > 16
+    r2, st2 = gpu_forward(wl)
+    assert st.K == st2.K
+    assert torch.equal(st.image, st2.image)
+
+
+def test_deterministic_lists_and_image():
+    _print_case("determinism", wl="c2_20k")
+    wl = wl_cache()["c2_20k"]
+    r, st = gpu_forward(wl)
+    keys, img = r.bins.keys[: st.K].clone(), st.image.clone()
+    r2, st2 = gpu_forward(wl)
+    assert torch.equal(keys, r2.bins.keys[: st2.K]) and torch.equal(img, st2.image)
+
+
+def test_edge_cases():
+    _print_case("edges", wl="edge")
+    # everything behind the camera or outside the image: K = 0, empty image
+    wl = synth.tiny_scene(42, n=50)
+    wl.scenes[0]["means"][2] = -1.0
+    r, st = gpu_forward(wl)
+    assert st.K == 0
+    assert float(st.image.abs().max()) == 0.0 and float(st.T_final.min()) == 1.0
+    # one huge Gaussian over a ragged image (partial tiles on both axes), one tiny one
+    wl = synth.tiny_scene(43, n=2, width=37, height=23)
+    wl.scenes[0]["scales"][:, 0] = 5.0
+    wl.scenes[0]["scales"][:, 1] = 1e-3
+    r, st = gpu_forward(wl)
+    _check_projection(wl, r)
+    flagged, pixels = _forward_compare(wl, r, st)
+    assert flagged <= 3
+    res = _backward_compare(wl, r, st, seed=5)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
