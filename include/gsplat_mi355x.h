@@ -107,6 +107,8 @@ typedef struct gs_gaussians {
  */
 typedef struct gs_splats {
     float *rec;              /* [P][12], 16-byte aligned */
+    float *raster;           /* [P][16], 64-byte aligned: compositing record written by gs_project and
+                                read by the rasterizer; its layout is private to the library */
     float *depth;            /* [P] t_z, 0 when culled */
     int32_t *rect;           /* [P][4] tile box x0, y0, x1, y1, inclusive, camera-local */
     int32_t *tiles_touched;  /* [P] tiles in the box; 0 = culled */
@@ -129,6 +131,8 @@ typedef struct gs_bins {
     uint64_t *keys;          /* [capacity] */
     int32_t *ids;            /* [capacity] splat slot of each entry */
     int32_t *ranges;         /* [n_tiles][2] start, end of each tile's run; empty tile = (0, 0) */
+    int32_t *schedule;       /* [gs_schedule_size(n_tiles)] rasterizer work list, written by
+                                gs_bin_and_sort; layout private to the library */
     int64_t *counters;       /* [2]: K = total intersections (may exceed capacity), overflow flag */
     int64_t capacity;        /* K_cap, at most 2^31 - 1 */
     int32_t n_tiles;         /* sum over cameras of tiles_x * tiles_y */
@@ -160,6 +164,12 @@ int gs_zero(void *ptr, size_t bytes, void *stream);
  */
 int gs_abi_layout(int64_t *out, int n);
 
+/*
+ * Gradient of the L2 image loss L = sum (C - target)^2 used by the training step:
+ * dL_dimage[i] = 2 (image[i] - target[i]) for i < n. Not part of the paper's method.
+ */
+int gs_l2_grad(const float *image, const float *target, int64_t n, float *dL_dimage, void *stream);
+
 /* --------------------------------------------------------------------- forward (Sec. 2) */
 
 /*
@@ -174,13 +184,17 @@ int gs_abi_layout(int64_t *out, int n);
 int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
                gs_splats *out, void *stream);
 
+/* Number of int32 entries of gs_bins.schedule for n_tiles tiles. */
+int64_t gs_schedule_size(int32_t n_tiles);
+
 /* Bytes of workspace gs_bin_and_sort needs for n_splats splats and a list capacity. */
 size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles);
 
 /*
  * Sec. 2.2: duplicate each splat once per tile of its box, sort the entries by
  * (tile, depth) with a stable LSD radix sort (ties keep splat order), and find each
- * tile's [start, end). K is written to bins->counters[0]; if K exceeds
+ * tile's [start, end), then write the rasterizer's work list (tiles in decreasing list
+ * length, long ones split into four parts). K is written to bins->counters[0]; if K exceeds
  * bins->capacity only the first `capacity` entries (in splat order) are emitted,
  * counters[1] is set to 1 and the list is incomplete: the caller reads the flag,
  * regrows and calls again. workspace: device memory of at least

@@ -17,12 +17,13 @@ LIB_PATH = os.path.join(HERE, "libgsplat_mi355x.so")
 
 GS_OK, GS_ERR_INVALID, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_DEVICE = 0, -1, -2, -3, -4
 REC_FLOATS = 12
+RASTER_FLOATS = 16
 TILE = 16
 
 EXPORTED = (
     "gs_device_check", "gs_last_hip_error", "gs_last_error_message", "gs_version", "gs_zero", "gs_abi_layout",
-    "gs_project", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
-    "gs_project_bwd",
+    "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
+    "gs_project_bwd", "gs_l2_grad",
 )
 
 
@@ -49,8 +50,8 @@ class GsGaussians(ctypes.Structure):
 
 
 class GsSplats(ctypes.Structure):
-    _fields_ = [("rec", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("rect", ctypes.c_void_p),
-                ("tiles_touched", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+    _fields_ = [("rec", ctypes.c_void_p), ("raster", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("rect", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
 
 
 class GsParams(ctypes.Structure):
@@ -60,8 +61,8 @@ class GsParams(ctypes.Structure):
 
 class GsBins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
-                ("counters", ctypes.c_void_p), ("capacity", ctypes.c_int64), ("n_tiles", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_void_p), ("counters", ctypes.c_void_p), ("capacity", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def expected_layout() -> list[int]:
@@ -100,10 +101,12 @@ def lib():
         "gs_abi_layout": (ctypes.c_int, [_P, ctypes.c_int]),
         "gs_project": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P]),
         "gs_bin_and_sort_workspace_size": (ctypes.c_size_t, [_I64, _I64, _I32]),
+        "gs_schedule_size": (ctypes.c_int64, [_I32]),
         "gs_bin_and_sort": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P, ctypes.c_size_t, _P]),
         "gs_rasterize_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
         "gs_rasterize_bwd": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "gs_project_bwd": (ctypes.c_int, [_P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+        "gs_l2_grad": (ctypes.c_int, [_P, _P, _I64, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -143,6 +146,10 @@ def gs_project(g: GsGaussians, cams_ptr: int, n_cams: int, n_splats: int, splats
     _check("gs_project", lib().gs_project(_ref(g), cams_ptr, n_cams, n_splats, _ref(splats), stream))
 
 
+def gs_schedule_size(n_tiles: int) -> int:
+    return int(lib().gs_schedule_size(n_tiles))
+
+
 def gs_bin_and_sort_workspace_size(n_splats: int, capacity: int, n_tiles: int) -> int:
     return int(lib().gs_bin_and_sort_workspace_size(n_splats, capacity, n_tiles))
 
@@ -171,3 +178,7 @@ def gs_project_bwd(g: GsGaussians, cams_ptr: int, n_cams: int, splats: GsSplats,
                    d_conic: int, d_means: int, d_scales: int, d_quats: int, d_campose: int | None, stream: int):
     _check("gs_project_bwd", lib().gs_project_bwd(_ref(g), cams_ptr, n_cams, _ref(splats), n_splats, d_mean2d, d_conic,
                                                   d_means, d_scales, d_quats, d_campose, stream))
+
+
+def gs_l2_grad(image: int, target: int, n: int, dL_dimage: int, stream: int):
+    _check("gs_l2_grad", lib().gs_l2_grad(image, target, n, dL_dimage, stream))

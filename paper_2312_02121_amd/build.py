@@ -17,6 +17,8 @@ SOURCES = ["runtime.hip", "project.hip", "binning.hip", "raster.hip", "project_b
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
+    # atomics are issued by one lane after an explicit wave reduction; skip the compiler's own
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # packed fp32 VALU forms are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",

@@ -301,6 +301,77 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict_
     if (k == kv - 1 || (keys[k + 1] >> 32) != t) ranges[2 * t + 1] = (int32_t)(k + 1);
 }
 
+// ------------------------------------------------------------------------ work list
+
+// Tiles with at least this many list entries are split into four quarter items.
+constexpr int kSplitLen = 256;
+
+__device__ inline int length_bucket(int len)
+{
+    // bucket 0 holds the longest lists; empty tiles land in the last bucket
+    const int lg = 31 - __clz(len + 1);
+    return kSchedNumBuckets - 1 - min(kSchedNumBuckets - 1, lg);
+}
+
+__global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ sched)
+{
+    sched[threadIdx.x] = 0;
+}
+
+// Per-block bucket histogram in LDS, then one global atomic per non-empty bucket.
+__global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restrict__ ranges, int n_tiles,
+                                                          int32_t *__restrict__ sched)
+{
+    __shared__ int cnt[kSchedNumBuckets];
+    if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tiles) {
+        const int len = ranges[2 * t + 1] - ranges[2 * t];
+        atomicAdd(&cnt[length_bucket(len)], len >= kSplitLen ? 4 : 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kSchedNumBuckets && cnt[threadIdx.x])
+        atomicAdd(&sched[kSchedBuckets + threadIdx.x], cnt[threadIdx.x]);
+}
+
+// Each block reserves one contiguous run per bucket (one global atomic per bucket), then
+// hands out positions inside its runs with LDS atomics. Order inside a bucket is free.
+__global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restrict__ ranges, int n_tiles,
+                                                         int32_t *__restrict__ sched)
+{
+    __shared__ int cnt[kSchedNumBuckets], base[kSchedNumBuckets];
+    if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int len = 0, b = 0, n = 0;
+    if (t < n_tiles) {
+        len = ranges[2 * t + 1] - ranges[2 * t];
+        b = length_bucket(len);
+        n = len >= kSplitLen ? 4 : 1;
+        atomicAdd(&cnt[b], n);
+    }
+    __syncthreads();
+    if (threadIdx.x < kSchedNumBuckets) {
+        const int bk = threadIdx.x;
+        int before = 0;
+        for (int j = 0; j < bk; ++j) before += sched[kSchedBuckets + j];
+        base[bk] = cnt[bk] ? before + atomicAdd(&sched[kSchedCursors + bk], cnt[bk]) : 0;
+        cnt[bk] = 0;
+        if (blockIdx.x == 0 && bk == 0) {
+            int tot = 0;
+            for (int j = 0; j < kSchedNumBuckets; ++j) tot += sched[kSchedBuckets + j];
+            sched[kSchedItems] = tot;
+        }
+    }
+    __syncthreads();
+    if (t >= n_tiles) return;
+    const int split = len >= kSplitLen;
+    const int pos = base[b] + atomicAdd(&cnt[b], n);
+    int32_t *items = sched + kSchedHeader;
+    for (int part = 0; part < n; ++part) items[pos + part] = (t << 3) | (split << 2) | part;
+}
+
 // ------------------------------------------------------------------------ workspace
 
 struct BinLayout {
@@ -338,6 +409,20 @@ static int key_bits(int32_t n_tiles)
 
 using namespace gsx;
 
+static int build_schedule(gs_bins *bins, hipStream_t st)
+{
+    const unsigned g = grid_for(bins->n_tiles, 256);
+    hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule);
+    hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, bins->schedule);
+    hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, bins->schedule);
+    return check_launch("gs_bin_and_sort");
+}
+
+extern "C" int64_t gs_schedule_size(int32_t n_tiles)
+{
+    return n_tiles < 0 ? 0 : (int64_t)kSchedHeader + 4ll * n_tiles;
+}
+
 extern "C" size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles)
 {
     (void)n_tiles;
@@ -353,7 +438,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null argument or bad size");
     if (bins->capacity < 1 || bins->capacity > 0x7fffffffll || bins->n_tiles < 1)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: capacity must be in [1, 2^31-1], n_tiles >= 1");
-    if (!bins->keys || !bins->ids || !bins->ranges || !bins->counters || !s->rect || !s->depth ||
+    if (!bins->keys || !bins->ids || !bins->ranges || !bins->schedule || !bins->counters || !s->rect || !s->depth ||
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
     const int64_t cap = bins->capacity;
@@ -374,7 +459,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
                        2ll * bins->n_tiles, 0);
     if (n_splats == 0) {
         hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, st, (int32_t *)bins->counters, 4, 0);
-        return check_launch("gs_bin_and_sort");
+        return build_schedule(bins, st);
     }
     int rc = scan_exclusive<int32_t, int64_t, int64_t>(s->tiles_touched, n_splats, offsets, scan_sums,
                                                         bins->counters, bins->counters + 1, cap, st);
@@ -401,5 +486,5 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     }
     hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys,
                        (const int64_t *)bins->counters, cap, bins->n_tiles, bins->ranges);
-    return check_launch("gs_bin_and_sort");
+    return build_schedule(bins, st);
 }

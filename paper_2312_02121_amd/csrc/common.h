@@ -13,6 +13,41 @@ constexpr int kTilePixels = kTile * kTile;
 constexpr int kWave = 64;                // CDNA wavefront width
 constexpr int kRecFloats = 12;           // floats per splat record
 
+// Compositing record of one splat (64 bytes, gs_splats.raster). The rasterizer reads it with
+// scalar loads, so every lane of a wave gets it in SGPRs without LDS or VALU traffic.
+//   alpha_raw(dx, dy) = exp2(lo + A dx^2 + B dx dy + C dy^2),  (dx, dy) = mu' - pixel centre
+// lo = log2(o); A = -log2(e)/2 Y00, B = -log2(e) Y01, C = -log2(e)/2 Y11 from the float32 conic.
+// The quadratic form is evaluated in float64: for thin splats Y is nearly singular and the three
+// terms cancel, which in float32 costs up to ~1e-5 of image accuracy. On CDNA a float64 FMA
+// issues at the rate of a non-packed float32 one, so this costs only two conversions per pixel.
+struct alignas(64) RasterRec {
+    float mx, my;     // mu', the same float32 values as in rec
+    double lo;
+    double A, B, C;
+    float c0, c1, c2;
+    float o;
+    int src;          // scene Gaussian index
+    int pad;          // unused in HBM; the rasterizer's LDS copy keeps the splat slot here
+};
+static_assert(sizeof(RasterRec) == 64, "RasterRec must be 64 bytes");
+
+constexpr double kLog2eD = 1.4426950408889634074;
+
+// Rasterizer work list (gs_bins.schedule, int32). Header words, then the items.
+// An item is tile << 3 | quarter << 2 | part: quarter = 0 covers the whole tile,
+// quarter = 1 covers rows 4 part .. 4 part + 3 of it.
+constexpr int kSchedItems = 0;      // number of items
+constexpr int kSchedFwd = 1;        // forward kernel: next item, then finished-wave count
+constexpr int kSchedBwd = 3;        // backward kernel: next item, then finished-wave count
+constexpr int kSchedFused = 5;      // fused kernel: next item, then finished-wave count
+constexpr int kSchedBuckets = 8;    // 16 bucket counts
+constexpr int kSchedCursors = 24;   // 16 bucket cursors
+constexpr int kSchedHeader = 64;
+constexpr int kSchedNumBuckets = 16;
+
+// Workgroups for a persistent launch: enough waves to fill every SIMD of the device.
+unsigned persistent_blocks(int waves_per_block);
+
 // ------------------------------------------------------------------ host-side status
 
 int set_error(int code, const char *msg);   // records msg, returns code

@@ -13,8 +13,8 @@ namespace gsx {
 
 __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
                                                       int n_cams, int64_t n_splats, float4 *__restrict__ rec,
-                                                      float *__restrict__ depth_out, int4 *__restrict__ rect_out,
-                                                      int32_t *__restrict__ tiles_out)
+                                                      RasterRec *__restrict__ rrec, float *__restrict__ depth_out,
+                                                      int4 *__restrict__ rect_out, int32_t *__restrict__ tiles_out)
 {
 #pragma clang fp contract(off)
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,6 +41,7 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     visible = visible && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz < (double)cam.far_plane;
 
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    RasterRec rr = {};
     int4 box = make_int4(0, 0, 0, 0);
     int32_t tiles = 0;
     float dep = 0.f;
@@ -103,15 +104,29 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
                 box = make_int4((int)x0, (int)y0, (int)x1, (int)y1);
                 tiles = (box.z - box.x + 1) * (box.w - box.y + 1);
                 dep = (float)tz;
-                r0 = make_float4((float)mu0, (float)mu1, (float)Y00, (float)Y01);
-                r1 = make_float4((float)Y11, g.opacities[i], g.colors[i], g.colors[n + i]);
+                const float y00 = (float)Y00, y01 = (float)Y01, y11 = (float)Y11;
+                const float o = g.opacities[i];
+                r0 = make_float4((float)mu0, (float)mu1, y00, y01);
+                r1 = make_float4(y11, o, g.colors[i], g.colors[n + i]);
                 r2 = make_float4(g.colors[2 * n + i], dep, __int_as_float((int)i), __int_as_float(c));
+                rr.mx = r0.x;
+                rr.my = r0.y;
+                rr.lo = o > 0.f ? log2((double)o) : -INFINITY;
+                rr.A = -0.5 * kLog2eD * (double)y00;
+                rr.B = -kLog2eD * (double)y01;
+                rr.C = -0.5 * kLog2eD * (double)y11;
+                rr.c0 = r1.z;
+                rr.c1 = r1.w;
+                rr.c2 = r2.x;
+                rr.o = o;
+                rr.src = (int)i;
             }
         }
     }
     rec[3 * p + 0] = r0;
     rec[3 * p + 1] = r1;
     rec[3 * p + 2] = r2;
+    rrec[p] = rr;
     depth_out[p] = dep;
     rect_out[p] = box;
     tiles_out[p] = tiles;
@@ -131,12 +146,12 @@ extern "C" int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t 
         return set_error(GS_ERR_INVALID, "gs_project: n_splats exceeds splat capacity");
     if (n_splats == 0) return GS_OK;
     if (!g->means || !g->quats || !g->scales || !g->colors || !g->opacities || g->n < 1 || !out->rec ||
-        !out->depth || !out->rect || !out->tiles_touched)
+        !out->raster || !out->depth || !out->rect || !out->tiles_touched)
         return set_error(GS_ERR_INVALID, "gs_project: null plane");
-    if ((((uintptr_t)out->rec) & 15) || (((uintptr_t)out->rect) & 15))
-        return set_error(GS_ERR_INVALID, "gs_project: rec and rect must be 16-byte aligned");
+    if ((((uintptr_t)out->rec) & 15) || (((uintptr_t)out->rect) & 15) || (((uintptr_t)out->raster) & 63))
+        return set_error(GS_ERR_INVALID, "gs_project: rec/rect must be 16-byte and raster 64-byte aligned");
     hipLaunchKernelGGL(project_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream, *g, cams,
-                       (int)n_cams, n_splats, (float4 *)out->rec, out->depth, (int4 *)out->rect,
-                       out->tiles_touched);
+                       (int)n_cams, n_splats, (float4 *)out->rec, (RasterRec *)out->raster, out->depth,
+                       (int4 *)out->rect, out->tiles_touched);
     return check_launch("gs_project");
 }

@@ -1,7 +1,11 @@
 // gs_project_bwd: gradients of the projection (Sec. 3.2, eqs. 22-28) and of the scale
-// and rotation parameterisation (Sec. 3.2.1, eqs. 29-31). One thread per splat slot,
-// float32 arithmetic. The conic Y is read from the splat record (computed in float64 by
-// gs_project) rather than re-inverted, so a nearly singular Sigma' loses nothing here.
+// and rotation parameterisation (Sec. 3.2.1, eqs. 29-31). One thread per splat slot.
+// The arithmetic is float64: dL/dSigma' = -Y dL/dY Y grows with the square of the conic,
+// which is large for thin splats, and the chain that follows sums terms of both signs;
+// in float32 that costs up to ~1e-3 of relative accuracy on single quaternion gradients.
+// The kernel is HBM-bound and CDNA issues float64 FMAs at the float32 rate, so this is
+// free. The conic Y is read from the splat record (computed in float64 by gs_project)
+// rather than re-inverted, so a nearly singular Sigma' loses nothing here.
 //
 // The mean route of eq. (23) is applied in its reduced form: with P of eq. (1), the
 // product 1/2 P^T D^T dL/dmu' equals J^T dL/dmu' extended by 0, i.e.
@@ -30,29 +34,29 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
         const gs_camera &cam = cams[c];
         const int64_t n = g.n;
         const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
-        const float mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
-        const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
-        const float s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
-        const float R[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
-        const float fx = cam.fx, fy = cam.fy;
+        const double mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
+        const double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+        const double s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
+        const double R[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
+        const double fx = cam.fx, fy = cam.fy;
 
         // forward quantities
-        const float tx = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
-        const float ty = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
-        const float tz = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
-        const float iz = 1.f / tz, iz2 = iz * iz;
-        const float J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
-        float T[6];
+        const double tx = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
+        const double ty = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
+        const double tz = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
+        const double iz = 1.0 / tz, iz2 = iz * iz;
+        const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
+        double T[6];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             T[j] = J00 * R[j] + J02 * R[6 + j];
             T[3 + j] = J11 * R[3 + j] + J12 * R[6 + j];
         }
-        const float Q[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
-                            2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
-                            2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-        const float sv[3] = {s0, s1, s2};
-        float M[9], S[9];
+        const double Q[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                            2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                            2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+        const double sv[3] = {s0, s1, s2};
+        double M[9], S[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -65,61 +69,61 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
 
         // dL/dSigma' = -Y dL/dY Y (Sec. 3.1), Y symmetric
         const float4 r0 = rec[3 * p], r1 = rec[3 * p + 1];
-        const float y00 = r0.z, y01 = r0.w, y11 = r1.x;
-        const float g00 = d_conic[p], g01 = d_conic[n_splats + p], g11 = d_conic[2 * n_splats + p];
-        const float a00 = y00 * g00 + y01 * g01, a01 = y00 * g01 + y01 * g11;   // Y G
-        const float a10 = y01 * g00 + y11 * g01, a11 = y01 * g01 + y11 * g11;
-        const float G00 = -(a00 * y00 + a01 * y01), G01 = -(a00 * y01 + a01 * y11);
-        const float G10 = -(a10 * y00 + a11 * y01), G11 = -(a10 * y01 + a11 * y11);
+        const double y00 = r0.z, y01 = r0.w, y11 = r1.x;
+        const double g00 = d_conic[p], g01 = d_conic[n_splats + p], g11 = d_conic[2 * n_splats + p];
+        const double a00 = y00 * g00 + y01 * g01, a01 = y00 * g01 + y01 * g11;   // Y G
+        const double a10 = y01 * g00 + y11 * g01, a11 = y01 * g01 + y11 * g11;
+        const double G00 = -(a00 * y00 + a01 * y01), G01 = -(a00 * y01 + a01 * y11);
+        const double G10 = -(a10 * y00 + a11 * y01), G11 = -(a10 * y01 + a11 * y11);
 
         // mean route (eq. 23 reduced)
-        const float dmx = d_mean2d[p], dmy = d_mean2d[n_splats + p];
-        float dtx = J00 * dmx, dty = J11 * dmy, dtz = J02 * dmx + J12 * dmy;
+        const double dmx = d_mean2d[p], dmy = d_mean2d[n_splats + p];
+        double dtx = J00 * dmx, dty = J11 * dmy, dtz = J02 * dmx + J12 * dmy;
 
         // covariance route: dL/dT = G T Sigma + G^T T Sigma (eq. 25), dL/dJ = dL/dT R_cw^T
-        float TS[6];
+        double TS[6];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 TS[3 * r + b] = T[3 * r] * S[b] + T[3 * r + 1] * S[3 + b] + T[3 * r + 2] * S[6 + b];
-        float dT[6];
+        double dT[6];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             dT[b] = (G00 + G00) * TS[b] + (G01 + G10) * TS[3 + b];
             dT[3 + b] = (G10 + G01) * TS[b] + (G11 + G11) * TS[3 + b];
         }
-        float dJ[6];
+        double dJ[6];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 dJ[3 * r + a] = dT[3 * r] * R[3 * a] + dT[3 * r + 1] * R[3 * a + 1] + dT[3 * r + 2] * R[3 * a + 2];
         // dJ/dt (Sec. 3.2)
-        const float iz3 = iz2 * iz;
+        const double iz3 = iz2 * iz;
         dtx += dJ[2] * (-fx * iz2);
         dty += dJ[5] * (-fy * iz2);
-        dtz += dJ[0] * (-fx * iz2) + dJ[2] * (2.f * fx * tx * iz3) + dJ[4] * (-fy * iz2) + dJ[5] * (2.f * fy * ty * iz3);
+        dtz += dJ[0] * (-fx * iz2) + dJ[2] * (2.0 * fx * tx * iz3) + dJ[4] * (-fy * iz2) + dJ[5] * (2.0 * fy * ty * iz3);
 
         // eq. (28): dL/dmu = R_cw^T dL/dt
-        const float dmu0 = R[0] * dtx + R[3] * dty + R[6] * dtz;
-        const float dmu1 = R[1] * dtx + R[4] * dty + R[7] * dtz;
-        const float dmu2 = R[2] * dtx + R[5] * dty + R[8] * dtz;
+        const double dmu0 = R[0] * dtx + R[3] * dty + R[6] * dtz;
+        const double dmu1 = R[1] * dtx + R[4] * dty + R[7] * dtz;
+        const double dmu2 = R[2] * dtx + R[5] * dty + R[8] * dtz;
 
         // eq. (24): dL/dSigma = T^T G T
-        float GT[6];
+        double GT[6];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             GT[b] = G00 * T[b] + G01 * T[3 + b];
             GT[3 + b] = G10 * T[b] + G11 * T[3 + b];
         }
-        float dS[9];
+        double dS[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) dS[3 * a + b] = T[a] * GT[b] + T[3 + a] * GT[3 + b];
         // eq. (29): dL/dM = (dL/dSigma + dL/dSigma^T) M
-        float dM[9];
+        double dM[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -127,58 +131,58 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
                 dM[3 * a + b] = (dS[3 * a] + dS[a]) * M[b] + (dS[3 * a + 1] + dS[3 + a]) * M[3 + b] +
                                 (dS[3 * a + 2] + dS[6 + a]) * M[6 + b];
         // eq. (30): dL/dR = dL/dM S^T, dL/dS = R^T dL/dM; eq. (31) keeps its diagonal
-        float dR[9];
+        double dR[9];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) dR[3 * a + b] = dM[3 * a + b] * sv[b];
-        float ds[3];
+        double ds[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) ds[b] = Q[b] * dM[b] + Q[3 + b] * dM[3 + b] + Q[6 + b] * dM[6 + b];
         // dR/dq (Sec. 3.2.1), q = (w, x, y, z)
-        const float dqw = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-        const float dqx = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - qw * dR[5] + qz * dR[6] +
-                                 qw * dR[7] - 2.f * qx * dR[8]);
-        const float dqy = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
-                                 qz * dR[7] - 2.f * qy * dR[8]);
-        const float dqz = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] +
+        const double dqw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+        const double dqx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                                 qw * dR[7] - 2.0 * qx * dR[8]);
+        const double dqy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                                 qz * dR[7] - 2.0 * qy * dR[8]);
+        const double dqz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
                                  qy * dR[5] + qx * dR[6] + qy * dR[7]);
 
         if (use_atomics) {
-            atomic_add_f32(&d_means[i], dmu0);
-            atomic_add_f32(&d_means[n + i], dmu1);
-            atomic_add_f32(&d_means[2 * n + i], dmu2);
-            atomic_add_f32(&d_scales[i], ds[0]);
-            atomic_add_f32(&d_scales[n + i], ds[1]);
-            atomic_add_f32(&d_scales[2 * n + i], ds[2]);
-            atomic_add_f32(&d_quats[i], dqw);
-            atomic_add_f32(&d_quats[n + i], dqx);
-            atomic_add_f32(&d_quats[2 * n + i], dqy);
-            atomic_add_f32(&d_quats[3 * n + i], dqz);
+            atomic_add_f32(&d_means[i], (float)dmu0);
+            atomic_add_f32(&d_means[n + i], (float)dmu1);
+            atomic_add_f32(&d_means[2 * n + i], (float)dmu2);
+            atomic_add_f32(&d_scales[i], (float)ds[0]);
+            atomic_add_f32(&d_scales[n + i], (float)ds[1]);
+            atomic_add_f32(&d_scales[2 * n + i], (float)ds[2]);
+            atomic_add_f32(&d_quats[i], (float)dqw);
+            atomic_add_f32(&d_quats[n + i], (float)dqx);
+            atomic_add_f32(&d_quats[2 * n + i], (float)dqy);
+            atomic_add_f32(&d_quats[3 * n + i], (float)dqz);
         } else {
-            d_means[i] += dmu0;
-            d_means[n + i] += dmu1;
-            d_means[2 * n + i] += dmu2;
-            d_scales[i] += ds[0];
-            d_scales[n + i] += ds[1];
-            d_scales[2 * n + i] += ds[2];
-            d_quats[i] += dqw;
-            d_quats[n + i] += dqx;
-            d_quats[2 * n + i] += dqy;
-            d_quats[3 * n + i] += dqz;
+            d_means[i] += (float)dmu0;
+            d_means[n + i] += (float)dmu1;
+            d_means[2 * n + i] += (float)dmu2;
+            d_scales[i] += (float)ds[0];
+            d_scales[n + i] += (float)ds[1];
+            d_scales[2 * n + i] += (float)ds[2];
+            d_quats[i] += (float)dqw;
+            d_quats[n + i] += (float)dqx;
+            d_quats[2 * n + i] += (float)dqy;
+            d_quats[3 * n + i] += (float)dqz;
         }
 
         if (d_pose) {
             // eq. (28): dL/dT_cw = dL/dt [mu; 1]^T, plus J^T dL/dT for R_cw entering T = J R_cw
-            const float dt[3] = {dtx, dty, dtz}, mu[3] = {mx, my, mz};
-            const float JtdT[9] = {J00 * dT[0], J00 * dT[1], J00 * dT[2],
+            const double dt[3] = {dtx, dty, dtz}, mu[3] = {mx, my, mz};
+            const double JtdT[9] = {J00 * dT[0], J00 * dT[1], J00 * dT[2],
                                    J11 * dT[3], J11 * dT[4], J11 * dT[5],
                                    J02 * dT[0] + J12 * dT[3], J02 * dT[1] + J12 * dT[4], J02 * dT[2] + J12 * dT[5]};
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
 #pragma unroll
-                for (int b = 0; b < 3; ++b) pose[4 * r + b] = dt[r] * mu[b] + JtdT[3 * r + b];
-                pose[4 * r + 3] = dt[r];
+                for (int b = 0; b < 3; ++b) pose[4 * r + b] = (float)(dt[r] * mu[b] + JtdT[3 * r + b]);
+                pose[4 * r + 3] = (float)dt[r];
             }
         }
     }

@@ -1,262 +1,392 @@
 // gs_rasterize_fwd / gs_rasterize_bwd: per-tile compositing (Sec. 2.2, eq. 7) and its
 // gradients (Sec. 3.1, eqs. 16-21).
 //
-// One workgroup of 256 lanes (4 wave64) per 16x16 tile, one lane per pixel. The tile's
-// depth-ordered list is walked in batches of kBatch splats staged in LDS: each lane
-// gathers one 48-byte splat record and stores it pre-scaled so that, per pixel,
-//   alpha_raw = o exp(-sigma) = exp2(log2 o + A dx^2 + B dx dy + C dy^2)
-// with A = -Y00 log2(e) / 2, B = -Y01 log2(e), C = -Y11 log2(e) / 2 and
-// (dx, dy) = Delta = mu' - pixel centre. Every lane of a wave then reads the same LDS
-// word (a broadcast, no bank conflicts).
+// Work items. gs_bin_and_sort leaves a work list of tiles in decreasing list length
+// (longest first). A tile with a short list is one item: one wave64, four horizontally
+// adjacent pixels per lane. A tile with a long list is four items, each a 16x4-pixel
+// quarter at one pixel per lane, so that its walk, the critical path of the launch, is
+// split over four waves. The kernels are persistent: every wave takes items from an
+// atomic counter until the list is exhausted, and the last wave out resets the counter
+// so the next launch (or graph replay) starts from zero. A wave raises its issue priority
+// (s_setprio) while it works on a quarter item, so that the longest walks keep their SIMD.
 //
-// The backward re-walks each pixel's list from its last composited entry, recomputing
-// sigma and alpha with the same arithmetic, recovering T by division from T_final
-// (eq. 17) and carrying G_S = sum_k dL/dC(k) S(k) (eq. 18 summed over channels). Per
-// pair it forms nine terms; they are summed over the wave with DPP (lane 63 holds the
-// total), added across the 4 waves in LDS, and flushed to global memory with one
-// atomic per term per (tile, splat) after each batch:
-//   v = dL/dalpha * alpha        ->  dL/do   = sum v / o
-//   v dx, v dy                   ->  dL/dmu' = -Y sum v Delta
-//   v dx^2, v dx dy, v dy^2      ->  dL/dY   = -1/2 sum v Delta Delta^T
-//   alpha T dL/dC(k)             ->  dL/dc(k)
+// Records. A wave walks its list in batches of 64 entries. For each batch every lane
+// gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
+// into the wave's own LDS slice; the next batch is gathered into registers while the
+// current one is composited, so the random record reads stay off the critical path. The
+// walk then reads each record back with broadcast LDS loads. No workgroup barrier is ever
+// needed: a wave only reads the LDS slice it wrote. Per lane and splat the row terms
+// lo + C dy^2 and B dy are formed once and shared by the lane's pixels; per pixel the
+// exponent costs one subtraction and two FMAs in float64 (exact Delta, no cancellation
+// loss), one conversion and a float32 exp2. Compositing is branch-free: a pixel that
+// skips, stops or is done composites with weight zero.
+//
+// Backward: each pixel walks its list from `last` down, recomputing alpha with the same
+// instructions as the forward, recovering T = T_after / (1 - alpha) (eq. 17) and carrying
+// G_S = sum_k dL/dC(k) S(k) (eq. 18 summed over channels). Per lane it sums the nine
+// per-pair terms of its pixels,
+//   v = dL/dalpha * alpha, v dx, v dy, v dx^2, v dx dy, v dy^2, alpha T dL/dC(k) (k = 0..2)
+// then the wave adds them across lanes (DPP) and lane 63 issues one atomic per term:
+//   dL/do = sum v / o, dL/dmu' = -Y sum v Delta, dL/dY = -1/2 sum v Delta Delta^T, dL/dc.
 #include "common.h"
 
 namespace gsx {
 
-constexpr int kBatch = 256;
-constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kBlockWaves = 4;
+constexpr int kBatch = kWave;   // list entries staged per wave and batch
 
-struct TileCtx {
-    int tile, start, end;
-    int row, col;          // pixel of this lane
-    bool inside;
-    int64_t pix;           // packed pixel index
+// The wave's LDS slice for one batch of records.
+__device__ inline RasterRec *wave_slice()
+{
+    __shared__ RasterRec slice[kBlockWaves][kBatch];
+    return slice[__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
+}
+
+// Gathers the records of list entries [b, b + n) into registers, one per lane.
+struct Gathered {
+    float4 q0, q1, q2, q3;
 };
 
-__device__ inline TileCtx tile_context(const gs_camera *__restrict__ cams, int n_cams,
-                                       const int32_t *__restrict__ ranges)
+__device__ inline Gathered gather(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, int b, int n,
+                                  int lane)
 {
-    TileCtx t;
-    t.tile = blockIdx.x;
-    const int c = camera_of_tile(cams, n_cams, t.tile);
-    const int local = t.tile - cams[c].tile_offset;
+    Gathered g;
+    if (lane < n) {
+        const int id = ids[b + lane];
+        const float4 *p = (const float4 *)(rr + id);
+        g.q0 = p[0];
+        g.q1 = p[1];
+        g.q2 = p[2];
+        g.q3 = p[3];
+        g.q3.w = __int_as_float(id);   // the record's spare word carries the splat slot
+    } else {
+        g.q0 = g.q1 = g.q2 = g.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return g;
+}
+
+__device__ inline void stage(RasterRec *slice, const Gathered &g, int lane)
+{
+    float4 *d = (float4 *)(slice + lane);
+    d[0] = g.q0;
+    d[1] = g.q1;
+    d[2] = g.q2;
+    d[3] = g.q3;
+}
+
+struct ItemPixels {
+    int start, end;
+    int row, col0;       // this lane's row and first column (image coordinates)
+    int W, H;
+    int64_t pix0;        // packed index of (row, col0)
+};
+
+// Decodes item = tile << 3 | quarter << 2 | part into this lane's pixels.
+template <int PX>
+__device__ inline ItemPixels item_pixels(const gs_camera *__restrict__ cams, int n_cams,
+                                         const int32_t *__restrict__ ranges, int item, int lane)
+{
+    ItemPixels t;
+    const int tile = item >> 3, part = item & 3;
+    const int c = camera_of_tile(cams, n_cams, tile);
+    const int local = tile - cams[c].tile_offset;
     const int tx_n = cams[c].tiles_x;
     const int ty = local / tx_n, tx = local - ty * tx_n;
-    t.row = ty * kTile + (int)(threadIdx.x / kTile);
-    t.col = tx * kTile + (int)(threadIdx.x % kTile);
-    const int W = cams[c].width, H = cams[c].height;
-    t.inside = t.row < H && t.col < W;
-    t.pix = cams[c].pixel_offset + (int64_t)t.row * W + t.col;
-    t.start = ranges[2 * t.tile];
-    t.end = ranges[2 * t.tile + 1];
+    t.W = cams[c].width;
+    t.H = cams[c].height;
+    if (PX == 4) {
+        t.row = ty * kTile + (lane >> 2);
+        t.col0 = tx * kTile + (lane & 3) * 4;
+    } else {
+        t.row = ty * kTile + part * 4 + (lane >> 4);
+        t.col0 = tx * kTile + (lane & 15);
+    }
+    t.pix0 = cams[c].pixel_offset + (int64_t)t.row * t.W + t.col0;
+    t.start = ranges[2 * tile];
+    t.end = ranges[2 * tile + 1];
     return t;
 }
 
-// Stage splat ids[k] into slot `slot` of the LDS batch.
-struct Stage {
-    float4 geo[kBatch];    // mu'x, mu'y, A, B
-    float4 geo2[kBatch];   // C, log2 o, c0, c1
-    float c2[kBatch];
-};
-
-__device__ inline void stage_one(Stage &s, int slot, const float4 *__restrict__ rec, int id)
+// alpha_raw for one pixel given the lane's shared row terms; identical in forward and backward.
+__device__ __forceinline__ float alpha_raw(const RasterRec &r, double dx, double bdy, double cdl)
 {
-    const float4 r0 = rec[3 * (int64_t)id + 0];
-    const float4 r1 = rec[3 * (int64_t)id + 1];
-    const float4 r2 = rec[3 * (int64_t)id + 2];
-    s.geo[slot] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
-    s.geo2[slot] = make_float4(-0.5f * kLog2e * r1.x, __log2f(r1.y), r1.z, r1.w);
-    s.c2[slot] = r2.x;
+    const double e = __builtin_fma(__builtin_fma(r.A, dx, bdy), dx, cdl);
+    return __builtin_amdgcn_exp2f((float)e);
 }
 
-__device__ inline float alpha_exponent(const float4 &g0, const float4 &g1, float dx, float dy)
+// Next item for this wave, or -1. The counter hands out positions in the work list; the
+// last wave to find the list exhausted resets the counters.
+__device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_items, int lane)
 {
-    return g1.y + dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy;
+    int pos = 0;
+    if (lane == 0) pos = atomicAdd(&sched[counter], 1);
+    pos = __builtin_amdgcn_readfirstlane(pos);
+    if (pos < n_items) return __builtin_amdgcn_readfirstlane(sched[kSchedHeader + pos]);
+    if (lane == 0) {
+        const int waves = (int)gridDim.x * kBlockWaves;
+        if (atomicAdd(&sched[counter + 1], 1) == waves - 1) {
+            sched[counter] = 0;
+            sched[counter + 1] = 0;
+        }
+    }
+    return -1;
 }
 
 // ----------------------------------------------------------------------------- forward
 
-__global__ __launch_bounds__(kTilePixels) void raster_fwd_kernel(const float4 *__restrict__ rec,
-                                                                 const int32_t *__restrict__ ids,
-                                                                 const int32_t *__restrict__ ranges,
-                                                                 const gs_camera *__restrict__ cams, int n_cams,
-                                                                 gs_params prm, int64_t n_pixels,
-                                                                 float *__restrict__ image, float *__restrict__ T_out,
-                                                                 int32_t *__restrict__ last_out,
-                                                                 int32_t *__restrict__ visited_out)
+// Per-pixel state is kept arithmetic so that every select depends on a single compare and no
+// lane masks need combining: a skipped splat gets alpha = 0 (a no-op update), and a finished
+// pixel carries T < 0 with |T| its final transmittance.
+template <int PX, bool kVisited>
+__device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
+                                const ItemPixels &t, const gs_params &prm, int64_t n_pixels,
+                                float *__restrict__ image, float *__restrict__ T_out, int32_t *__restrict__ last_out,
+                                int32_t *__restrict__ visited_out)
 {
-    __shared__ Stage s;
-    const TileCtx t = tile_context(cams, n_cams, ranges);
-    const float px = (float)t.col + 0.5f, py = (float)t.row + 0.5f;
-    float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    int last = 0, vis = 0;
-    bool done = !t.inside;
+    const double pyd = (double)t.row + 0.5;
+    double pxd[PX];
+    float T[PX], c0[PX], c1[PX], c2[PX];
+    int last[PX], vis[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        pxd[q] = (double)(t.col0 + q) + 0.5;
+        T[q] = (t.row < t.H && t.col0 + q < t.W) ? 1.f : -1.f;
+        c0[q] = c1[q] = c2[q] = 0.f;
+        last[q] = vis[q] = 0;
+    }
+    RasterRec *slice = wave_slice();
+    const int lane = threadIdx.x & (kWave - 1);
+    Gathered next = gather(rr, ids, t.start, min(kBatch, t.end - t.start), lane);
     for (int b = t.start; b < t.end; b += kBatch) {
-        if (__syncthreads_count(done) == kTilePixels) break;
         const int nb = min(kBatch, t.end - b);
-        if ((int)threadIdx.x < nb) stage_one(s, threadIdx.x, rec, ids[b + threadIdx.x]);
-        __syncthreads();
-        if (!done) {
-            for (int j = 0; j < nb; ++j) {
-                const float4 g0 = s.geo[j], g1 = s.geo2[j];
-                const float dx = g0.x - px, dy = g0.y - py;
-                const float alpha = fminf(prm.alpha_max, __builtin_amdgcn_exp2f(alpha_exponent(g0, g1, dx, dy)));
-                ++vis;
-                if (alpha < prm.alpha_min) continue;
-                const float Tn = T * (1.f - alpha);
-                if (Tn < prm.T_min) { done = true; break; }
-                const float w = alpha * T;
-                c0 += g1.z * w;
-                c1 += g1.w * w;
-                c2 += s.c2[j] * w;
-                T = Tn;
-                last = b - t.start + j + 1;
+        stage(slice, next, lane);
+        if (b + kBatch < t.end) next = gather(rr, ids, b + kBatch, min(kBatch, t.end - b - kBatch), lane);
+        float tmax = T[0];
+#pragma unroll
+        for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, T[q]);
+        if (__ballot(tmax >= 0.f) == 0) break;          // every pixel of the item is finished
+        for (int j = 0; j < nb; ++j) {
+            if ((j & 7) == 7) {
+                float m = T[0];
+#pragma unroll
+                for (int q = 1; q < PX; ++q) m = fmaxf(m, T[q]);
+                if (__ballot(m >= 0.f) == 0) break;
+            }
+            const RasterRec r = slice[j];
+            const double dy = (double)r.my - pyd;
+            const double bdy = r.B * dy;
+            const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
+            const int pos1 = b + j - t.start + 1;
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const double dx = (double)r.mx - pxd[q];
+                float a = fminf(prm.alpha_max, alpha_raw(r, dx, bdy, cdl));
+                a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
+                if (kVisited) vis[q] += T[q] >= 0.f ? 1 : 0;
+                const float Tn = T[q] * (1.f - a);
+                const bool stop = Tn < prm.T_min;                // also true once finished (T < 0)
+                const float w = stop ? 0.f : a * T[q];
+                c0[q] = __builtin_fmaf(r.c0, w, c0[q]);
+                c1[q] = __builtin_fmaf(r.c1, w, c1[q]);
+                c2[q] = __builtin_fmaf(r.c2, w, c2[q]);
+                last[q] = w > 0.f ? pos1 : last[q];
+                T[q] = stop ? -fabsf(T[q]) : Tn;
             }
         }
-        __syncthreads();
     }
-    if (t.inside) {
-        image[t.pix] = c0;
-        image[n_pixels + t.pix] = c1;
-        image[2 * n_pixels + t.pix] = c2;
-        T_out[t.pix] = T;
-        last_out[t.pix] = last;
-        if (visited_out) visited_out[t.pix] = vis;
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        if (t.row < t.H && t.col0 + q < t.W) {
+            const int64_t pix = t.pix0 + q;
+            image[pix] = c0[q];
+            image[n_pixels + pix] = c1[q];
+            image[2 * n_pixels + pix] = c2[q];
+            T_out[pix] = fabsf(T[q]);
+            last_out[pix] = last[q];
+            if (kVisited) visited_out[pix] = vis[q];
+        }
+    }
+}
+
+template <bool kVisited>
+__global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
+    const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, int64_t n_pixels,
+    float *__restrict__ image, float *__restrict__ T_out, int32_t *__restrict__ last_out,
+    int32_t *__restrict__ visited_out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    for (;;) {
+        const int item = next_item(sched, kSchedFwd, n_items, lane);
+        if (item < 0) break;
+        if (item & 4) {
+            __builtin_amdgcn_s_setprio(2);
+            fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, n_pixels, image,
+                                  T_out, last_out, visited_out);
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, n_pixels, image,
+                                  T_out, last_out, visited_out);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------- backward
 
-struct StageB {
-    Stage g;
-    int id[kBatch];
-    int src[kBatch];
-    float opac[kBatch];
-    float acc[9][kBatch];
+__device__ inline int wave_max(int v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v = max(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+struct BwdOut {
+    int64_t n_splats, n_gauss;
+    float *d_mean2d, *d_conic, *d_colors, *d_opac;
 };
 
-__global__ __launch_bounds__(kTilePixels) void raster_bwd_kernel(const float4 *__restrict__ rec,
-                                                                 const int32_t *__restrict__ ids,
-                                                                 const int32_t *__restrict__ ranges,
-                                                                 const gs_camera *__restrict__ cams, int n_cams,
-                                                                 gs_params prm, int64_t n_pixels,
-                                                                 const float *__restrict__ dL_dimage,
-                                                                 const float *__restrict__ T_final,
-                                                                 const int32_t *__restrict__ last_in,
-                                                                 int64_t n_splats, int64_t n_gauss,
-                                                                 float *__restrict__ d_mean2d,
-                                                                 float *__restrict__ d_conic,
-                                                                 float *__restrict__ d_colors,
-                                                                 float *__restrict__ d_opac)
+template <int PX>
+__device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
+                                const ItemPixels &t, const gs_params &prm, int64_t n_pixels,
+                                const float *__restrict__ dL_dimage, const float *__restrict__ T_final,
+                                const int32_t *__restrict__ last_in, const BwdOut &out, int lane)
 {
-    __shared__ StageB s;
-    __shared__ int s_maxlast;
-    const TileCtx t = tile_context(cams, n_cams, ranges);
-    const float px = (float)t.col + 0.5f, py = (float)t.row + 0.5f;
-    float gr = 0.f, gg = 0.f, gb = 0.f, T = 1.f;
-    int last = 0;
-    if (t.inside) {
-        gr = dL_dimage[t.pix];
-        gg = dL_dimage[n_pixels + t.pix];
-        gb = dL_dimage[2 * n_pixels + t.pix];
-        T = T_final[t.pix];
-        last = last_in[t.pix];
+    const double pyd = (double)t.row + 0.5;
+    double pxd[PX];
+    float T[PX], gS[PX], g0[PX], g1[PX], g2[PX];
+    int last[PX];
+    int maxlast = 0;
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        pxd[q] = (double)(t.col0 + q) + 0.5;
+        gS[q] = 0.f;
+        T[q] = 1.f;
+        g0[q] = g1[q] = g2[q] = 0.f;
+        last[q] = 0;
+        if (t.row < t.H && t.col0 + q < t.W) {
+            const int64_t pix = t.pix0 + q;
+            T[q] = T_final[pix];
+            last[q] = last_in[pix];
+            g0[q] = dL_dimage[pix];
+            g1[q] = dL_dimage[n_pixels + pix];
+            g2[q] = dL_dimage[2 * n_pixels + pix];
+        }
+        maxlast = max(maxlast, last[q]);
     }
-    if (threadIdx.x == 0) s_maxlast = 0;
-    __syncthreads();
-    if (last > 0) atomicMax(&s_maxlast, last);
-    __syncthreads();
-    const int maxlast = s_maxlast;
-    const int lane = threadIdx.x & (kWave - 1);
-    float gS = 0.f;
-    for (int bend = t.start + maxlast; bend > t.start; bend -= kBatch) {
+    maxlast = __builtin_amdgcn_readfirstlane(wave_max(maxlast));
+    if (maxlast == 0) return;
+    const float kInvLog2e = (float)(1.0 / kLog2eD);
+    RasterRec *slice = wave_slice();
+    const int kend = t.start + maxlast;
+    // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
+    Gathered next = gather(rr, ids, max(t.start, kend - kBatch), kend - max(t.start, kend - kBatch), lane);
+    for (int bend = kend; bend > t.start; bend -= kBatch) {
         const int bstart = max(t.start, bend - kBatch);
         const int nb = bend - bstart;
-        if ((int)threadIdx.x < nb) {
-            const int id = ids[bstart + threadIdx.x];
-            stage_one(s.g, threadIdx.x, rec, id);
-            const float4 r1 = rec[3 * (int64_t)id + 1];
-            const float4 r2 = rec[3 * (int64_t)id + 2];
-            s.id[threadIdx.x] = id;
-            s.opac[threadIdx.x] = r1.y;
-            s.src[threadIdx.x] = __float_as_int(r2.z);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s.acc[q][threadIdx.x] = 0.f;
+        stage(slice, next, lane);
+        if (bstart > t.start) {
+            const int pb = max(t.start, bstart - kBatch);
+            next = gather(rr, ids, pb, bstart - pb, lane);
         }
-        __syncthreads();
         for (int j = nb - 1; j >= 0; --j) {
-            const int pos = bstart - t.start + j;   // position in the tile's list
-            float v[9];
+            const int pos = bstart + j - t.start;
+            const RasterRec r = slice[j];
+            const int id = r.pad;
+            const double dy = (double)r.my - pyd;
+            const double bdy = r.B * dy;
+            const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
+            const float dyf = (float)dy;
+            float s_v = 0.f, s_x = 0.f, s_y = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, s_c0 = 0.f, s_c1 = 0.f,
+                  s_c2 = 0.f;
+            float live_sum = 0.f;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) v[q] = 0.f;
-            bool contrib = false;
-            if (pos < last) {
-                const float4 g0 = s.g.geo[j], g1 = s.g.geo2[j];
-                const float dx = g0.x - px, dy = g0.y - py;
-                const float a_raw = __builtin_amdgcn_exp2f(alpha_exponent(g0, g1, dx, dy));
-                const float alpha = fminf(prm.alpha_max, a_raw);
-                if (alpha >= prm.alpha_min) {
-                    contrib = true;
-                    const float r = __builtin_amdgcn_rcpf(1.f - alpha);
-                    T = T * r;                                   // T before this splat (eq. 17)
-                    const float w = alpha * T;
-                    v[6] = w * gr;                               // eq. (16)
-                    v[7] = w * gg;
-                    v[8] = w * gb;
-                    const float gc = gr * g1.z + gg * g1.w + gb * s.g.c2[j];
-                    const float dalpha = gc * T - gS * r;        // eq. (18)
-                    gS += gc * w;
-                    if (a_raw <= prm.alpha_max) {
-                        const float vv = dalpha * alpha;         // eq. (19): dalpha/dsigma = -alpha
-                        v[0] = vv;
-                        v[1] = vv * dx;
-                        v[2] = vv * dy;
-                        v[3] = vv * dx * dx;
-                        v[4] = vv * dx * dy;
-                        v[5] = vv * dy * dy;
-                    }
-                }
+            for (int q = 0; q < PX; ++q) {
+                // inactive (past `last`) or skipped pairs get alpha = 0: then rcp(1 - alpha) = 1,
+                // w = 0 and v = 0, and the pair changes nothing
+                const double dx = (double)r.mx - pxd[q];
+                const float a_raw = alpha_raw(r, dx, bdy, cdl);
+                float a = fminf(prm.alpha_max, a_raw);
+                a = pos < last[q] ? a : 0.f;
+                a = a < prm.alpha_min ? 0.f : a;
+                live_sum += a;
+                const float rinv = __builtin_amdgcn_rcpf(1.f - a);
+                T[q] *= rinv;                                      // T before this splat (eq. 17)
+                const float w = a * T[q];
+                s_c0 = __builtin_fmaf(w, g0[q], s_c0);               // eq. (16)
+                s_c1 = __builtin_fmaf(w, g1[q], s_c1);
+                s_c2 = __builtin_fmaf(w, g2[q], s_c2);
+                const float gc = g0[q] * r.c0 + g1[q] * r.c1 + g2[q] * r.c2;
+                const float dalpha = gc * T[q] - gS[q] * rinv;      // eq. (18)
+                gS[q] = __builtin_fmaf(gc, w, gS[q]);
+                // eq. (19): dalpha/dsigma = -alpha; a clamped alpha passes no gradient to o or sigma
+                const float v = a_raw > prm.alpha_max ? 0.f : dalpha * a;
+                const float dxf = (float)dx;
+                const float vx = v * dxf;
+                s_v += v;
+                s_x += vx;
+                s_y = __builtin_fmaf(v, dyf, s_y);
+                s_xx = __builtin_fmaf(vx, dxf, s_xx);
+                s_xy = __builtin_fmaf(vx, dyf, s_xy);
+                s_yy = __builtin_fmaf(v * dyf, dyf, s_yy);
             }
-            if (__ballot(contrib) != 0) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const float sum = wave_sum_to_lane63(v[q]);
-                    if (lane == kWave - 1) atomicAdd(&s.acc[q][j], sum);
-                }
+            if (__ballot(live_sum > 0.f) == 0) continue;
+            s_v = wave_sum_to_lane63(s_v);
+            s_x = wave_sum_to_lane63(s_x);
+            s_y = wave_sum_to_lane63(s_y);
+            s_xx = wave_sum_to_lane63(s_xx);
+            s_xy = wave_sum_to_lane63(s_xy);
+            s_yy = wave_sum_to_lane63(s_yy);
+            s_c0 = wave_sum_to_lane63(s_c0);
+            s_c1 = wave_sum_to_lane63(s_c1);
+            s_c2 = wave_sum_to_lane63(s_c2);
+            if (lane == kWave - 1) {
+                // Y = -(2A, B; B, 2C) / log2(e); dL/dmu' = -Y sum v Delta
+                const float A2 = (float)(2.0 * r.A), B1 = (float)r.B, C2 = (float)(2.0 * r.C);
+                atomic_add_f32(&out.d_mean2d[id], (A2 * s_x + B1 * s_y) * kInvLog2e);
+                atomic_add_f32(&out.d_mean2d[out.n_splats + id], (B1 * s_x + C2 * s_y) * kInvLog2e);
+                atomic_add_f32(&out.d_conic[id], -0.5f * s_xx);
+                atomic_add_f32(&out.d_conic[out.n_splats + id], -0.5f * s_xy);
+                atomic_add_f32(&out.d_conic[2 * out.n_splats + id], -0.5f * s_yy);
+                atomic_add_f32(&out.d_colors[r.src], s_c0);
+                atomic_add_f32(&out.d_colors[out.n_gauss + r.src], s_c1);
+                atomic_add_f32(&out.d_colors[2 * out.n_gauss + r.src], s_c2);
+                atomic_add_f32(&out.d_opac[r.src], s_v / r.o);
             }
         }
-        __syncthreads();
-        if ((int)threadIdx.x < nb) {
-            const int k = threadIdx.x;
-            const float Sv = s.acc[0][k];
-            const float c_r = s.acc[6][k], c_g = s.acc[7][k], c_b = s.acc[8][k];
-            if (Sv != 0.f || c_r != 0.f || c_g != 0.f || c_b != 0.f) {
-                const int id = s.id[k], src = s.src[k];
-                const float4 g0 = s.g.geo[k], g1 = s.g.geo2[k];
-                const float Y00 = g0.z * (-2.f / kLog2e), Y01 = g0.w * (-1.f / kLog2e), Y11 = g1.x * (-2.f / kLog2e);
-                const float Sx = s.acc[1][k], Sy = s.acc[2][k];
-                atomic_add_f32(&d_mean2d[id], -(Y00 * Sx + Y01 * Sy));
-                atomic_add_f32(&d_mean2d[n_splats + id], -(Y01 * Sx + Y11 * Sy));
-                atomic_add_f32(&d_conic[id], -0.5f * s.acc[3][k]);
-                atomic_add_f32(&d_conic[n_splats + id], -0.5f * s.acc[4][k]);
-                atomic_add_f32(&d_conic[2 * n_splats + id], -0.5f * s.acc[5][k]);
-                atomic_add_f32(&d_colors[src], c_r);
-                atomic_add_f32(&d_colors[n_gauss + src], c_g);
-                atomic_add_f32(&d_colors[2 * n_gauss + src], c_b);
-                atomic_add_f32(&d_opac[src], Sv / s.opac[k]);
-            }
+    }
+}
+
+__global__ __launch_bounds__(kWave * kBlockWaves) void raster_bwd_kernel(
+    const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, int64_t n_pixels,
+    const float *__restrict__ dL_dimage, const float *__restrict__ T_final, const int32_t *__restrict__ last_in,
+    BwdOut out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    for (;;) {
+        const int item = next_item(sched, kSchedBwd, n_items, lane);
+        if (item < 0) break;
+        if (item & 4) {
+            __builtin_amdgcn_s_setprio(2);
+            bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, n_pixels, dL_dimage, T_final,
+                        last_in, out, lane);
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, n_pixels, dL_dimage, T_final,
+                        last_in, out, lane);
         }
-        __syncthreads();
     }
 }
 
 static int check_raster_args(const gs_splats *s, const gs_bins *bins, const gs_camera *cams, int32_t n_cams,
                              const gs_params *prm, int64_t n_pixels)
 {
-    if (!s || !bins || !cams || !prm || n_cams < 1 || n_pixels < 0 || !s->rec || !bins->ids || !bins->ranges ||
-        bins->n_tiles < 0)
+    if (!s || !bins || !cams || !prm || n_cams < 1 || n_pixels < 0 || !s->raster || !bins->ids || !bins->ranges ||
+        !bins->schedule || bins->n_tiles < 0)
         return set_error(GS_ERR_INVALID, "rasterize: null argument or bad size");
-    if (((uintptr_t)s->rec) & 15) return set_error(GS_ERR_INVALID, "rasterize: rec must be 16-byte aligned");
+    if (((uintptr_t)s->raster) & 63) return set_error(GS_ERR_INVALID, "rasterize: raster must be 64-byte aligned");
     return GS_OK;
 }
 
@@ -273,9 +403,16 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     if (rc != GS_OK) return rc;
     if (!image || !T_final || !last) return set_error(GS_ERR_INVALID, "gs_rasterize_fwd: null output");
     if (bins->n_tiles == 0) return GS_OK;
-    hipLaunchKernelGGL(raster_fwd_kernel, dim3((unsigned)bins->n_tiles), dim3(kTilePixels), 0, (hipStream_t)stream,
-                       (const float4 *)s->rec, bins->ids, bins->ranges, cams, (int)n_cams, *prm, n_pixels, image,
-                       T_final, last, visited);
+    // every tile is on the work list, empty ones included, so each pixel is written exactly once
+    const dim3 grid(persistent_blocks(kBlockWaves)), block(kWave * kBlockWaves);
+    if (visited)
+        hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, n_pixels, image, T_final,
+                           last, visited);
+    else
+        hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, n_pixels, image, T_final,
+                           last, (int32_t *)nullptr);
     return check_launch("gs_rasterize_fwd");
 }
 
@@ -293,8 +430,9 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     if (!(prm->alpha_max < 1.0f))
         return set_error(GS_ERR_INVALID, "gs_rasterize_bwd: alpha_max must be below 1 (eq. 17 divides by 1 - alpha)");
     if (bins->n_tiles == 0) return GS_OK;
-    hipLaunchKernelGGL(raster_bwd_kernel, dim3((unsigned)bins->n_tiles), dim3(kTilePixels), 0, (hipStream_t)stream,
-                       (const float4 *)s->rec, bins->ids, bins->ranges, cams, (int)n_cams, *prm, n_pixels, dL_dimage,
-                       T_final, last, n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac);
+    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
+    hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
+                       (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
+                       (int)n_cams, *prm, n_pixels, dL_dimage, T_final, last, out);
     return check_launch("gs_rasterize_bwd");
 }

@@ -1,5 +1,6 @@
 // Library runtime: per-thread error state, device check, graph-safe zeroing.
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "common.h"
@@ -30,6 +31,25 @@ int check_hip(hipError_t e, const char *what)
 }
 
 int check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
+
+unsigned persistent_blocks(int waves_per_block)
+{
+    static int cached_dev = -1, cached_cus = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (dev != cached_dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached_cus = cus;
+        cached_dev = dev;
+    }
+    // GSX_PERSISTENT_BLOCKS overrides the grid (tuning and diagnosis)
+    static const char *env = getenv("GSX_PERSISTENT_BLOCKS");
+    if (env && atoi(env) > 0) return (unsigned)atoi(env);
+    // 4 SIMDs per CU, up to 8 resident waves per SIMD
+    return (unsigned)((cached_cus * 32 + waves_per_block - 1) / waves_per_block);
+}
 
 __global__ __launch_bounds__(256) void zero_kernel(uint4 *__restrict__ p16, int64_t n16, unsigned char *__restrict__ tail,
                                                    int64_t ntail)
@@ -100,4 +120,35 @@ extern "C" int gs_abi_layout(int64_t *out, int n)
     const int m = (int)(sizeof(v) / sizeof(v[0]));
     for (int k = 0; k < n && k < m; ++k) out[k] = v[k];
     return m;
+}
+
+namespace gsx {
+__global__ __launch_bounds__(256) void l2_grad_kernel(const float4 *__restrict__ img, const float4 *__restrict__ tgt,
+                                                      int64_t n4, float4 *__restrict__ out,
+                                                      const float *__restrict__ img1, const float *__restrict__ tgt1,
+                                                      float *__restrict__ out1, int64_t ntail)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) {
+        const float4 a = img[i], b = tgt[i];
+        out[i] = make_float4(2.f * (a.x - b.x), 2.f * (a.y - b.y), 2.f * (a.z - b.z), 2.f * (a.w - b.w));
+    }
+    if (i < ntail) out1[i] = 2.f * (img1[i] - tgt1[i]);
+}
+}  // namespace gsx
+
+// dL/dC of L = sum (C - target)^2 over n floats: dL_dimage = 2 (image - target).
+extern "C" int gs_l2_grad(const float *image, const float *target, int64_t n, float *dL_dimage, void *stream)
+{
+    clear_error();
+    if (!image || !target || !dL_dimage || n < 0) return set_error(GS_ERR_INVALID, "gs_l2_grad: bad argument");
+    if (n == 0) return GS_OK;
+    const bool aligned = ((((uintptr_t)image) | ((uintptr_t)target) | ((uintptr_t)dL_dimage)) & 15) == 0;
+    const int64_t n4 = aligned ? n / 4 : 0;
+    const int64_t tail = n - 4 * n4;
+    const int64_t threads = n4 > tail ? n4 : tail;
+    hipLaunchKernelGGL(l2_grad_kernel, dim3(grid_for(threads, 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const float4 *)image, (const float4 *)target, n4, (float4 *)dL_dimage, image + 4 * n4,
+                       target + 4 * n4, dL_dimage + 4 * n4, tail);
+    return check_launch("gs_l2_grad");
 }

@@ -133,6 +133,7 @@ class GaussianSet:
 @dataclass
 class Splats:
     rec: torch.Tensor
+    raster: torch.Tensor
     depth: torch.Tensor
     rect: torch.Tensor
     tiles: torch.Tensor
@@ -141,12 +142,14 @@ class Splats:
     def alloc(P: int, device) -> "Splats":
         P1 = max(P, 1)
         return Splats(torch.empty(P1 * abi.REC_FLOATS, dtype=torch.float32, device=device),
+                      torch.empty(P1 * abi.RASTER_FLOATS, dtype=torch.float32, device=device),
                       torch.empty(P1, dtype=torch.float32, device=device),
                       torch.empty(P1 * 4, dtype=torch.int32, device=device),
                       torch.empty(P1, dtype=torch.int32, device=device))
 
     def struct(self, P: int) -> abi.GsSplats:
-        return abi.GsSplats(_ptr(self.rec), _ptr(self.depth), _ptr(self.rect), _ptr(self.tiles), P)
+        return abi.GsSplats(_ptr(self.rec), _ptr(self.raster), _ptr(self.depth), _ptr(self.rect), _ptr(self.tiles),
+                            P)
 
 
 @dataclass
@@ -154,6 +157,7 @@ class Bins:
     keys: torch.Tensor
     ids: torch.Tensor
     ranges: torch.Tensor
+    schedule: torch.Tensor
     counters: torch.Tensor
     workspace: torch.Tensor
     capacity: int
@@ -166,12 +170,13 @@ class Bins:
         return Bins(torch.empty(capacity, dtype=torch.int64, device=device),
                     torch.empty(capacity, dtype=torch.int32, device=device),
                     torch.empty(2 * max(n_tiles, 1), dtype=torch.int32, device=device),
+                    torch.empty(abi.gs_schedule_size(n_tiles), dtype=torch.int32, device=device),
                     torch.zeros(2, dtype=torch.int64, device=device),
                     torch.empty(max(ws, 1), dtype=torch.uint8, device=device), capacity, n_tiles)
 
     def struct(self) -> abi.GsBins:
-        return abi.GsBins(_ptr(self.keys), _ptr(self.ids), _ptr(self.ranges), _ptr(self.counters), self.capacity,
-                          self.n_tiles, 0)
+        return abi.GsBins(_ptr(self.keys), _ptr(self.ids), _ptr(self.ranges), _ptr(self.schedule),
+                          _ptr(self.counters), self.capacity, self.n_tiles, 0)
 
 
 @dataclass
@@ -272,3 +277,79 @@ class Rasterizer:
                            _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]),
                            _ptr(grads.get("campose")), stream)
         return grads
+
+
+class TrainStep:
+    """One step of fwd + L2 loss gradient + bwd over a fixed camera set, with every
+    buffer preallocated, so the step allocates nothing and can be timed or captured.
+
+    Stages (each a C-ABI call on the current stream):
+      project, bin_and_sort, rasterize_fwd, l2_grad, zero, rasterize_bwd, project_bwd
+    """
+
+    STAGES = ("project", "bin_and_sort", "rasterize_fwd", "l2_grad", "zero_grads", "rasterize_bwd", "project_bwd")
+
+    def __init__(self, g: GaussianSet, cams: CameraSet, targets: torch.Tensor, params: abi.GsParams | None = None,
+                 capacity: int | None = None, capacity_margin: float = 1.25):
+        self.g, self.cams = g, cams
+        self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True)
+        self.targets = targets.contiguous().view(3, -1).to(torch.float32)
+        assert self.targets.shape[1] == cams.n_pixels
+        st = self.r.forward(g)                      # sizes the list capacity
+        if capacity is None and st.K * capacity_margin > self.r.capacity:
+            self.r.capacity = int(st.K * capacity_margin) + 1024
+            self.r.bins = Bins.alloc(cams.n_splats, self.r.capacity, cams.n_tiles, cams.device)
+            st = self.r.forward(g)
+        self.K = st.K
+        torch.cuda.synchronize()
+        self.E_fwd = int(self.r.visited.sum())     # pairs whose alpha the forward evaluates
+        self.E_bwd = int(self.r.last.sum())        # pairs the backward walks
+        self.r.visited = None                      # the timed step does not write it
+        P, n = cams.n_splats, g.n
+        sizes = {"mean2d": 2 * max(P, 1), "conic": 3 * max(P, 1), "colors": 3 * n, "opacities": n,
+                 "means": 3 * n, "scales": 3 * n, "quats": 4 * n}
+        total = sum(sizes.values())
+        self.grad_flat = torch.empty(total, dtype=torch.float32, device=cams.device)
+        self.grads, o = {}, 0
+        for k, sz in sizes.items():
+            self.grads[k] = self.grad_flat[o:o + sz]
+            o += sz
+        self.dL = torch.empty(3, cams.n_pixels, dtype=torch.float32, device=cams.device)
+
+    def run_stage(self, name: str, stream: int):
+        r, cams, g, P = self.r, self.cams, self.g, self.cams.n_splats
+        if name == "project":
+            r.project(g, stream)
+        elif name == "bin_and_sort":
+            r.bin_and_sort(stream)
+        elif name == "rasterize_fwd":
+            r.rasterize_fwd(stream)
+        elif name == "l2_grad":
+            abi.gs_l2_grad(r.image.data_ptr(), self.targets.data_ptr(), r.image.numel(), self.dL.data_ptr(), stream)
+        elif name == "zero_grads":
+            abi.gs_zero(self.grad_flat.data_ptr(), self.grad_flat.numel() * 4, stream)
+        elif name == "rasterize_bwd":
+            gr = self.grads
+            abi.gs_rasterize_bwd(r.splats.struct(P), P, r.bins.struct(), cams.ptr, cams.n_cams, r.params,
+                                 cams.n_pixels, self.dL.data_ptr(), r.T_final.data_ptr(), r.last.data_ptr(),
+                                 gr["mean2d"].data_ptr(), gr["conic"].data_ptr(), g.n, gr["colors"].data_ptr(),
+                                 gr["opacities"].data_ptr(), stream)
+        elif name == "project_bwd":
+            gr = self.grads
+            abi.gs_project_bwd(g.struct(), cams.ptr, cams.n_cams, r.splats.struct(P), P, gr["mean2d"].data_ptr(),
+                               gr["conic"].data_ptr(), gr["means"].data_ptr(), gr["scales"].data_ptr(),
+                               gr["quats"].data_ptr(), None, stream)
+        else:
+            raise KeyError(name)
+
+    def __call__(self, stream: int | None = None, events: list | None = None):
+        stream = current_stream() if stream is None else stream
+        for i, name in enumerate(self.STAGES):
+            if events is not None:
+                events[i].record()
+            self.run_stage(name, stream)
+        if events is not None:
+            events[len(self.STAGES)].record()
+
+    def overflowed(self) -> bool:
+        return bool(self.r.bins.counters[1].item())

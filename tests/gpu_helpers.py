@@ -79,6 +79,14 @@ def elementwise_ok(a, b, rel=GRAD_REL):
     return bool(np.all(np.abs(a - b) <= rel * (np.abs(b) + rms) + 1e-30))
 
 
+def worst_element(a, b):
+    """(index, gpu, ref, normalised error) of the element furthest from the elementwise bar."""
+    rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
+    r = np.abs(a - b) / (np.abs(b) + rms + 1e-30)
+    i = np.unravel_index(int(np.argmax(r)), r.shape)
+    return tuple(int(x) for x in i), float(a[i]), float(b[i]), float(r[i])
+
+
 def tile_offsets(wl):
     offs, t = [], 0
     for c in wl.cameras:
