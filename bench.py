@@ -28,7 +28,6 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic VALU lane-operations per Gaussian-pixel pair (exp2 and rcp count 4)
 SLOTS_FWD = 21
 SLOTS_BWD = 46
-KERNEL_OF_STAGE = {"rasterize_fwd": "raster_fwd_kernel", "rasterize_bwd": "raster_bwd_kernel"}
 
 
 def log(*a):
@@ -78,13 +77,78 @@ def cpu_baseline(wl, E_fwd: int, repeats: int = 3):
             "seconds_per_step": t}
 
 
+def time_steps(fn, steps: int, warmup: int) -> float:
+    """Mean ms per call over `steps` calls after `warmup`, events around the whole region."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def batched_vs_per_view(cfg: int, steps: int, warmup: int) -> dict:
+    """One fused persistent launch over every camera, captured in a HIP graph, against the same
+    kernels run one view per launch sequence with no graph."""
+    import numpy as np
+    import torch
+    from paper_2312_02121_amd import pipeline, synth
+    wl = synth.make_config(cfg)
+    g = pipeline.GaussianSet(wl.scenes)
+    cams = pipeline.CameraSet(wl.cameras, g.sizes)
+    tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
+    step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_image=False)
+    graph = pipeline.GraphStep(step)
+    ms_b = time_steps(graph, steps, warmup)
+    if step.overflowed():
+        raise SystemExit(f"config {cfg}: list overflow in the captured step")
+    E = step.E_fwd
+    del graph, step
+    torch.cuda.empty_cache()
+    targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
+    per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
+    ms_v = time_steps(per_view, steps, warmup)
+    del per_view
+    torch.cuda.empty_cache()
+    log(f"config {cfg}: batched {ms_b:.3f} ms, per-view {ms_v:.3f} ms")
+    return {"workload": wl.name, "views": cams.n_cams, "n_gaussians": g.n, "E_fwd": E,
+            "batched_ms_per_step": ms_b, "per_view_ms_per_step": ms_v,
+            "batched_evals_per_s": E / (ms_b * 1e-3), "per_view_evals_per_s": E / (ms_v * 1e-3),
+            "speedup": ms_v / ms_b, "batched_ms_per_view": ms_b / cams.n_cams}
+
+
+def autograd_ms(wl, steps: int, warmup: int) -> float:
+    """ms per fwd + L2 + bwd step through the torch.autograd.Function (host sync included)."""
+    import numpy as np
+    import torch
+    from paper_2312_02121_amd.autograd import render
+    s = wl.scenes[0]
+    ps = [torch.tensor(np.asarray(s[k]), device="cuda", requires_grad=True)
+          for k in ("means", "quats", "scales", "colors", "opacities")]
+    tgt = torch.from_numpy(wl.targets[0]).cuda()
+
+    def one():
+        img = render(*ps, wl.cameras)[0]
+        ((img - tgt) ** 2).sum().backward()
+    return time_steps(one, steps, warmup)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--mode", choices=("fused", "separate"), default="fused")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autograd", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the rasterizer is built and measured on a single MI355X); "
@@ -103,36 +167,38 @@ def main():
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     targets = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
-    step = pipeline.TrainStep(g, cams, targets)
+    step = pipeline.TrainStep(g, cams, targets, mode=args.mode)
     log(f"K={step.K} E_fwd={step.E_fwd} E_bwd={step.E_bwd} P={cams.n_splats} pixels={cams.n_pixels}")
 
+    # per-stage times (eager launches, events between stages on the launch stream)
     n_st = len(step.STAGES)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_st + 1)] for _ in range(args.steps)]
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record()
     for k in range(args.steps):
         step(events=evs[k])
-    t_end.record()
     torch.cuda.synchronize()
-    if step.overflowed():
-        raise SystemExit("intersection list overflowed its capacity during the timed steps")
-    total_ms = t_start.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
     stage_ms = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
                 for i, name in enumerate(step.STAGES)}
     log("stages (ms): " + " ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
 
-    work = {"rasterize_fwd": SLOTS_FWD * step.E_fwd, "rasterize_bwd": SLOTS_BWD * step.E_bwd}
-    dom = max(work, key=lambda s: stage_ms[s])
+    # the timed step: the whole path, captured once in a HIP graph and replayed
+    runner = step if args.no_graph else pipeline.GraphStep(step)
+    ms_step = time_steps(runner, args.steps, args.warmup)
+    if step.overflowed():
+        raise SystemExit("intersection list overflowed its capacity during the timed steps")
+    log(f"step {ms_step:.4f} ms ({'eager' if args.no_graph else 'graph'})")
+
+    work = {"rasterize_fwd": SLOTS_FWD * step.E_fwd, "rasterize_bwd": SLOTS_BWD * step.E_bwd,
+            "fused": SLOTS_FWD * step.E_fwd + SLOTS_BWD * step.E_bwd}
+    dom = max((s for s in work if s in stage_ms), key=lambda s: stage_ms[s])
     achieved = work[dom] / (stage_ms[dom] * 1e-3) / 1e12
-    traffic = traffic_from_profiles(KERNEL_OF_STAGE[dom])
-    roofline = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom], "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                "other": {s: (work[s] / (stage_ms[s] * 1e-3) / 1e12) / VALU_PEAK_TOPS for s in work}}
+    kname = {"rasterize_fwd": "raster_fwd_kernel", "rasterize_bwd": "raster_bwd_kernel",
+             "fused": "raster_fused_kernel"}[dom]
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_from_profiles(kname),
+                "slots_per_pair": {"fwd": SLOTS_FWD, "bwd": SLOTS_BWD}}
 
     views = cams.n_cams
     line = {
@@ -141,12 +207,21 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "n_gaussians": g.n, "views": views, "width": int(cams.host[0]["width"]),
                    "height": int(cams.host[0]["height"]), "K": step.K, "E_fwd": step.E_fwd, "E_bwd": step.E_bwd,
-                   "ms_per_view": ms_step / views, "parallelism": "single-gpu"},
+                   "ms_per_view": ms_step / views, "mode": args.mode, "graph": not args.no_graph,
+                   "parallelism": "single-gpu"},
         "stages_ms": stage_ms,
         "roofline": roofline,
     }
+    del runner
+    if not args.no_autograd and args.config == 3:
+        line["autograd_ms_per_step"] = autograd_ms(wl, max(3, args.steps // 4), 2)
+        log(f"autograd path {line['autograd_ms_per_step']:.3f} ms/step")
+    if not args.no_batched:
+        del step
+        torch.cuda.empty_cache()
+        line["batched"] = {f"c{c}": batched_vs_per_view(c, max(3, args.steps // 4), 2) for c in (4, 5)}
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
-        line["cpu_baseline"] = cpu_baseline(wl, step.E_fwd)
+        line["cpu_baseline"] = cpu_baseline(wl, line["config"]["E_fwd"])
     print(json.dumps(line), flush=True)
 
 

@@ -243,6 +243,20 @@ int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, 
                      int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream);
 
 /*
+ * Fused training step over a batch of cameras: for every work item (a tile, or a quarter
+ * of a long-list tile, of any camera) the forward of eq. (7), the gradient of the L2
+ * image loss L = sum (C - target)^2, dL/dC = 2 (C - target), and the backward of
+ * Sec. 3.1 run back to back inside one persistent launch, so the image, T and `last`
+ * stay in registers. target [3][n_pixels]. image: optional (NULL) output of C. loss:
+ * optional (NULL) device float to which L is added. Gradient outputs and errors as for
+ * gs_rasterize_bwd (accumulated; zero them first).
+ */
+int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
+                          int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *target,
+                          float *image, float *loss, float *dL_dmean2d, float *dL_dconic,
+                          int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream);
+
+/*
  * Sec. 3.2 and 3.2.1 (eqs. 22-31): from dL/dmu' and dL/dY of each visible splat,
  * dL/dSigma' = -Y dL/dY Y, the mean route of eq. (23) (second row with h), the
  * covariance route through T = J R_cw and dJ/dt, then dL/dmu = R_cw^T dL/dt,
@@ -256,6 +270,30 @@ int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams,
                    int64_t n_splats, const float *dL_dmean2d, const float *dL_dconic,
                    float *dL_dmeans, float *dL_dscales, float *dL_dquats, float *dL_dcampose,
                    void *stream);
+
+/* ------------------------------------------------------------------------ HIP graphs */
+
+/*
+ * A captured sequence of calls, replayable with one launch. Every call above is
+ * capture-safe (no allocation, no host synchronisation, no hipMemset), so a training
+ * step (project, bin_and_sort, zero, fused rasterization, project_bwd) can be captured
+ * once and replayed while the buffers it names stay allocated. The list capacity is fixed
+ * at capture time: read bins->counters[1] after a replay and recapture with larger
+ * buffers if it is set.
+ */
+typedef struct gs_graph gs_graph;
+
+/* Starts capturing `stream` (a non-null hipStream_t) in thread-local mode. */
+int gs_graph_begin(void *stream);
+
+/* Ends the capture of `stream` and instantiates it; *out receives the graph. */
+int gs_graph_end(void *stream, gs_graph **out);
+
+/* Replays the graph on `stream`. */
+int gs_graph_launch(gs_graph *graph, void *stream);
+
+/* Releases the graph. */
+int gs_graph_destroy(gs_graph *graph);
 
 #ifdef __cplusplus
 }

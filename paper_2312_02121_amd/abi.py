@@ -23,7 +23,8 @@ TILE = 16
 EXPORTED = (
     "gs_device_check", "gs_last_hip_error", "gs_last_error_message", "gs_version", "gs_zero", "gs_abi_layout",
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
-    "gs_project_bwd", "gs_l2_grad",
+    "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
+    "gs_graph_destroy",
 )
 
 
@@ -107,6 +108,12 @@ def lib():
         "gs_rasterize_bwd": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "gs_project_bwd": (ctypes.c_int, [_P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
         "gs_l2_grad": (ctypes.c_int, [_P, _P, _I64, _P, _P]),
+        "gs_rasterize_fused_l2": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P,
+                                                 _P]),
+        "gs_graph_begin": (ctypes.c_int, [_P]),
+        "gs_graph_end": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_void_p)]),
+        "gs_graph_launch": (ctypes.c_int, [_P, _P]),
+        "gs_graph_destroy": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -182,3 +189,29 @@ def gs_project_bwd(g: GsGaussians, cams_ptr: int, n_cams: int, splats: GsSplats,
 
 def gs_l2_grad(image: int, target: int, n: int, dL_dimage: int, stream: int):
     _check("gs_l2_grad", lib().gs_l2_grad(image, target, n, dL_dimage, stream))
+
+
+def gs_rasterize_fused_l2(splats: GsSplats, n_splats: int, bins: GsBins, cams_ptr: int, n_cams: int, prm: GsParams,
+                          n_pixels: int, target: int, image: int | None, loss: int | None, d_mean2d: int, d_conic: int,
+                          n_gaussians: int, d_colors: int, d_opac: int, stream: int):
+    _check("gs_rasterize_fused_l2", lib().gs_rasterize_fused_l2(_ref(splats), n_splats, _ref(bins), cams_ptr, n_cams,
+                                                                _ref(prm), n_pixels, target, image, loss, d_mean2d,
+                                                                d_conic, n_gaussians, d_colors, d_opac, stream))
+
+
+def gs_graph_begin(stream: int):
+    _check("gs_graph_begin", lib().gs_graph_begin(stream))
+
+
+def gs_graph_end(stream: int) -> int:
+    out = ctypes.c_void_p()
+    _check("gs_graph_end", lib().gs_graph_end(stream, ctypes.byref(out)))
+    return out.value
+
+
+def gs_graph_launch(graph: int, stream: int):
+    _check("gs_graph_launch", lib().gs_graph_launch(graph, stream))
+
+
+def gs_graph_destroy(graph: int):
+    _check("gs_graph_destroy", lib().gs_graph_destroy(graph))

@@ -134,26 +134,42 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
 
 // ----------------------------------------------------------------------------- forward
 
-// Per-pixel state is kept arithmetic so that every select depends on a single compare and no
-// lane masks need combining: a skipped splat gets alpha = 0 (a no-op update), and a finished
-// pixel carries T < 0 with |T| its final transmittance.
-template <int PX, bool kVisited>
-__device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
-                                const ItemPixels &t, const gs_params &prm, int64_t n_pixels,
-                                float *__restrict__ image, float *__restrict__ T_out, int32_t *__restrict__ last_out,
-                                int32_t *__restrict__ visited_out)
-{
-    const double pyd = (double)t.row + 0.5;
+// Per-pixel state of a work item. It is kept arithmetic so that every select depends on a
+// single compare and no lane masks need combining: a skipped splat gets alpha = 0 (a no-op
+// update), and during the forward walk a finished pixel carries T < 0 with |T| its final
+// transmittance.
+template <int PX>
+struct PixState {
+    double pyd;
     double pxd[PX];
     float T[PX], c0[PX], c1[PX], c2[PX];
     int last[PX], vis[PX];
+};
+
+template <int PX>
+__device__ inline bool pixel_inside(const ItemPixels &t, int q)
+{
+    return t.row < t.H && t.col0 + q < t.W;
+}
+
+template <int PX>
+__device__ inline void init_state(const ItemPixels &t, PixState<PX> &ps)
+{
+    ps.pyd = (double)t.row + 0.5;
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
-        pxd[q] = (double)(t.col0 + q) + 0.5;
-        T[q] = (t.row < t.H && t.col0 + q < t.W) ? 1.f : -1.f;
-        c0[q] = c1[q] = c2[q] = 0.f;
-        last[q] = vis[q] = 0;
+        ps.pxd[q] = (double)(t.col0 + q) + 0.5;
+        ps.T[q] = pixel_inside<PX>(t, q) ? 1.f : -1.f;
+        ps.c0[q] = ps.c1[q] = ps.c2[q] = 0.f;
+        ps.last[q] = ps.vis[q] = 0;
     }
+}
+
+// Front-to-back walk of the item's list (eq. 7). On return T holds |T_final|.
+template <int PX, bool kVisited>
+__device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
+                                const gs_params &prm, PixState<PX> &ps)
+{
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
     Gathered next = gather(rr, ids, t.start, min(kBatch, t.end - t.start), lane);
@@ -161,78 +177,42 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
         const int nb = min(kBatch, t.end - b);
         stage(slice, next, lane);
         if (b + kBatch < t.end) next = gather(rr, ids, b + kBatch, min(kBatch, t.end - b - kBatch), lane);
-        float tmax = T[0];
+        float tmax = ps.T[0];
 #pragma unroll
-        for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, T[q]);
+        for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
         if (__ballot(tmax >= 0.f) == 0) break;          // every pixel of the item is finished
         for (int j = 0; j < nb; ++j) {
             if ((j & 7) == 7) {
-                float m = T[0];
+                float m = ps.T[0];
 #pragma unroll
-                for (int q = 1; q < PX; ++q) m = fmaxf(m, T[q]);
+                for (int q = 1; q < PX; ++q) m = fmaxf(m, ps.T[q]);
                 if (__ballot(m >= 0.f) == 0) break;
             }
             const RasterRec r = slice[j];
-            const double dy = (double)r.my - pyd;
+            const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
             const int pos1 = b + j - t.start + 1;
 #pragma unroll
             for (int q = 0; q < PX; ++q) {
-                const double dx = (double)r.mx - pxd[q];
+                const double dx = (double)r.mx - ps.pxd[q];
                 float a = fminf(prm.alpha_max, alpha_raw(r, dx, bdy, cdl));
                 a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
-                if (kVisited) vis[q] += T[q] >= 0.f ? 1 : 0;
-                const float Tn = T[q] * (1.f - a);
+                if (kVisited) ps.vis[q] += ps.T[q] >= 0.f ? 1 : 0;
+                const float Tn = ps.T[q] * (1.f - a);
                 const bool stop = Tn < prm.T_min;                // also true once finished (T < 0)
-                const float w = stop ? 0.f : a * T[q];
-                c0[q] = __builtin_fmaf(r.c0, w, c0[q]);
-                c1[q] = __builtin_fmaf(r.c1, w, c1[q]);
-                c2[q] = __builtin_fmaf(r.c2, w, c2[q]);
-                last[q] = w > 0.f ? pos1 : last[q];
-                T[q] = stop ? -fabsf(T[q]) : Tn;
+                const float w = stop ? 0.f : a * ps.T[q];
+                ps.c0[q] = __builtin_fmaf(r.c0, w, ps.c0[q]);
+                ps.c1[q] = __builtin_fmaf(r.c1, w, ps.c1[q]);
+                ps.c2[q] = __builtin_fmaf(r.c2, w, ps.c2[q]);
+                ps.last[q] = w > 0.f ? pos1 : ps.last[q];
+                ps.T[q] = stop ? -fabsf(ps.T[q]) : Tn;
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < PX; ++q) {
-        if (t.row < t.H && t.col0 + q < t.W) {
-            const int64_t pix = t.pix0 + q;
-            image[pix] = c0[q];
-            image[n_pixels + pix] = c1[q];
-            image[2 * n_pixels + pix] = c2[q];
-            T_out[pix] = fabsf(T[q]);
-            last_out[pix] = last[q];
-            if (kVisited) visited_out[pix] = vis[q];
-        }
-    }
+    for (int q = 0; q < PX; ++q) ps.T[q] = fabsf(ps.T[q]);
 }
-
-template <bool kVisited>
-__global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
-    const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, int64_t n_pixels,
-    float *__restrict__ image, float *__restrict__ T_out, int32_t *__restrict__ last_out,
-    int32_t *__restrict__ visited_out)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
-    for (;;) {
-        const int item = next_item(sched, kSchedFwd, n_items, lane);
-        if (item < 0) break;
-        if (item & 4) {
-            __builtin_amdgcn_s_setprio(2);
-            fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, n_pixels, image,
-                                  T_out, last_out, visited_out);
-            __builtin_amdgcn_s_setprio(0);
-        } else {
-            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, n_pixels, image,
-                                  T_out, last_out, visited_out);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------- backward
 
 __device__ inline int wave_max(int v)
 {
@@ -246,36 +226,23 @@ struct BwdOut {
     float *d_mean2d, *d_conic, *d_colors, *d_opac;
 };
 
+// Back-to-front walk (Sec. 3.1). On entry T holds T_final, last the start positions and
+// g0..g2 the upstream gradient dL/dC of each pixel.
 template <int PX>
-__device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
-                                const ItemPixels &t, const gs_params &prm, int64_t n_pixels,
-                                const float *__restrict__ dL_dimage, const float *__restrict__ T_final,
-                                const int32_t *__restrict__ last_in, const BwdOut &out, int lane)
+__device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
+                                const gs_params &prm, const PixState<PX> &ps, float (&T)[PX],
+                                const float (&g0)[PX], const float (&g1)[PX], const float (&g2)[PX],
+                                const BwdOut &out)
 {
-    const double pyd = (double)t.row + 0.5;
-    double pxd[PX];
-    float T[PX], gS[PX], g0[PX], g1[PX], g2[PX];
-    int last[PX];
+    const int lane = threadIdx.x & (kWave - 1);
     int maxlast = 0;
 #pragma unroll
-    for (int q = 0; q < PX; ++q) {
-        pxd[q] = (double)(t.col0 + q) + 0.5;
-        gS[q] = 0.f;
-        T[q] = 1.f;
-        g0[q] = g1[q] = g2[q] = 0.f;
-        last[q] = 0;
-        if (t.row < t.H && t.col0 + q < t.W) {
-            const int64_t pix = t.pix0 + q;
-            T[q] = T_final[pix];
-            last[q] = last_in[pix];
-            g0[q] = dL_dimage[pix];
-            g1[q] = dL_dimage[n_pixels + pix];
-            g2[q] = dL_dimage[2 * n_pixels + pix];
-        }
-        maxlast = max(maxlast, last[q]);
-    }
+    for (int q = 0; q < PX; ++q) maxlast = max(maxlast, ps.last[q]);
     maxlast = __builtin_amdgcn_readfirstlane(wave_max(maxlast));
     if (maxlast == 0) return;
+    float gS[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) gS[q] = 0.f;
     const float kInvLog2e = (float)(1.0 / kLog2eD);
     RasterRec *slice = wave_slice();
     const int kend = t.start + maxlast;
@@ -293,7 +260,7 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
             const int pos = bstart + j - t.start;
             const RasterRec r = slice[j];
             const int id = r.pad;
-            const double dy = (double)r.my - pyd;
+            const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
             const float dyf = (float)dy;
@@ -304,10 +271,10 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
             for (int q = 0; q < PX; ++q) {
                 // inactive (past `last`) or skipped pairs get alpha = 0: then rcp(1 - alpha) = 1,
                 // w = 0 and v = 0, and the pair changes nothing
-                const double dx = (double)r.mx - pxd[q];
+                const double dx = (double)r.mx - ps.pxd[q];
                 const float a_raw = alpha_raw(r, dx, bdy, cdl);
                 float a = fminf(prm.alpha_max, a_raw);
-                a = pos < last[q] ? a : 0.f;
+                a = pos < ps.last[q] ? a : 0.f;
                 a = a < prm.alpha_min ? 0.f : a;
                 live_sum += a;
                 const float rinv = __builtin_amdgcn_rcpf(1.f - a);
@@ -357,11 +324,87 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
     }
 }
 
+// ----------------------------------------------------------------------------- kernels
+
+struct FwdOut {
+    int64_t n_pixels;
+    float *image, *T_out;
+    int32_t *last_out, *visited_out;
+};
+
+template <int PX, bool kVisited>
+__device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
+                                const ItemPixels &t, const gs_params &prm, const FwdOut &o)
+{
+    PixState<PX> ps;
+    init_state<PX>(t, ps);
+    fwd_walk<PX, kVisited>(rr, ids, t, prm, ps);
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        if (pixel_inside<PX>(t, q)) {
+            const int64_t pix = t.pix0 + q;
+            o.image[pix] = ps.c0[q];
+            o.image[o.n_pixels + pix] = ps.c1[q];
+            o.image[2 * o.n_pixels + pix] = ps.c2[q];
+            o.T_out[pix] = ps.T[q];
+            o.last_out[pix] = ps.last[q];
+            if (kVisited) o.visited_out[pix] = ps.vis[q];
+        }
+    }
+}
+
+template <bool kVisited>
+__global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
+    const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    for (;;) {
+        const int item = next_item(sched, kSchedFwd, n_items, lane);
+        if (item < 0) break;
+        if (item & 4) {
+            __builtin_amdgcn_s_setprio(2);
+            fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o);
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o);
+        }
+    }
+}
+
+struct BwdIn {
+    int64_t n_pixels;
+    const float *dL_dimage, *T_final;
+    const int32_t *last_in;
+};
+
+template <int PX>
+__device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
+                                const ItemPixels &t, const gs_params &prm, const BwdIn &in, const BwdOut &out)
+{
+    PixState<PX> ps;
+    init_state<PX>(t, ps);
+    float T[PX], g0[PX], g1[PX], g2[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        T[q] = 1.f;
+        g0[q] = g1[q] = g2[q] = 0.f;
+        if (pixel_inside<PX>(t, q)) {
+            const int64_t pix = t.pix0 + q;
+            T[q] = in.T_final[pix];
+            ps.last[q] = in.last_in[pix];
+            g0[q] = in.dL_dimage[pix];
+            g1[q] = in.dL_dimage[in.n_pixels + pix];
+            g2[q] = in.dL_dimage[2 * in.n_pixels + pix];
+        }
+    }
+    bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
+}
+
 __global__ __launch_bounds__(kWave * kBlockWaves) void raster_bwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, int64_t n_pixels,
-    const float *__restrict__ dL_dimage, const float *__restrict__ T_final, const int32_t *__restrict__ last_in,
-    BwdOut out)
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
@@ -370,12 +413,76 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_bwd_kernel(
         if (item < 0) break;
         if (item & 4) {
             __builtin_amdgcn_s_setprio(2);
-            bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, n_pixels, dL_dimage, T_final,
-                        last_in, out, lane);
+            bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, n_pixels, dL_dimage, T_final,
-                        last_in, out, lane);
+            bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
+        }
+    }
+}
+
+// Fused training step of one item: forward, dL/dC = 2 (C - target) in registers, backward.
+struct FusedIO {
+    int64_t n_pixels;
+    const float *target;
+    float *image;   // optional
+    float *loss;    // optional, accumulated sum of (C - target)^2
+};
+
+template <int PX>
+__device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
+                                  const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out)
+{
+    PixState<PX> ps;
+    init_state<PX>(t, ps);
+    fwd_walk<PX, false>(rr, ids, t, prm, ps);
+    float g0[PX], g1[PX], g2[PX];
+    float l2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        g0[q] = g1[q] = g2[q] = 0.f;
+        if (pixel_inside<PX>(t, q)) {
+            const int64_t pix = t.pix0 + q;
+            const float d0 = ps.c0[q] - io.target[pix];
+            const float d1 = ps.c1[q] - io.target[io.n_pixels + pix];
+            const float d2 = ps.c2[q] - io.target[2 * io.n_pixels + pix];
+            g0[q] = 2.f * d0;
+            g1[q] = 2.f * d1;
+            g2[q] = 2.f * d2;
+            l2 += d0 * d0 + d1 * d1 + d2 * d2;
+            if (io.image) {
+                io.image[pix] = ps.c0[q];
+                io.image[io.n_pixels + pix] = ps.c1[q];
+                io.image[2 * io.n_pixels + pix] = ps.c2[q];
+            }
+        }
+    }
+    if (io.loss) {
+        l2 = wave_sum_to_lane63(l2);
+        if ((threadIdx.x & (kWave - 1)) == kWave - 1) atomic_add_f32(io.loss, l2);
+    }
+    float T[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) T[q] = ps.T[q];
+    bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
+}
+
+__global__ __launch_bounds__(kWave * kBlockWaves) void raster_fused_kernel(
+    const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FusedIO io,
+    BwdOut out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    for (;;) {
+        const int item = next_item(sched, kSchedFused, n_items, lane);
+        if (item < 0) break;
+        if (item & 4) {
+            __builtin_amdgcn_s_setprio(2);
+            fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out);
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out);
         }
     }
 }
@@ -405,15 +512,25 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     if (bins->n_tiles == 0) return GS_OK;
     // every tile is on the work list, empty ones included, so each pixel is written exactly once
     const dim3 grid(persistent_blocks(kBlockWaves)), block(kWave * kBlockWaves);
+    const FwdOut o{n_pixels, image, T_final, last, visited};
     if (visited)
         hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, n_pixels, image, T_final,
-                           last, visited);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o);
     else
         hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, n_pixels, image, T_final,
-                           last, (int32_t *)nullptr);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o);
     return check_launch("gs_rasterize_fwd");
+}
+
+static int check_bwd_outputs(const gs_splats *s, int64_t n_splats, const gs_params *prm, float *dL_dmean2d,
+                             float *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac)
+{
+    if (!dL_dmean2d || !dL_dconic || !dL_dcolors || !dL_dopac || n_splats < 0 || n_splats > s->capacity ||
+        n_gaussians < 1)
+        return set_error(GS_ERR_INVALID, "rasterize backward: null gradient buffer or bad size");
+    if (!(prm->alpha_max < 1.0f))
+        return set_error(GS_ERR_INVALID, "rasterize backward: alpha_max must be below 1 (eq. 17 divides by 1 - alpha)");
+    return GS_OK;
 }
 
 extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
@@ -424,15 +541,35 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     clear_error();
     int rc = check_raster_args(s, bins, cams, n_cams, prm, n_pixels);
     if (rc != GS_OK) return rc;
-    if (!dL_dimage || !T_final || !last || !dL_dmean2d || !dL_dconic || !dL_dcolors || !dL_dopac ||
-        n_splats < 0 || n_splats > s->capacity || n_gaussians < 1)
-        return set_error(GS_ERR_INVALID, "gs_rasterize_bwd: null argument or bad size");
-    if (!(prm->alpha_max < 1.0f))
-        return set_error(GS_ERR_INVALID, "gs_rasterize_bwd: alpha_max must be below 1 (eq. 17 divides by 1 - alpha)");
+    if (!dL_dimage || !T_final || !last) return set_error(GS_ERR_INVALID, "gs_rasterize_bwd: null input");
+    rc = check_bwd_outputs(s, n_splats, prm, dL_dmean2d, dL_dconic, n_gaussians, dL_dcolors, dL_dopac);
+    if (rc != GS_OK) return rc;
     if (bins->n_tiles == 0) return GS_OK;
+    const BwdIn in{n_pixels, dL_dimage, T_final, last};
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, n_pixels, dL_dimage, T_final, last, out);
+                       (int)n_cams, *prm, in, out);
     return check_launch("gs_rasterize_bwd");
+}
+
+extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *bins,
+                                     const gs_camera *cams, int32_t n_cams, const gs_params *prm, int64_t n_pixels,
+                                     const float *target, float *image, float *loss, float *dL_dmean2d,
+                                     float *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac,
+                                     void *stream)
+{
+    clear_error();
+    int rc = check_raster_args(s, bins, cams, n_cams, prm, n_pixels);
+    if (rc != GS_OK) return rc;
+    if (!target) return set_error(GS_ERR_INVALID, "gs_rasterize_fused_l2: null target");
+    rc = check_bwd_outputs(s, n_splats, prm, dL_dmean2d, dL_dconic, n_gaussians, dL_dcolors, dL_dopac);
+    if (rc != GS_OK) return rc;
+    if (bins->n_tiles == 0) return GS_OK;
+    const FusedIO io{n_pixels, target, image, loss};
+    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
+    hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
+                       (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
+                       (int)n_cams, *prm, io, out);
+    return check_launch("gs_rasterize_fused_l2");
 }

@@ -3,6 +3,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <new>
+
 #include "common.h"
 
 namespace gsx {
@@ -151,4 +153,61 @@ extern "C" int gs_l2_grad(const float *image, const float *target, int64_t n, fl
                        (const float4 *)image, (const float4 *)target, n4, (float4 *)dL_dimage, image + 4 * n4,
                        target + 4 * n4, dL_dimage + 4 * n4, tail);
     return check_launch("gs_l2_grad");
+}
+
+// ------------------------------------------------------------------------- HIP graphs
+
+struct gs_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" int gs_graph_begin(void *stream)
+{
+    clear_error();
+    if (!stream) return set_error(GS_ERR_INVALID, "gs_graph_begin: capture needs a non-null stream");
+    return check_hip(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal),
+                     "hipStreamBeginCapture");
+}
+
+extern "C" int gs_graph_end(void *stream, gs_graph **out)
+{
+    clear_error();
+    if (!stream || !out) return set_error(GS_ERR_INVALID, "gs_graph_end: null argument");
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    int rc = check_hip(hipStreamEndCapture((hipStream_t)stream, &g), "hipStreamEndCapture");
+    if (rc != GS_OK) return rc;
+    hipGraphExec_t e = nullptr;
+    rc = check_hip(hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (rc != GS_OK) {
+        (void)hipGraphDestroy(g);
+        return rc;
+    }
+    gs_graph *h = new (std::nothrow) gs_graph{g, e};
+    if (!h) {
+        (void)hipGraphExecDestroy(e);
+        (void)hipGraphDestroy(g);
+        return set_error(GS_ERR_INVALID, "gs_graph_end: out of host memory");
+    }
+    *out = h;
+    return GS_OK;
+}
+
+extern "C" int gs_graph_launch(gs_graph *graph, void *stream)
+{
+    clear_error();
+    if (!graph) return set_error(GS_ERR_INVALID, "gs_graph_launch: null graph");
+    return check_hip(hipGraphLaunch(graph->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+extern "C" int gs_graph_destroy(gs_graph *graph)
+{
+    clear_error();
+    if (!graph) return GS_OK;
+    const hipError_t e1 = hipGraphExecDestroy(graph->exec);
+    const hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    const int rc = check_hip(e1, "hipGraphExecDestroy");
+    return rc != GS_OK ? rc : check_hip(e2, "hipGraphDestroy");
 }

@@ -283,15 +283,23 @@ class TrainStep:
     """One step of fwd + L2 loss gradient + bwd over a fixed camera set, with every
     buffer preallocated, so the step allocates nothing and can be timed or captured.
 
-    Stages (each a C-ABI call on the current stream):
-      project, bin_and_sort, rasterize_fwd, l2_grad, zero, rasterize_bwd, project_bwd
+    mode "separate": project, bin_and_sort, rasterize_fwd, l2_grad, zero, rasterize_bwd,
+                     project_bwd (the image, T and last round-trip through HBM)
+    mode "fused":    project, bin_and_sort, zero, fused (fwd + L2 + bwd per work item),
+                     project_bwd
     """
 
-    STAGES = ("project", "bin_and_sort", "rasterize_fwd", "l2_grad", "zero_grads", "rasterize_bwd", "project_bwd")
+    STAGE_SETS = {
+        "separate": ("project", "bin_and_sort", "rasterize_fwd", "l2_grad", "zero_grads", "rasterize_bwd",
+                     "project_bwd"),
+        "fused": ("project", "bin_and_sort", "zero_grads", "fused", "project_bwd"),
+    }
 
     def __init__(self, g: GaussianSet, cams: CameraSet, targets: torch.Tensor, params: abi.GsParams | None = None,
-                 capacity: int | None = None, capacity_margin: float = 1.25):
-        self.g, self.cams = g, cams
+                 capacity: int | None = None, capacity_margin: float = 1.25, mode: str = "separate",
+                 keep_image: bool = True, scene_grads: "TrainStep | None" = None):
+        self.g, self.cams, self.mode = g, cams, mode
+        self.STAGES = self.STAGE_SETS[mode]
         self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True)
         self.targets = targets.contiguous().view(3, -1).to(torch.float32)
         assert self.targets.shape[1] == cams.n_pixels
@@ -306,18 +314,40 @@ class TrainStep:
         self.E_bwd = int(self.r.last.sum())        # pairs the backward walks
         self.r.visited = None                      # the timed step does not write it
         P, n = cams.n_splats, g.n
-        sizes = {"mean2d": 2 * max(P, 1), "conic": 3 * max(P, 1), "colors": 3 * n, "opacities": n,
-                 "means": 3 * n, "scales": 3 * n, "quats": 4 * n}
-        total = sum(sizes.values())
-        self.grad_flat = torch.empty(total, dtype=torch.float32, device=cams.device)
+        # per-slot gradients (this camera set only) and per-scene gradients, which another
+        # step may own: then this step accumulates into them and does not zero them
+        P1 = max(P, 1)
+        slot = {"mean2d": (2, P1), "conic": (3, P1)}
+        scene = {"colors": (3, n), "opacities": (n,), "means": (3, n), "scales": (3, n), "quats": (4, n),
+                 "loss": (1,)}
+        numel = lambda sh: int(np.prod(sh))
+        self.slot_flat = torch.empty(sum(numel(v) for v in slot.values()), dtype=torch.float32, device=cams.device)
         self.grads, o = {}, 0
-        for k, sz in sizes.items():
-            self.grads[k] = self.grad_flat[o:o + sz]
-            o += sz
+        for k, sh in slot.items():
+            self.grads[k] = self.slot_flat[o:o + numel(sh)].view(sh)
+            o += numel(sh)
+        self.owns_scene_grads = scene_grads is None
+        if scene_grads is None:
+            self.scene_flat = torch.empty(sum(numel(v) for v in scene.values()), dtype=torch.float32,
+                                          device=cams.device)
+            o = 0
+            for k, sh in scene.items():
+                self.grads[k] = self.scene_flat[o:o + numel(sh)].view(sh)
+                o += numel(sh)
+        else:
+            self.scene_flat = scene_grads.scene_flat
+            for k in scene:
+                self.grads[k] = scene_grads.grads[k]
         self.dL = torch.empty(3, cams.n_pixels, dtype=torch.float32, device=cams.device)
+        self.keep_image = keep_image
+
+    @property
+    def loss(self) -> torch.Tensor:
+        return self.grads["loss"]
 
     def run_stage(self, name: str, stream: int):
         r, cams, g, P = self.r, self.cams, self.g, self.cams.n_splats
+        gr = self.grads
         if name == "project":
             r.project(g, stream)
         elif name == "bin_and_sort":
@@ -327,15 +357,21 @@ class TrainStep:
         elif name == "l2_grad":
             abi.gs_l2_grad(r.image.data_ptr(), self.targets.data_ptr(), r.image.numel(), self.dL.data_ptr(), stream)
         elif name == "zero_grads":
-            abi.gs_zero(self.grad_flat.data_ptr(), self.grad_flat.numel() * 4, stream)
+            abi.gs_zero(self.slot_flat.data_ptr(), self.slot_flat.numel() * 4, stream)
+            if self.owns_scene_grads:
+                abi.gs_zero(self.scene_flat.data_ptr(), self.scene_flat.numel() * 4, stream)
         elif name == "rasterize_bwd":
-            gr = self.grads
             abi.gs_rasterize_bwd(r.splats.struct(P), P, r.bins.struct(), cams.ptr, cams.n_cams, r.params,
                                  cams.n_pixels, self.dL.data_ptr(), r.T_final.data_ptr(), r.last.data_ptr(),
                                  gr["mean2d"].data_ptr(), gr["conic"].data_ptr(), g.n, gr["colors"].data_ptr(),
                                  gr["opacities"].data_ptr(), stream)
+        elif name == "fused":
+            abi.gs_rasterize_fused_l2(r.splats.struct(P), P, r.bins.struct(), cams.ptr, cams.n_cams, r.params,
+                                      cams.n_pixels, self.targets.data_ptr(),
+                                      r.image.data_ptr() if self.keep_image else None, gr["loss"].data_ptr(),
+                                      gr["mean2d"].data_ptr(), gr["conic"].data_ptr(), g.n,
+                                      gr["colors"].data_ptr(), gr["opacities"].data_ptr(), stream)
         elif name == "project_bwd":
-            gr = self.grads
             abi.gs_project_bwd(g.struct(), cams.ptr, cams.n_cams, r.splats.struct(P), P, gr["mean2d"].data_ptr(),
                                gr["conic"].data_ptr(), gr["means"].data_ptr(), gr["scales"].data_ptr(),
                                gr["quats"].data_ptr(), None, stream)
@@ -353,3 +389,62 @@ class TrainStep:
 
     def overflowed(self) -> bool:
         return bool(self.r.bins.counters[1].item())
+
+
+class GraphStep:
+    """A TrainStep captured once into a HIP graph (gs_graph_* of the C ABI) and replayed.
+
+    Capture runs on a private stream of default priority; replays go to the caller's
+    stream. Buffers named by the graph belong to the wrapped TrainStep and stay alive with it.
+    """
+
+    def __init__(self, step: TrainStep):
+        self.step = step
+        self.stream = torch.cuda.Stream()
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            step(stream=self.stream.cuda_stream)          # warm the path outside capture
+            self.stream.synchronize()
+            abi.gs_graph_begin(self.stream.cuda_stream)
+            try:
+                step(stream=self.stream.cuda_stream)
+            finally:
+                self.graph = abi.gs_graph_end(self.stream.cuda_stream)
+        cur.wait_stream(self.stream)
+
+    def __call__(self, stream: int | None = None):
+        abi.gs_graph_launch(self.graph, current_stream() if stream is None else stream)
+
+    def __del__(self):
+        g = getattr(self, "graph", None)
+        if g:
+            try:
+                abi.gs_graph_destroy(g)
+            except Exception:
+                pass
+            self.graph = None
+
+
+class PerViewSteps:
+    """The same step run one camera at a time (one CameraSet per view), no graph: the
+    one-view-per-launch baseline for the batched form."""
+
+    def __init__(self, g: GaussianSet, cameras: Sequence, targets: Sequence[torch.Tensor],
+                 params: abi.GsParams | None = None, mode: str = "separate"):
+        self.steps = []
+        for c, t in zip(cameras, targets):
+            cs = CameraSet([c], g.sizes)
+            first = self.steps[0] if self.steps else None
+            self.steps.append(TrainStep(g, cs, t, params, mode=mode, scene_grads=first))
+        self.E_fwd = sum(s.E_fwd for s in self.steps)
+        self.E_bwd = sum(s.E_bwd for s in self.steps)
+        self.K = sum(s.K for s in self.steps)
+        self.grads = self.steps[0].grads
+
+    def __call__(self, stream: int | None = None):
+        for s in self.steps:
+            s(stream)
+
+    def overflowed(self) -> bool:
+        return any(s.overflowed() for s in self.steps)
