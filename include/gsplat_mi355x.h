@@ -192,22 +192,26 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
 
 /*
  * Sec. 2.2: duplicate each splat once per tile of its box, sort the entries by
- * (tile, depth) with a stable LSD radix sort (ties keep splat order), and find each
- * tile's [start, end), then write the rasterizer's work list (tiles in decreasing list
- * length, long ones split into four parts). K is written to bins->counters[0]; if K exceeds
- * bins->capacity only the first `capacity` entries (in splat order) are emitted,
- * counters[1] is set to 1 and the list is incomplete: the caller reads the flag,
- * regrows and calls again. workspace: device memory of at least
- * gs_bin_and_sort_workspace_size() bytes. cams: as for gs_project.
- * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1]),
- * GS_ERR_CAPACITY (workspace too small).
+ * (tile, depth) with ties in splat order -- the order of one stable LSD radix sort of the
+ * 64-bit keys -- and find each tile's [start, end), then write the rasterizer's work list
+ * (tiles in decreasing list length, long ones split into four parts). The sort is done as
+ * a stable depth sort of the splats followed by a stable tile-id sort of the entries
+ * emitted in depth order, which yields the same list. K is written to
+ * bins->counters[0]; if K exceeds bins->capacity only the first `capacity` entries (in
+ * depth order of their splats) are kept, counters[1] is set to 1 and the list is
+ * incomplete: the caller reads the flag, regrows and calls again. workspace: device
+ * memory of at least gs_bin_and_sort_workspace_size() bytes, contents free on entry and
+ * exit. cams: as for gs_project.
+ * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1], n_splats outside
+ * [0, 2^31 - 1]), GS_ERR_CAPACITY (workspace too small).
  */
 int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
                     gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Sec. 2.2, eq. (7): per pixel, composite its tile's list front to back with online
- * transmittance. One workgroup per 16x16 tile.
+ * transmittance. A persistent launch takes work items (whole 16x16 tiles, or 16x4 quarters
+ * of long-list tiles) from the work list gs_bin_and_sort wrote, longest first.
  * Outputs over the packed pixels of all cameras (n_pixels = sum of width * height):
  *   image   [3][n_pixels]  C
  *   T_final [n_pixels]     T after the last composited entry

@@ -1,17 +1,33 @@
 // gs_bin_and_sort: tile binning and per-tile depth order (Sec. 2.2).
 //
-//   1. exclusive scan of tiles_touched (int64) -> emit offsets, K = total
-//   2. emit: each visible splat writes (global tile << 32 | depth bits, slot) for every
-//      tile of its box, row-major, at its scan offset (entries beyond capacity are dropped
-//      and the overflow flag is raised)
-//   3. stable LSD radix sort over the low 32 + ceil(log2(n_tiles)) key bits; each pass is
-//      a per-block digit histogram, a scan of the digit-major histogram table and a
-//      stable scatter. Block ranking uses wave ballots to group equal digits and LDS
-//      counters per (wave, digit), so no LDS atomics contend on popular digits.
-//   4. ranges: [start, end) of each tile's run.
+// The result is the list of (tile, depth, splat) entries sorted by the 64-bit key
+// (global tile << 32) | float32 depth bits, equal keys in splat order -- the order a single
+// stable LSD radix sort of those 64-bit keys produces. It is computed as two stable
+// LDS-histogram radix sorts whose traffic does not grow with the 32 depth bits per entry:
 //
-// Every kernel is sized from host-known capacities and reads K from device memory, so
-// the whole sequence replays unchanged inside a captured HIP graph.
+//   1. depth sort of the P splats: 32-bit keys (float bits of t_z, culled splats last),
+//      values = splat slot; four 8-bit passes over P keys. Ties keep slot order.
+//   2. exclusive scan of tiles_touched in depth-rank order -> per-splat emit offsets and
+//      K = total intersections (an overflow flag is raised when K exceeds the capacity).
+//   3. emit in depth-rank order: each splat writes (global tile id, slot) for every tile of
+//      its box, row-major. A lane emits its own splat when the box is small; splats with
+//      large boxes (near the camera they can cover the whole image) are written by the
+//      whole wave together, so one splat never serialises a thread over thousands of tiles.
+//   4. stable sort of the K entries by tile id alone: ceil(log2(n_tiles) / 8) 8-bit passes
+//      (two for 1920x1080 or 1280x720). Being stable, it keeps the depth-rank order inside
+//      every tile. The last pass writes the splat slots to bins->ids and the 64-bit keys
+//      (tile << 32 | depth bits of the slot) to bins->keys.
+//   5. ranges: [start, end) of each tile's run; then the rasterizer's work list.
+//
+// Per entry this moves ~40 bytes where six 8-bit passes over 64-bit keys move ~190; for
+// views with near-plane splats (hundreds of millions of entries) the sort is HBM-bound and
+// the difference is the whole cost.
+//
+// Each pass is a per-block digit histogram, a scan of the digit-major histogram table and
+// a stable scatter. Block ranking uses wave ballots to group equal digits and LDS counters
+// per (wave, digit), so no LDS atomics contend on popular digits. Every kernel is sized
+// from host-known capacities and reads its element count from device memory, so the whole
+// sequence replays unchanged inside a captured HIP graph.
 #include "common.h"
 
 namespace gsx {
@@ -49,15 +65,28 @@ __device__ inline T block_exclusive_scan(T v, T *total)
     return before + incl - v;
 }
 
-template <typename TIn, typename TAcc>
-__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const TIn *__restrict__ in, int64_t n,
-                                                                 TAcc *__restrict__ sums)
+// The scans read their input through a loader: load(i) returns element i (i < n).
+template <typename T>
+struct ArrayLoad {
+    const T *p;
+    __device__ T operator()(int64_t i) const { return p[i]; }
+};
+
+// tiles_touched of the splat at depth rank i
+struct RankTiles {
+    const int32_t *tiles;
+    const int32_t *rank_ids;
+    __device__ int64_t operator()(int64_t i) const { return tiles[rank_ids[i]]; }
+};
+
+template <typename Load, typename TAcc>
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(Load in, int64_t n, TAcc *__restrict__ sums)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     TAcc acc = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) acc += (TAcc)in[base + k];
+        if (base + k < n) acc += (TAcc)in(base + k);
     TAcc tot;
     block_exclusive_scan<TAcc>(acc, &tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -85,69 +114,41 @@ __global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(TAcc *__restrict_
     }
 }
 
-template <typename TIn, typename TAcc, typename TOut>
-__global__ __launch_bounds__(kScanBlock) void scan_down_kernel(const TIn *__restrict__ in, int64_t n,
-                                                               const TAcc *__restrict__ sums,
+template <typename Load, typename TAcc, typename TOut>
+__global__ __launch_bounds__(kScanBlock) void scan_down_kernel(Load in, int64_t n, const TAcc *__restrict__ sums,
                                                                TOut *__restrict__ out)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    TIn vals[kScanItems];
+    TAcc vals[kScanItems];
     TAcc acc = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        vals[k] = base + k < n ? in[base + k] : (TIn)0;
-        acc += (TAcc)vals[k];
+        vals[k] = base + k < n ? (TAcc)in(base + k) : (TAcc)0;
+        acc += vals[k];
     }
     TAcc tot;
     TAcc run = block_exclusive_scan<TAcc>(acc, &tot) + sums[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = (TOut)run;
-        run += (TAcc)vals[k];
+        run += vals[k];
     }
 }
 
 static int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 
-// Exclusive scan of n values into out; sums needs scan_blocks(n) entries.
-template <typename TIn, typename TAcc, typename TOut>
-static int scan_exclusive(const TIn *in, int64_t n, TOut *out, TAcc *sums, int64_t *total, int64_t *flag,
-                          int64_t cap, hipStream_t st)
+// Exclusive scan of n loaded values into out; sums needs scan_blocks(n) entries.
+template <typename TAcc, typename TOut, typename Load>
+static int scan_exclusive(Load in, int64_t n, TOut *out, TAcc *sums, int64_t *total, int64_t *flag, int64_t cap,
+                          hipStream_t st)
 {
     const int64_t nb = scan_blocks(n);
     if (nb == 0) return GS_OK;
-    hipLaunchKernelGGL((scan_reduce_kernel<TIn, TAcc>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, sums);
+    hipLaunchKernelGGL((scan_reduce_kernel<Load, TAcc>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, sums);
     hipLaunchKernelGGL((scan_sums_kernel<TAcc>), dim3(1), dim3(kScanBlock), 0, st, sums, nb, total, flag, cap);
-    hipLaunchKernelGGL((scan_down_kernel<TIn, TAcc, TOut>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n,
+    hipLaunchKernelGGL((scan_down_kernel<Load, TAcc, TOut>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n,
                        sums, out);
     return check_launch("scan");
-}
-
-// ------------------------------------------------------------------------------ emit
-
-__global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ tiles, const int64_t *__restrict__ offsets,
-                                                   const int4 *__restrict__ rect, const float *__restrict__ depth,
-                                                   const gs_camera *__restrict__ cams, int n_cams, int64_t n_splats,
-                                                   int64_t cap, uint64_t *__restrict__ keys, int32_t *__restrict__ ids)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_splats) return;
-    const int cnt = tiles[p];
-    if (cnt <= 0) return;
-    int64_t k = offsets[p];
-    if (k >= cap) return;
-    const int c = camera_of_splat(cams, n_cams, p);
-    const int toff = cams[c].tile_offset, tx_n = cams[c].tiles_x;
-    const int4 b = rect[p];
-    const uint64_t dbits = (uint64_t)__float_as_uint(depth[p]);
-    for (int ty = b.y; ty <= b.w; ++ty)
-        for (int tx = b.x; tx <= b.z; ++tx) {
-            if (k >= cap) return;
-            const uint64_t tile = (uint64_t)(toff + ty * tx_n + tx);
-            keys[k] = (tile << 32) | dbits;
-            ids[k] = (int32_t)p;
-            ++k;
-        }
 }
 
 // ------------------------------------------------------------------------ radix sort
@@ -159,9 +160,9 @@ constexpr int kSortChunk = kSortBlock * kSortItems;  // keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-__device__ inline int64_t sort_count(const int64_t *counters, int64_t cap)
+__device__ inline int64_t sort_count(const int64_t *counter, int64_t cap)
 {
-    const int64_t k = counters[0];
+    const int64_t k = *counter;
     return k < cap ? k : cap;
 }
 
@@ -179,8 +180,8 @@ __device__ inline uint64_t match_digit(unsigned digit, uint64_t valid)
 
 // Counts digits of this block's chunk. Wave w owns keys [w*M, (w+1)*M) of the chunk
 // (M = kSortChunk / kSortWaves), walked in order so that ranks are stable.
-__device__ inline void count_digits(const uint64_t (&key)[kSortItems], int64_t chunk_base, int64_t kvalid,
-                                    int shift, unsigned (*cnt)[kRadix])
+__device__ inline void count_digits(const uint32_t (&key)[kSortItems], int64_t chunk_base, int64_t kvalid, int shift,
+                                    unsigned (*cnt)[kRadix])
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
@@ -189,28 +190,28 @@ __device__ inline void count_digits(const uint64_t (&key)[kSortItems], int64_t c
         const bool ok = idx < kvalid;
         const uint64_t valid = __ballot(ok);
         if (valid == 0) break;
-        const unsigned d = (unsigned)(key[r] >> shift) & (kRadix - 1);
+        const unsigned d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         if (ok && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
     }
 }
 
-__global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint64_t *__restrict__ keys,
-                                                                const int64_t *__restrict__ counters, int64_t cap,
+__global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys,
+                                                                const int64_t *__restrict__ count, int64_t cap,
                                                                 int shift, int nblocks, unsigned *__restrict__ hist)
 {
     __shared__ unsigned cnt[kSortWaves][kRadix];
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
     __syncthreads();
-    const int64_t kvalid = sort_count(counters, cap);
+    const int64_t kvalid = sort_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base < kvalid) {
         const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-        uint64_t key[kSortItems];
+        uint32_t key[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-            key[r] = idx < kvalid ? keys[idx] : 0ull;
+            key[r] = idx < kvalid ? keys[idx] : 0u;
         }
         count_digits(key, base, kvalid, shift, cnt);
     }
@@ -224,29 +225,33 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint64_t *
 }
 
 // hist_scan holds, digit-major, the exclusive prefix of the histogram table: the output
-// position of the first key with digit d in block b.
-__global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint64_t *__restrict__ keys_in,
+// position of the first key with digit d in block b. When keys64_out is set (the last tile
+// pass), the scatter writes the 64-bit output key (tile << 32 | depth bits of the value)
+// there instead of the 32-bit key.
+__global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
                                                                    const int32_t *__restrict__ vals_in,
-                                                                   const int64_t *__restrict__ counters, int64_t cap,
+                                                                   const int64_t *__restrict__ count, int64_t cap,
                                                                    int shift, int nblocks,
                                                                    const unsigned *__restrict__ hist_scan,
-                                                                   uint64_t *__restrict__ keys_out,
-                                                                   int32_t *__restrict__ vals_out)
+                                                                   uint32_t *__restrict__ keys_out,
+                                                                   int32_t *__restrict__ vals_out,
+                                                                   uint64_t *__restrict__ keys64_out,
+                                                                   const float *__restrict__ depth)
 {
     __shared__ unsigned cnt[kSortWaves][kRadix];
-    const int64_t kvalid = sort_count(counters, cap);
+    const int64_t kvalid = sort_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base >= kvalid) return;   // uniform over the block
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint64_t key[kSortItems];
+    uint32_t key[kSortItems];
     int32_t val[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
         const bool ok = idx < kvalid;
-        key[r] = ok ? keys_in[idx] : 0ull;
+        key[r] = ok ? keys_in[idx] : 0u;
         val[r] = ok ? vals_in[idx] : 0;
     }
     count_digits(key, base, kvalid, shift, cnt);
@@ -268,16 +273,96 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint64_
         const bool ok = idx < kvalid;
         const uint64_t valid = __ballot(ok);
         if (valid == 0) break;
-        const unsigned d = (unsigned)(key[r] >> shift) & (kRadix - 1);
+        const unsigned d = (key[r] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         const unsigned pos = cnt[wave][d] + (unsigned)__popcll(peers & lanemask_lt());
         __builtin_amdgcn_wave_barrier();
         if (ok && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
         if (ok) {
-            keys_out[pos] = key[r];
             vals_out[pos] = val[r];
+            if (keys64_out)
+                keys64_out[pos] = ((uint64_t)key[r] << 32) | (uint64_t)__float_as_uint(depth[val[r]]);
+            else
+                keys_out[pos] = key[r];
         }
+    }
+}
+
+// ------------------------------------------------------------------- depth order, emit
+
+// Depth keys of every splat: float bits of t_z (positive, so bit order is value order);
+// culled splats get 0xffffffff and sort last. Thread 0 also stores the key count.
+__global__ __launch_bounds__(256) void depth_keys_kernel(const int32_t *__restrict__ tiles,
+                                                         const float *__restrict__ depth, int64_t n,
+                                                         uint32_t *__restrict__ dkey, int32_t *__restrict__ dval,
+                                                         int64_t *__restrict__ count)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *count = n;
+    if (p >= n) return;
+    dkey[p] = tiles[p] > 0 ? __float_as_uint(depth[p]) : 0xffffffffu;
+    dval[p] = (int32_t)p;
+}
+
+// Splats whose box has at most this many tiles are emitted by their own lane.
+constexpr int kEmitLaneMax = 16;
+
+__device__ inline void emit_tiles(int64_t k0, int count_begin, int count_step, int n_tiles_box, const int4 &b,
+                                  int toff, int tx_n, int32_t slot, int64_t cap, uint32_t *__restrict__ tkey,
+                                  int32_t *__restrict__ tval)
+{
+    const int w = b.z - b.x + 1;
+    for (int j = count_begin; j < n_tiles_box; j += count_step) {
+        const int64_t k = k0 + j;
+        if (k >= cap) break;
+        const int ty = b.y + j / w, tx = b.x + j % w;
+        tkey[k] = (uint32_t)(toff + ty * tx_n + tx);
+        tval[k] = slot;
+    }
+}
+
+// One thread per depth rank. Entries are written at the rank's scan offset, row-major over
+// the box; entries beyond the capacity are dropped (the overflow flag is already set).
+__global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ rank_ids,
+                                                   const int64_t *__restrict__ offsets,
+                                                   const int32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                                                   const gs_camera *__restrict__ cams, int n_cams, int64_t n_splats,
+                                                   int64_t cap, uint32_t *__restrict__ tkey,
+                                                   int32_t *__restrict__ tval)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t slot = 0;
+    int cnt = 0;
+    int64_t k0 = 0;
+    if (r < n_splats) {
+        slot = rank_ids[r];
+        cnt = tiles[slot];
+        k0 = offsets[r];
+        if (k0 >= cap) cnt = 0;
+    }
+    int toff = 0, tx_n = 1;
+    int4 b = make_int4(0, 0, 0, 0);
+    if (cnt > 0) {
+        const int c = camera_of_splat(cams, n_cams, slot);
+        toff = cams[c].tile_offset;
+        tx_n = cams[c].tiles_x;
+        b = rect[slot];
+    }
+    if (cnt > 0 && cnt <= kEmitLaneMax) emit_tiles(k0, 0, 1, cnt, b, toff, tx_n, slot, cap, tkey, tval);
+    // large boxes: the whole wave writes them, one splat at a time
+    uint64_t big = __ballot(cnt > kEmitLaneMax);
+    while (big) {
+        const int src = __builtin_ctzll(big);
+        big &= big - 1;
+        const int bcnt = __shfl(cnt, src, kWave);
+        const int64_t bk0 = __shfl(k0, src, kWave);
+        const int32_t bslot = __shfl(slot, src, kWave);
+        const int btoff = __shfl(toff, src, kWave), btx = __shfl(tx_n, src, kWave);
+        const int4 bb = make_int4(__shfl(b.x, src, kWave), __shfl(b.y, src, kWave), __shfl(b.z, src, kWave),
+                                  __shfl(b.w, src, kWave));
+        emit_tiles(bk0, lane, kWave, bcnt, bb, btoff, btx, bslot, cap, tkey, tval);
     }
 }
 
@@ -374,9 +459,13 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 
 // ------------------------------------------------------------------------ workspace
 
+// Workspace: depth-sort buffers (two key/value pairs over P splats), per-rank emit offsets,
+// scan partial sums, one 32-bit key/value pair over the capacity (the other pair of the
+// tile-sort ping-pong lives in bins->keys / bins->ids until the last pass overwrites them),
+// and the radix histogram table.
 struct BinLayout {
-    size_t offsets, scan_sums, keys_alt, vals_alt, hist, hist_sums, total;
-    int64_t scan_nb, sort_nb, hist_n;
+    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, scan_sums, tkey, tval, hist, hist_sums, total;
+    int64_t depth_nb, tile_nb, hist_n;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -384,25 +473,47 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static BinLayout bin_layout(int64_t n_splats, int64_t cap)
 {
     BinLayout L{};
-    L.scan_nb = scan_blocks(n_splats);
-    L.sort_nb = (cap + kSortChunk - 1) / kSortChunk;
-    L.hist_n = L.sort_nb * kRadix;
+    L.depth_nb = (n_splats + kSortChunk - 1) / kSortChunk;
+    L.tile_nb = (cap + kSortChunk - 1) / kSortChunk;
+    L.hist_n = (L.depth_nb > L.tile_nb ? L.depth_nb : L.tile_nb) * kRadix;
+    const size_t p4 = align256((size_t)n_splats * 4);
     size_t o = 0;
+    L.dkeyA = o;     o += p4;
+    L.dvalA = o;     o += p4;
+    L.dkeyB = o;     o += p4;
+    L.dvalB = o;     o += p4;
+    L.dcount = o;    o += 256;
     L.offsets = o;   o += align256((size_t)n_splats * sizeof(int64_t));
-    L.scan_sums = o; o += align256((size_t)(L.scan_nb + 1) * sizeof(int64_t));
-    L.keys_alt = o;  o += align256((size_t)cap * sizeof(uint64_t));
-    L.vals_alt = o;  o += align256((size_t)cap * sizeof(int32_t));
+    L.scan_sums = o; o += align256((size_t)(scan_blocks(n_splats) + 1) * sizeof(int64_t));
+    L.tkey = o;      o += align256((size_t)cap * 4);
+    L.tval = o;      o += align256((size_t)cap * 4);
     L.hist = o;      o += align256((size_t)L.hist_n * sizeof(unsigned));
     L.hist_sums = o; o += align256((size_t)(scan_blocks(L.hist_n) + 1) * sizeof(unsigned));
     L.total = o;
     return L;
 }
 
-static int key_bits(int32_t n_tiles)
+static int tile_bits(int32_t n_tiles)
 {
     int tb = 0;
     while ((1ll << tb) < (int64_t)n_tiles) ++tb;
-    return 32 + tb;
+    return tb;
+}
+
+// One stable LSD pass: histogram, scan of the digit-major table, scatter.
+static int radix_pass(const uint32_t *kin, const int32_t *vin, const int64_t *count, int64_t cap, int shift,
+                      int64_t nb, unsigned *hist, unsigned *hist_sums, uint32_t *kout, int32_t *vout,
+                      uint64_t *keys64, const float *depth, hipStream_t st)
+{
+    if (nb == 0) return GS_OK;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortBlock), 0, st, kin, count, cap, shift,
+                       (int)nb, hist);
+    const int rc = scan_exclusive<unsigned, unsigned>(ArrayLoad<unsigned>{hist}, nb * kRadix, hist, hist_sums,
+                                                      nullptr, nullptr, -1, st);
+    if (rc != GS_OK) return rc;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortBlock), 0, st, kin, vin, count, cap,
+                       shift, (int)nb, hist, kout, vout, keys64, depth);
+    return check_launch("radix pass");
 }
 
 }  // namespace gsx
@@ -438,6 +549,8 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null argument or bad size");
     if (bins->capacity < 1 || bins->capacity > 0x7fffffffll || bins->n_tiles < 1)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: capacity must be in [1, 2^31-1], n_tiles >= 1");
+    if (n_splats > 0x7fffffffll)
+        return set_error(GS_ERR_INVALID, "gs_bin_and_sort: n_splats must be below 2^31");
     if (!bins->keys || !bins->ids || !bins->ranges || !bins->schedule || !bins->counters || !s->rect || !s->depth ||
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
@@ -447,12 +560,14 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort: workspace too small");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
+    uint32_t *dkeyA = (uint32_t *)(ws + L.dkeyA), *dkeyB = (uint32_t *)(ws + L.dkeyB);
+    int32_t *dvalA = (int32_t *)(ws + L.dvalA), *dvalB = (int32_t *)(ws + L.dvalB);
+    int64_t *dcount = (int64_t *)(ws + L.dcount);
     int64_t *offsets = (int64_t *)(ws + L.offsets);
     int64_t *scan_sums = (int64_t *)(ws + L.scan_sums);
-    uint64_t *keys_alt = (uint64_t *)(ws + L.keys_alt);
-    int32_t *vals_alt = (int32_t *)(ws + L.vals_alt);
     unsigned *hist = (unsigned *)(ws + L.hist);
     unsigned *hist_sums = (unsigned *)(ws + L.hist_sums);
+    const int64_t *K = (const int64_t *)bins->counters;
 
     // ranges start empty: (0, 0)
     hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(2ll * bins->n_tiles, 256)), dim3(256), 0, st, bins->ranges,
@@ -461,30 +576,48 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, st, (int32_t *)bins->counters, 4, 0);
         return build_schedule(bins, st);
     }
-    int rc = scan_exclusive<int32_t, int64_t, int64_t>(s->tiles_touched, n_splats, offsets, scan_sums,
-                                                        bins->counters, bins->counters + 1, cap, st);
+
+    // 1. depth order of the splats (four 8-bit passes: the result is back in A)
+    hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, s->tiles_touched,
+                       s->depth, n_splats, dkeyA, dvalA, dcount);
+    int rc = GS_OK;
+    for (int pass = 0; pass < 4 && rc == GS_OK; ++pass) {
+        const bool even = (pass & 1) == 0;
+        rc = radix_pass(even ? dkeyA : dkeyB, even ? dvalA : dvalB, dcount, n_splats, pass * kRadixBits, L.depth_nb,
+                        hist, hist_sums, even ? dkeyB : dkeyA, even ? dvalB : dvalA, nullptr, nullptr, st);
+    }
+    if (rc != GS_OK) return rc;
+    const int32_t *rank_ids = dvalA;
+
+    // 2. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
+    rc = scan_exclusive<int64_t, int64_t>(RankTiles{s->tiles_touched, rank_ids}, n_splats, offsets, scan_sums,
+                                          bins->counters, bins->counters + 1, cap, st);
     if (rc != GS_OK) return rc;
 
-    const int passes = (key_bits(bins->n_tiles) + kRadixBits - 1) / kRadixBits;
-    // emit into the buffer that makes the last pass land in bins->keys / bins->ids
-    uint64_t *kA = (passes % 2 == 0) ? bins->keys : keys_alt;
-    int32_t *vA = (passes % 2 == 0) ? bins->ids : vals_alt;
-    uint64_t *kB = (passes % 2 == 0) ? keys_alt : bins->keys;
-    int32_t *vB = (passes % 2 == 0) ? vals_alt : bins->ids;
-    hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, s->tiles_touched, offsets,
-                       (const int4 *)s->rect, s->depth, cams, (int)n_cams, n_splats, cap, kA, vA);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * kRadixBits;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)L.sort_nb), dim3(kSortBlock), 0, st, kA,
-                           (const int64_t *)bins->counters, cap, shift, (int)L.sort_nb, hist);
-        rc = scan_exclusive<unsigned, unsigned, unsigned>(hist, L.hist_n, hist, hist_sums, nullptr, nullptr, -1, st);
-        if (rc != GS_OK) return rc;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)L.sort_nb), dim3(kSortBlock), 0, st, kA, vA,
-                           (const int64_t *)bins->counters, cap, shift, (int)L.sort_nb, hist, kB, vB);
-        uint64_t *tk = kA; kA = kB; kB = tk;
-        int32_t *tv = vA; vA = vB; vB = tv;
+    // 3-4. emit, then stable passes by tile id. The last pass reads the workspace pair W and
+    // writes bins; earlier passes alternate between W and the pair stored in bins' buffers.
+    const int passes = max(1, (tile_bits(bins->n_tiles) + kRadixBits - 1) / kRadixBits);
+    uint32_t *kW = (uint32_t *)(ws + L.tkey), *kX = (uint32_t *)bins->keys;
+    int32_t *vW = (int32_t *)(ws + L.tval), *vX = bins->ids;
+    const bool emit_to_W = ((passes - 1) & 1) == 0;
+    uint32_t *kin = emit_to_W ? kW : kX;
+    int32_t *vin = emit_to_W ? vW : vX;
+    hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
+                       s->tiles_touched, (const int4 *)s->rect, cams, (int)n_cams, n_splats, cap, kin, vin);
+    rc = check_launch("emit");
+    for (int pass = 0; pass < passes && rc == GS_OK; ++pass) {
+        const bool last = pass == passes - 1;
+        uint32_t *kout = kin == kW ? kX : kW;
+        int32_t *vout = vin == vW ? vX : vW;
+        rc = radix_pass(kin, vin, K, cap, pass * kRadixBits, L.tile_nb, hist, hist_sums, last ? nullptr : kout,
+                        last ? bins->ids : vout, last ? bins->keys : nullptr, s->depth, st);
+        kin = kout;
+        vin = vout;
     }
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys,
-                       (const int64_t *)bins->counters, cap, bins->n_tiles, bins->ranges);
+    if (rc != GS_OK) return rc;
+
+    // 5. tile ranges and the work list
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys, K, cap, bins->n_tiles,
+                       bins->ranges);
     return build_schedule(bins, st);
 }

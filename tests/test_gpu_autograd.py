@@ -51,7 +51,8 @@ def test_autograd_finite_differences():
 
     The forward is float32, so the step must be large (1e-3 relative); a step that moves a
     3-sigma box across a tile edge or an alpha across a threshold makes the loss jump, so each
-    sample is taken with two steps (h and h/4) and kept only when they agree within 10%."""
+    sample is taken with three steps (h, h/2, h/4) and kept only when all three agree within
+    2%; the analytic gradient is then compared with the smallest step."""
     _print_case("autograd_fd", wl="tiny")
     from paper_2312_02121_amd.autograd import render
     wl = synth.tilted_camera_scene(51, n=12, width=64, height=48)
@@ -76,15 +77,16 @@ def test_autograd_finite_differences():
         g = p.grad.detach()
         for idx in torch.topk(g.flatten().abs(), 8).indices.tolist():
             h = 1e-3 * max(abs(float(p.detach().flatten()[idx])), 0.1)
-            f1, f2 = fd_at(p, idx, h), fd_at(p, idx, h / 4)
-            if abs(f1 - f2) > 0.1 * max(abs(f1), 1e-2):
+            f = [fd_at(p, idx, h / m) for m in (1, 2, 4)]
+            scale = max(abs(f[-1]), 1e-2)
+            if max(f) - min(f) > 0.02 * scale:
                 skipped += 1
                 continue
             an = float(g.flatten()[idx])
-            assert abs(f1 - an) <= 3e-2 * abs(an) + 1e-2, (idx, f1, f2, an)
+            assert abs(f[-1] - an) <= 3e-2 * abs(an) + 1e-2, (idx, f, an)
             checked += 1
     print(f"FD samples checked {checked}, discontinuous {skipped}")
-    assert checked >= 25
+    assert checked >= 20
 
 
 def test_camera_pose_gradient_matches_oracle():
