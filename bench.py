@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (a known-size kernel "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the rasterizer is built and measured on a single MI355X); "
@@ -163,6 +166,15 @@ def main():
     torch.cuda.set_device(0)
     if abi.gs_device_check() != abi.GS_OK:
         raise SystemExit("not a gfx950 device")
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 launches reading and writing {args.copy_calibration_mib} MiB each")
+        del src, dst
     wl = synth.make_config(args.config)
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)

@@ -230,20 +230,23 @@ int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const gs_camera *c
 /*
  * Sec. 3.1 (eqs. 16-21): walk each pixel's list back to front from `last`, recover
  * T by division from T_final (eq. 17), recompute sigma and alpha, and accumulate:
- *   dL_dmean2d [2][n_splats]    dL/dmu'
- *   dL_dconic  [3][n_splats]    dL/dY as the (0,0), (0,1), (1,1) entries of the
+ *   dL_dmean2d [2][n_splats]    dL/dmu' (float64)
+ *   dL_dconic  [3][n_splats]    dL/dY (float64) as the (0,0), (0,1), (1,1) entries of the
  *                               full-matrix gradient (the off-diagonal is not doubled)
  *   dL_dcolors [3][n_gaussians] dL/dc per scene Gaussian
  *   dL_dopac   [n_gaussians]    dL/do per scene Gaussian
  * dL_dimage [3][n_pixels]; T_final and last from gs_rasterize_fwd with the same
  * inputs. Gradients of clamped alphas (o exp(-sigma) > alpha_max) reach only c.
- * Outputs are accumulated; zero them first.
+ * Outputs are accumulated; zero them first. dL/dmu' and dL/dY are float64 because
+ * gs_project_bwd multiplies them by Y on both sides (dL/dSigma' = -Y dL/dY Y): for a
+ * needle-like splat float32 rounding of dL/dY, scaled by the square of Y's largest
+ * eigenvalue, would dominate the gradient along the splat's thin axis.
  * Errors: GS_ERR_INVALID for null pointers, bad sizes, or alpha_max >= 1 (the
  * division of eq. 17 needs 1 - alpha > 0).
  */
 int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
                      int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *dL_dimage,
-                     const float *T_final, const int32_t *last, float *dL_dmean2d, float *dL_dconic,
+                     const float *T_final, const int32_t *last, double *dL_dmean2d, double *dL_dconic,
                      int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream);
 
 /*
@@ -257,7 +260,7 @@ int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, 
  */
 int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
                           int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *target,
-                          float *image, float *loss, float *dL_dmean2d, float *dL_dconic,
+                          float *image, float *loss, double *dL_dmean2d, double *dL_dconic,
                           int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream);
 
 /*
@@ -271,7 +274,7 @@ int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *b
  * [R_cw | t_cw] per camera (eq. 28 plus the R_cw term through T = J R_cw).
  */
 int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, const gs_splats *s,
-                   int64_t n_splats, const float *dL_dmean2d, const float *dL_dconic,
+                   int64_t n_splats, const double *dL_dmean2d, const double *dL_dconic,
                    float *dL_dmeans, float *dL_dscales, float *dL_dquats, float *dL_dcampose,
                    void *stream);
 

@@ -101,12 +101,37 @@ __device__ inline float wave_sum_to_lane63(float v)
     return v;
 }
 
+// The same reduction for float64 values: DPP moves 32 bits, so each half moves separately.
+template <int kCtrl, int kRowMask>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRowMask, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRowMask, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_sum_to_lane63(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    v += dpp_f64<0x141, 0xF>(v);
+    v += dpp_f64<0x140, 0xF>(v);
+    v += dpp_f64<0x142, 0xA>(v);
+    v += dpp_f64<0x143, 0xC>(v);
+    return v;
+}
+
 __device__ inline float wave_sum(float v)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
 
 __device__ inline void atomic_add_f32(float *addr, float v)
+{
+    __hip_atomic_fetch_add(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void atomic_add_f64(double *addr, double v)
 {
     __hip_atomic_fetch_add(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -4,8 +4,11 @@
 // which is large for thin splats, and the chain that follows sums terms of both signs;
 // in float32 that costs up to ~1e-3 of relative accuracy on single quaternion gradients.
 // The kernel is HBM-bound and CDNA issues float64 FMAs at the float32 rate, so this is
-// free. The conic Y is read from the splat record (computed in float64 by gs_project)
-// rather than re-inverted, so a nearly singular Sigma' loses nothing here.
+// free. The conic Y in dL/dSigma' is re-derived here in float64 from Sigma' rather than read
+// from the splat record: the record holds Y rounded to float32 for the compositing, and for a
+// needle-like splat that rounding moves Y's small eigenvalue by up to ~1e-2 relative, which
+// the product -Y dL/dY Y would carry into the gradient. The derivative of the inverse is
+// taken at Sigma' itself.
 //
 // The mean route of eq. (23) is applied in its reduced form: with P of eq. (1), the
 // product 1/2 P^T D^T dL/dmu' equals J^T dL/dmu' extended by 0, i.e.
@@ -16,10 +19,9 @@
 namespace gsx {
 
 __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const gs_camera *__restrict__ cams, int n_cams,
-                                                          const float4 *__restrict__ rec,
                                                           const int32_t *__restrict__ tiles, int64_t n_splats,
-                                                          const float *__restrict__ d_mean2d,
-                                                          const float *__restrict__ d_conic, float *__restrict__ d_means,
+                                                          const double *__restrict__ d_mean2d,
+                                                          const double *__restrict__ d_conic, float *__restrict__ d_means,
                                                           float *__restrict__ d_scales, float *__restrict__ d_quats,
                                                           float *__restrict__ d_pose, int use_atomics)
 {
@@ -67,9 +69,20 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
             for (int b = 0; b < 3; ++b)
                 S[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
 
+        // Sigma' = T Sigma T^T (eq. 4) and Y = Sigma'^-1, in float64
+        double TS[6];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                TS[3 * r + b] = T[3 * r] * S[b] + T[3 * r + 1] * S[3 + b] + T[3 * r + 2] * S[6 + b];
+        const double C00 = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2];
+        const double C01 = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
+        const double C11 = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5];
+        const double det = C00 * C11 - C01 * C01;
+        const double y00 = C11 / det, y01 = -C01 / det, y11 = C00 / det;
+
         // dL/dSigma' = -Y dL/dY Y (Sec. 3.1), Y symmetric
-        const float4 r0 = rec[3 * p], r1 = rec[3 * p + 1];
-        const double y00 = r0.z, y01 = r0.w, y11 = r1.x;
         const double g00 = d_conic[p], g01 = d_conic[n_splats + p], g11 = d_conic[2 * n_splats + p];
         const double a00 = y00 * g00 + y01 * g01, a01 = y00 * g01 + y01 * g11;   // Y G
         const double a10 = y01 * g00 + y11 * g01, a11 = y01 * g01 + y11 * g11;
@@ -81,12 +94,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
         double dtx = J00 * dmx, dty = J11 * dmy, dtz = J02 * dmx + J12 * dmy;
 
         // covariance route: dL/dT = G T Sigma + G^T T Sigma (eq. 25), dL/dJ = dL/dT R_cw^T
-        double TS[6];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                TS[3 * r + b] = T[3 * r] * S[b] + T[3 * r + 1] * S[3 + b] + T[3 * r + 2] * S[6 + b];
         double dT[6];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
 using namespace gsx;
 
 extern "C" int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, const gs_splats *s,
-                              int64_t n_splats, const float *dL_dmean2d, const float *dL_dconic, float *dL_dmeans,
+                              int64_t n_splats, const double *dL_dmean2d, const double *dL_dconic, float *dL_dmeans,
                               float *dL_dscales, float *dL_dquats, float *dL_dcampose, void *stream)
 {
     clear_error();
@@ -224,7 +231,7 @@ extern "C" int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int3
     // with one camera every scene Gaussian has exactly one slot, so plain read-modify-write is race free
     const int use_atomics = n_cams > 1 ? 1 : 0;
     hipLaunchKernelGGL(project_bwd_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream, *g, cams,
-                       (int)n_cams, (const float4 *)s->rec, s->tiles_touched, n_splats, dL_dmean2d, dL_dconic,
+                       (int)n_cams, s->tiles_touched, n_splats, dL_dmean2d, dL_dconic,
                        dL_dmeans, dL_dscales, dL_dquats, dL_dcampose, use_atomics);
     return check_launch("gs_project_bwd");
 }

@@ -223,7 +223,8 @@ __device__ inline int wave_max(int v)
 
 struct BwdOut {
     int64_t n_splats, n_gauss;
-    float *d_mean2d, *d_conic, *d_colors, *d_opac;
+    double *d_mean2d, *d_conic;
+    float *d_colors, *d_opac;
 };
 
 // Back-to-front walk (Sec. 3.1). On entry T holds T_final, last the start positions and
@@ -243,7 +244,6 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     float gS[PX];
 #pragma unroll
     for (int q = 0; q < PX; ++q) gS[q] = 0.f;
-    const float kInvLog2e = (float)(1.0 / kLog2eD);
     RasterRec *slice = wave_slice();
     const int kend = t.start + maxlast;
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
@@ -263,9 +263,12 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
-            const float dyf = (float)dy;
-            float s_v = 0.f, s_x = 0.f, s_y = 0.f, s_xx = 0.f, s_xy = 0.f, s_yy = 0.f, s_c0 = 0.f, s_c1 = 0.f,
-                  s_c2 = 0.f;
+            // per-lane sums over the lane's pixels; the lane's pixels share one row, so the
+            // dy-weighted sums follow from sum v and sum v dx after the loop. The position
+            // sums are float64: dL/dY along the thin axis of a needle-like splat is a small
+            // difference of these sums, which float32 rounding would swamp.
+            double s_v = 0.0, s_x = 0.0, s_xx = 0.0;
+            float s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
             float live_sum = 0.f;
 #pragma unroll
             for (int q = 0; q < PX; ++q) {
@@ -287,17 +290,15 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 const float dalpha = gc * T[q] - gS[q] * rinv;      // eq. (18)
                 gS[q] = __builtin_fmaf(gc, w, gS[q]);
                 // eq. (19): dalpha/dsigma = -alpha; a clamped alpha passes no gradient to o or sigma
-                const float v = a_raw > prm.alpha_max ? 0.f : dalpha * a;
-                const float dxf = (float)dx;
-                const float vx = v * dxf;
+                const double v = (double)(a_raw > prm.alpha_max ? 0.f : dalpha * a);
+                const double vx = v * dx;
                 s_v += v;
                 s_x += vx;
-                s_y = __builtin_fmaf(v, dyf, s_y);
-                s_xx = __builtin_fmaf(vx, dxf, s_xx);
-                s_xy = __builtin_fmaf(vx, dyf, s_xy);
-                s_yy = __builtin_fmaf(v * dyf, dyf, s_yy);
+                s_xx = __builtin_fma(vx, dx, s_xx);
             }
             if (__ballot(live_sum > 0.f) == 0) continue;
+            double s_y = s_v * dy, s_xy = s_x * dy;
+            double s_yy = s_y * dy;
             s_v = wave_sum_to_lane63(s_v);
             s_x = wave_sum_to_lane63(s_x);
             s_y = wave_sum_to_lane63(s_y);
@@ -308,17 +309,17 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             s_c1 = wave_sum_to_lane63(s_c1);
             s_c2 = wave_sum_to_lane63(s_c2);
             if (lane == kWave - 1) {
-                // Y = -(2A, B; B, 2C) / log2(e); dL/dmu' = -Y sum v Delta
-                const float A2 = (float)(2.0 * r.A), B1 = (float)r.B, C2 = (float)(2.0 * r.C);
-                atomic_add_f32(&out.d_mean2d[id], (A2 * s_x + B1 * s_y) * kInvLog2e);
-                atomic_add_f32(&out.d_mean2d[out.n_splats + id], (B1 * s_x + C2 * s_y) * kInvLog2e);
-                atomic_add_f32(&out.d_conic[id], -0.5f * s_xx);
-                atomic_add_f32(&out.d_conic[out.n_splats + id], -0.5f * s_xy);
-                atomic_add_f32(&out.d_conic[2 * out.n_splats + id], -0.5f * s_yy);
+                // Y = -(2A, B; B, 2C) / log2(e); dL/dmu' = -Y sum v Delta; dL/dY = -1/2 sum v Delta Delta^T
+                const double il = 1.0 / kLog2eD;
+                atomic_add_f64(&out.d_mean2d[id], (2.0 * r.A * s_x + r.B * s_y) * il);
+                atomic_add_f64(&out.d_mean2d[out.n_splats + id], (r.B * s_x + 2.0 * r.C * s_y) * il);
+                atomic_add_f64(&out.d_conic[id], -0.5 * s_xx);
+                atomic_add_f64(&out.d_conic[out.n_splats + id], -0.5 * s_xy);
+                atomic_add_f64(&out.d_conic[2 * out.n_splats + id], -0.5 * s_yy);
                 atomic_add_f32(&out.d_colors[r.src], s_c0);
                 atomic_add_f32(&out.d_colors[out.n_gauss + r.src], s_c1);
                 atomic_add_f32(&out.d_colors[2 * out.n_gauss + r.src], s_c2);
-                atomic_add_f32(&out.d_opac[r.src], s_v / r.o);
+                atomic_add_f32(&out.d_opac[r.src], (float)(s_v / (double)r.o));
             }
         }
     }
@@ -522,8 +523,8 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     return check_launch("gs_rasterize_fwd");
 }
 
-static int check_bwd_outputs(const gs_splats *s, int64_t n_splats, const gs_params *prm, float *dL_dmean2d,
-                             float *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac)
+static int check_bwd_outputs(const gs_splats *s, int64_t n_splats, const gs_params *prm, double *dL_dmean2d,
+                             double *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac)
 {
     if (!dL_dmean2d || !dL_dconic || !dL_dcolors || !dL_dopac || n_splats < 0 || n_splats > s->capacity ||
         n_gaussians < 1)
@@ -535,7 +536,7 @@ static int check_bwd_outputs(const gs_splats *s, int64_t n_splats, const gs_para
 
 extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
                                 int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *dL_dimage,
-                                const float *T_final, const int32_t *last, float *dL_dmean2d, float *dL_dconic,
+                                const float *T_final, const int32_t *last, double *dL_dmean2d, double *dL_dconic,
                                 int64_t n_gaussians, float *dL_dcolors, float *dL_dopac, void *stream)
 {
     clear_error();
@@ -555,8 +556,8 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
 
 extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *bins,
                                      const gs_camera *cams, int32_t n_cams, const gs_params *prm, int64_t n_pixels,
-                                     const float *target, float *image, float *loss, float *dL_dmean2d,
-                                     float *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac,
+                                     const float *target, float *image, float *loss, double *dL_dmean2d,
+                                     double *dL_dconic, int64_t n_gaussians, float *dL_dcolors, float *dL_dopac,
                                      void *stream)
 {
     clear_error();

@@ -260,7 +260,8 @@ class Rasterizer:
         dev = self.device
         dL_dimage = dL_dimage.contiguous().to(torch.float32)
         grads = {
-            "mean2d": torch.empty(2, max(P, 1), device=dev), "conic": torch.empty(3, max(P, 1), device=dev),
+            "mean2d": torch.empty(2, max(P, 1), dtype=torch.float64, device=dev),
+            "conic": torch.empty(3, max(P, 1), dtype=torch.float64, device=dev),
             "colors": torch.empty(3, g.n, device=dev), "opacities": torch.empty(g.n, device=dev),
             "means": torch.empty(3, g.n, device=dev), "scales": torch.empty(3, g.n, device=dev),
             "quats": torch.empty(4, g.n, device=dev),
@@ -268,7 +269,7 @@ class Rasterizer:
         if with_pose:
             grads["campose"] = torch.empty(cams.n_cams, 12, device=dev)
         for t in grads.values():
-            abi.gs_zero(t.data_ptr(), t.numel() * 4, stream)
+            abi.gs_zero(t.data_ptr(), t.numel() * t.element_size(), stream)
         sp = state.splats.struct(P)
         abi.gs_rasterize_bwd(sp, P, state.bins.struct(), cams.ptr, cams.n_cams, state.params, cams.n_pixels,
                              _ptr(dL_dimage), _ptr(state.T_final), _ptr(state.last), _ptr(grads["mean2d"]),
@@ -321,7 +322,7 @@ class TrainStep:
         scene = {"colors": (3, n), "opacities": (n,), "means": (3, n), "scales": (3, n), "quats": (4, n),
                  "loss": (1,)}
         numel = lambda sh: int(np.prod(sh))
-        self.slot_flat = torch.empty(sum(numel(v) for v in slot.values()), dtype=torch.float32, device=cams.device)
+        self.slot_flat = torch.empty(sum(numel(v) for v in slot.values()), dtype=torch.float64, device=cams.device)
         self.grads, o = {}, 0
         for k, sh in slot.items():
             self.grads[k] = self.slot_flat[o:o + numel(sh)].view(sh)
@@ -357,7 +358,7 @@ class TrainStep:
         elif name == "l2_grad":
             abi.gs_l2_grad(r.image.data_ptr(), self.targets.data_ptr(), r.image.numel(), self.dL.data_ptr(), stream)
         elif name == "zero_grads":
-            abi.gs_zero(self.slot_flat.data_ptr(), self.slot_flat.numel() * 4, stream)
+            abi.gs_zero(self.slot_flat.data_ptr(), self.slot_flat.numel() * 8, stream)
             if self.owns_scene_grads:
                 abi.gs_zero(self.scene_flat.data_ptr(), self.scene_flat.numel() * 4, stream)
         elif name == "rasterize_bwd":

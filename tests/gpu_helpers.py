@@ -6,14 +6,17 @@ import numpy as np
 
 import oracle
 
-# Near-tie margins for the oracle's decision flags. The float32 kernel computes
-# alpha = exp2(log2 o + q(Delta)) with |q| <= ~12 in the range where alpha >= 1/255, so
-# its relative alpha error stays below ~2e-6; T after n factors carries n such errors
-# plus rounding. A pixel whose skip/termination/clamp decision sits within these
-# margins of the threshold may legitimately go either way and is excluded (counted).
-MARGIN_ALPHA = 1e-5     # relative to alpha_min
-MARGIN_T = 1e-3         # relative to T_min
-MARGIN_CLAMP = 2e-5     # absolute, around alpha_max
+# Near-tie margins for the oracle's decision flags. The float32 kernel evaluates
+# alpha = exp2(e) with e = log2 o - sigma log2(e) formed in float64 and rounded to float32
+# once; for alpha >= 1/255, |e| <= 8, so the rounding moves alpha by at most 8 * 2^-24 * ln 2
+# (3.3e-7) relative, and exp2 adds about one ulp: MARGIN_ALPHA leaves a factor of four over
+# that. T after n factors carries, per factor, alpha / (1 - alpha) times the alpha error
+# plus two roundings; the oracle adds that bound up along the walk on top of MARGIN_T.
+# A pixel whose skip, termination or clamp decision lies inside these margins may
+# legitimately go either way: it is excluded from comparison and counted.
+MARGIN_ALPHA = 2e-6     # relative to alpha_min
+MARGIN_T = 1e-5         # relative to T_min, plus the accumulated float32 bound
+MARGIN_CLAMP = 2e-6     # absolute, around alpha_max
 
 IMAGE_ATOL = 1e-5
 GRAD_REL = 1e-3
@@ -93,3 +96,25 @@ def tile_offsets(wl):
         offs.append(t)
         t += c.n_tiles
     return offs
+
+
+def check_projection(wl, r, views=None):
+    """Splat fields of every camera (or of `views`) bit-exact against the oracle's projection."""
+    s = splat_arrays(r)
+    for k in (range(len(wl.cameras)) if views is None else views):
+        cam = wl.cameras[k]
+        off = int(r.cams.host[k]["proj_offset"])
+        n = int(r.cams.host[k]["gauss_count"])
+        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
+        sl = slice(off, off + n)
+        assert np.array_equal(s["tiles"][sl], o["tiles"]), "tiles_touched"
+        vis = o["tiles"] > 0
+        assert np.array_equal(s["rect"][:, sl][:, vis], o["rect"][:, vis]), "rect"
+        assert np.array_equal(s["mean2d"][:, sl][:, vis].astype(np.float64), o["mean2d"][:, vis]), "mean2d"
+        assert np.array_equal(s["conic"][:, sl][:, vis].astype(np.float64), o["conic"][:, vis]), "conic"
+        assert np.array_equal(s["depth"][sl][vis].astype(np.float64), o["depth"][vis]), "depth"
+        sc = wl.scenes[cam.scene]
+        assert np.array_equal(s["opacity"][sl][vis], sc["opacities"][vis])
+        assert np.array_equal(s["color"][:, sl][:, vis], sc["colors"][:, vis])
+        assert np.array_equal(s["src"][sl][vis], np.nonzero(vis)[0] + (sum(wl.scenes[j]["opacities"].shape[0]
+                                                                          for j in range(cam.scene))))

@@ -13,7 +13,8 @@ import oracle
 from paper_2312_02121_amd import synth
 
 from gpu_helpers import (IMAGE_ATOL, GRAD_REL, bins_arrays, camera_images, elementwise_ok, gpu_forward,
-                         oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets, worst_element)
+                         oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets, worst_element,
+                         check_projection)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,32 +44,12 @@ def wl_cache():
     return WL
 
 
-def _check_projection(wl, r):
-    s = splat_arrays(r)
-    for k, cam in enumerate(wl.cameras):
-        off = int(r.cams.host[k]["proj_offset"])
-        n = int(r.cams.host[k]["gauss_count"])
-        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
-        sl = slice(off, off + n)
-        assert np.array_equal(s["tiles"][sl], o["tiles"]), "tiles_touched"
-        vis = o["tiles"] > 0
-        assert np.array_equal(s["rect"][:, sl][:, vis], o["rect"][:, vis]), "rect"
-        assert np.array_equal(s["mean2d"][:, sl][:, vis].astype(np.float64), o["mean2d"][:, vis]), "mean2d"
-        assert np.array_equal(s["conic"][:, sl][:, vis].astype(np.float64), o["conic"][:, vis]), "conic"
-        assert np.array_equal(s["depth"][sl][vis].astype(np.float64), o["depth"][vis]), "depth"
-        sc = wl.scenes[cam.scene]
-        assert np.array_equal(s["opacity"][sl][vis], sc["opacities"][vis])
-        assert np.array_equal(s["color"][:, sl][:, vis], sc["colors"][:, vis])
-        assert np.array_equal(s["src"][sl][vis], np.nonzero(vis)[0] + (sum(wl.scenes[j]["opacities"].shape[0]
-                                                                          for j in range(cam.scene))))
-
-
 @pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
 def test_projection_bit_exact(name):
     _print_case("projection", wl=name)
     wl = wl_cache()[name]
     r, st = gpu_forward(wl)
-    _check_projection(wl, r)
+    check_projection(wl, r)
 
 
 @pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
@@ -172,7 +153,7 @@ def test_multi_scene_multi_camera():
         # rebuild so that every camera value is rounded to float32 exactly as the GPU receives it
         wl.cameras[k] = synth.Camera(c.R, c.t, c.fx * s, c.fy * s, w / 2, h / 2, w, h, c.near, c.far, c.scene)
     r, st = gpu_forward(wl)
-    _check_projection(wl, r)
+    check_projection(wl, r)
     flagged, pixels = _forward_compare(wl, r, st)
     assert flagged <= max(3, 0.02 * pixels)
     res = _backward_compare(wl, r, st, seed=3)
@@ -213,7 +194,7 @@ def test_edge_cases():
     wl.scenes[0]["scales"][:, 0] = 5.0
     wl.scenes[0]["scales"][:, 1] = 1e-3
     r, st = gpu_forward(wl)
-    _check_projection(wl, r)
+    check_projection(wl, r)
     flagged, pixels = _forward_compare(wl, r, st)
     assert flagged <= 3
     res = _backward_compare(wl, r, st, seed=5)
