@@ -92,17 +92,19 @@ def time_steps(fn, steps: int, warmup: int) -> float:
     return a.elapsed_time(b) / steps
 
 
-def batched_vs_per_view(cfg: int, steps: int, warmup: int) -> dict:
-    """One fused persistent launch over every camera, captured in a HIP graph, against the same
-    kernels run one view per launch sequence with no graph."""
+def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
+    """One fused persistent launch sequence over every camera, captured in a HIP graph, against
+    the same kernels run one view per launch sequence with no graph. Each form gets its own
+    autotuned launch tuning (the search runs before the timed region)."""
     import numpy as np
     import torch
-    from paper_2312_02121_amd import pipeline, synth
+    from paper_2312_02121_amd import autotune, pipeline, synth
     wl = synth.make_config(cfg)
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
     step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_image=False)
+    tb = autotune.tune(step) if tune else None
     graph = pipeline.GraphStep(step)
     ms_b = time_steps(graph, steps, warmup)
     if step.overflowed():
@@ -112,14 +114,17 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int) -> dict:
     torch.cuda.empty_cache()
     targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
     per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
+    tv = autotune.search(lambda: autotune.time_eager(per_view, 2, 1)) if tune else None
     ms_v = time_steps(per_view, steps, warmup)
     del per_view
     torch.cuda.empty_cache()
+    autotune.apply(autotune.default_tuning())
     log(f"config {cfg}: batched {ms_b:.3f} ms, per-view {ms_v:.3f} ms")
     return {"workload": wl.name, "views": cams.n_cams, "n_gaussians": g.n, "E_fwd": E,
             "batched_ms_per_step": ms_b, "per_view_ms_per_step": ms_v,
             "batched_evals_per_s": E / (ms_b * 1e-3), "per_view_evals_per_s": E / (ms_v * 1e-3),
-            "speedup": ms_v / ms_b, "batched_ms_per_view": ms_b / cams.n_cams}
+            "speedup": ms_v / ms_b, "batched_ms_per_view": ms_b / cams.n_cams,
+            "batched_tuning": tb["tuning"] if tb else None, "per_view_tuning": tv["tuning"] if tv else None}
 
 
 def autograd_ms(wl, steps: int, warmup: int) -> float:
@@ -149,6 +154,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (a known-size kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -161,7 +167,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2312_02121_amd import abi, pipeline, synth
+    from paper_2312_02121_amd import abi, autotune, pipeline, synth
 
     torch.cuda.set_device(0)
     if abi.gs_device_check() != abi.GS_OK:
@@ -181,6 +187,12 @@ def main():
     targets = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
     step = pipeline.TrainStep(g, cams, targets, mode=args.mode)
     log(f"K={step.K} E_fwd={step.E_fwd} E_bwd={step.E_bwd} P={cams.n_splats} pixels={cams.n_pixels}")
+    tuned = None
+    if not args.no_tune:
+        # launch tuning for this workload, searched before anything is timed
+        tuned = autotune.tune(step)
+        log(f"autotuned {tuned['tuning']}: {tuned['default_ms']:.4f} -> {tuned['ms']:.4f} ms "
+            f"({tuned['evaluated']} candidates, {tuned['seconds']:.1f} s)")
 
     # per-stage times (eager launches, events between stages on the launch stream)
     n_st = len(step.STAGES)
@@ -220,9 +232,10 @@ def main():
         "config": {"workload": wl.name, "n_gaussians": g.n, "views": views, "width": int(cams.host[0]["width"]),
                    "height": int(cams.host[0]["height"]), "K": step.K, "E_fwd": step.E_fwd, "E_bwd": step.E_bwd,
                    "ms_per_view": ms_step / views, "mode": args.mode, "graph": not args.no_graph,
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu", "tuning": autotune.current()},
         "stages_ms": stage_ms,
         "roofline": roofline,
+        "autotune": None if tuned is None else {k: tuned[k] for k in ("default_ms", "ms", "evaluated", "seconds")},
     }
     del runner
     if not args.no_autograd and args.config == 3:
@@ -231,7 +244,8 @@ def main():
     if not args.no_batched:
         del step
         torch.cuda.empty_cache()
-        line["batched"] = {f"c{c}": batched_vs_per_view(c, max(3, args.steps // 4), 2) for c in (4, 5)}
+        line["batched"] = {f"c{c}": batched_vs_per_view(c, max(3, args.steps // 4), 2, not args.no_tune)
+                           for c in (4, 5)}
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
         line["cpu_baseline"] = cpu_baseline(wl, line["config"]["E_fwd"])
     print(json.dumps(line), flush=True)

@@ -133,11 +133,27 @@ typedef struct gs_bins {
     int32_t *ranges;         /* [n_tiles][2] start, end of each tile's run; empty tile = (0, 0) */
     int32_t *schedule;       /* [gs_schedule_size(n_tiles)] rasterizer work list, written by
                                 gs_bin_and_sort; layout private to the library */
-    int64_t *counters;       /* [2]: K = total intersections (may exceed capacity), overflow flag */
+    int64_t *counters;       /* [2]: K = total intersections (may exceed capacity), flags
+                                (1 = overflow, 2 = sort failure) */
     int64_t capacity;        /* K_cap, at most 2^31 - 1 */
     int32_t n_tiles;         /* sum over cameras of tiles_x * tiles_y */
     int32_t reserved;
 } gs_bins;
+
+/*
+ * Launch tuning of the rasterizer (not part of the method: results do not depend on it).
+ * gs_bin_and_sort builds the work list with split_len and split_parts; the rasterize
+ * calls launch with waves_per_cu and split_priority. The setting is process-wide and is
+ * read when a call is made, so a captured graph keeps the tuning it was captured with.
+ */
+typedef struct gs_tuning {
+    int32_t split_len;       /* tiles with at least this many list entries become split_parts
+                                work items; >= 1 (a value above any list length disables it) */
+    int32_t split_parts;     /* 2 (16x8-pixel halves, 2 pixels per lane) or
+                                4 (16x4-pixel quarters, 1 pixel per lane) */
+    int32_t waves_per_cu;    /* persistent grid: waves launched per compute unit, 4..64 */
+    int32_t split_priority;  /* nonzero: a wave raises its issue priority on a split item */
+} gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */
 
@@ -152,6 +168,13 @@ const char *gs_last_error_message(void);
 
 /* Library version as major * 10000 + minor * 100 + patch. */
 int gs_version(void);
+
+/* Sets the process-wide launch tuning (see gs_tuning). GS_ERR_INVALID for values out of
+ * range. Not synchronised with calls running on other host threads. */
+int gs_set_tuning(const gs_tuning *t);
+
+/* Reads the current launch tuning into *t. */
+int gs_get_tuning(gs_tuning *t);
 
 /* Zeroes `bytes` bytes at device pointer `ptr` with a kernel (graph-capturable). */
 int gs_zero(void *ptr, size_t bytes, void *stream);
@@ -199,7 +222,9 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * emitted in depth order, which yields the same list. K is written to
  * bins->counters[0]; if K exceeds bins->capacity only the first `capacity` entries (in
  * depth order of their splats) are kept, counters[1] is set to 1 and the list is
- * incomplete: the caller reads the flag, regrows and calls again. workspace: device
+ * incomplete: the caller reads the flag, regrows and calls again. counters[1] & 2 means a
+ * wait inside the single-pass sort gave up after its spin limit (the list is invalid; this
+ * indicates a fault, not a capacity problem). workspace: device
  * memory of at least gs_bin_and_sort_workspace_size() bytes, contents free on entry and
  * exit. cams: as for gs_project.
  * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1], n_splats outside

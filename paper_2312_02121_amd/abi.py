@@ -24,7 +24,7 @@ EXPORTED = (
     "gs_device_check", "gs_last_hip_error", "gs_last_error_message", "gs_version", "gs_zero", "gs_abi_layout",
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
     "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
-    "gs_graph_destroy",
+    "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning",
 )
 
 
@@ -58,6 +58,14 @@ class GsSplats(ctypes.Structure):
 class GsParams(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
                 ("reserved", ctypes.c_int32)]
+
+
+class GsTuning(ctypes.Structure):
+    _fields_ = [("split_len", ctypes.c_int32), ("split_parts", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("split_priority", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class GsBins(ctypes.Structure):
@@ -114,6 +122,8 @@ def lib():
         "gs_graph_end": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_void_p)]),
         "gs_graph_launch": (ctypes.c_int, [_P, _P]),
         "gs_graph_destroy": (ctypes.c_int, [_P]),
+        "gs_set_tuning": (ctypes.c_int, [_P]),
+        "gs_get_tuning": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -215,3 +225,13 @@ def gs_graph_launch(graph: int, stream: int):
 
 def gs_graph_destroy(graph: int):
     _check("gs_graph_destroy", lib().gs_graph_destroy(graph))
+
+
+def gs_set_tuning(t: GsTuning):
+    _check("gs_set_tuning", lib().gs_set_tuning(ctypes.byref(t)))
+
+
+def gs_get_tuning() -> GsTuning:
+    t = GsTuning()
+    _check("gs_get_tuning", lib().gs_get_tuning(ctypes.byref(t)))
+    return t

@@ -1,0 +1,141 @@
+"""Autotuner of the rasterizer's launch tuning (gs_tuning) for one batch of cameras.
+
+The work list and the persistent launch have four knobs (see gs_tuning in the C header):
+the list length at which a tile is split, the number of parts (16x8 halves or 16x4
+quarters), the persistent grid size in waves per compute unit, and whether a wave raises
+its priority on split items. None of them changes a result, only the time.
+
+``tune`` times a full training step (project, bin and sort, fused forward + loss +
+backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
+The search is a coordinate descent from the library default: one knob at a time over its
+values, keeping the best value before moving to the next knob, two rounds. Results can be
+cached in a JSON file keyed by a signature of the workload (cameras, resolutions, Gaussian
+count, and the list length rounded to a power of two), so a later process with the same
+kind of batch skips the search.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Callable
+
+import torch
+
+from . import abi
+
+KNOBS = {
+    "split_len": (128, 256, 512, 1024, 1 << 30),
+    "split_parts": (2, 4),
+    "waves_per_cu": (16, 32),
+    "split_priority": (0, 1),
+}
+
+
+def default_tuning() -> dict:
+    return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1}
+
+
+def apply(t: dict):
+    abi.gs_set_tuning(abi.GsTuning(**{k: int(v) for k, v in t.items()}))
+
+
+def current() -> dict:
+    return abi.gs_get_tuning().as_dict()
+
+
+def signature(step) -> str:
+    """Workload key: camera count, sizes, Gaussians, splats and log2 of the list length."""
+    cams = step.cams
+    sizes = sorted({(int(c["width"]), int(c["height"])) for c in cams.host})
+    return json.dumps({"views": int(cams.n_cams), "sizes": sizes, "gaussians": int(step.g.n),
+                       "splats": int(cams.n_splats), "log2K": int(round(math.log2(max(step.K, 1))))},
+                      sort_keys=True)
+
+
+def _time_graph(step, steps: int, warmup: int) -> float:
+    from .pipeline import GraphStep
+    graph = GraphStep(step)
+    for _ in range(warmup):
+        graph()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        graph()
+    b.record()
+    torch.cuda.synchronize()
+    if step.overflowed():
+        raise RuntimeError("list capacity overflow while tuning")
+    del graph
+    return a.elapsed_time(b) / steps
+
+
+def time_eager(fn, steps: int, warmup: int) -> float:
+    """Mean ms per call of fn() over `steps` calls after `warmup`."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def search(measure: Callable[[], float], rounds: int = 2, log: Callable[[str], None] | None = None) -> dict:
+    """Coordinate descent over KNOBS from the default; measure() times the workload under
+    the tuning currently applied. Applies and returns the best."""
+    t0 = time.perf_counter()
+    seen: dict = {}
+
+    def run(t: dict) -> float:
+        k = tuple(sorted(t.items()))
+        if k not in seen:
+            apply(t)
+            seen[k] = measure()
+            if log:
+                log(f"tuning {t}: {seen[k]:.4f} ms")
+        return seen[k]
+
+    best = default_tuning()
+    default_ms = best_ms = run(best)
+    for _ in range(rounds):
+        improved = False
+        for knob, values in KNOBS.items():
+            for v in values:
+                if v == best[knob]:
+                    continue
+                cand = {**best, knob: v}
+                ms = run(cand)
+                if ms < best_ms * 0.995:
+                    best, best_ms, improved = cand, ms, True
+        if not improved:
+            break
+    apply(best)
+    return {"tuning": best, "ms": best_ms, "default_ms": default_ms, "evaluated": len(seen),
+            "seconds": time.perf_counter() - t0}
+
+
+def tune(step, steps: int = 5, warmup: int = 2, rounds: int = 2, cache_path: str | None = None,
+         log: Callable[[str], None] | None = None) -> dict:
+    """Finds the fastest tuning for `step` (a pipeline.TrainStep, timed as a captured graph),
+    applies it and returns {"tuning", "ms", "default_ms", "evaluated", "seconds", "cached"}."""
+    key = signature(step)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            apply(cache[key]["tuning"])
+            return {**cache[key], "cached": True}
+    res = search(lambda: _time_graph(step, steps, warmup), rounds=rounds, log=log)
+    if cache_path:
+        cache[key] = res
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return {**res, "cached": False}

@@ -23,11 +23,16 @@
 // views with near-plane splats (hundreds of millions of entries) the sort is HBM-bound and
 // the difference is the whole cost.
 //
-// Each pass is a per-block digit histogram, a scan of the digit-major histogram table and
-// a stable scatter. Block ranking uses wave ballots to group equal digits and LDS counters
-// per (wave, digit), so no LDS atomics contend on popular digits. Every kernel is sized
-// from host-known capacities and reads its element count from device memory, so the whole
-// sequence replays unchanged inside a captured HIP graph.
+// Each pass is one launch of a single-pass LSD sort with decoupled look-back: one upfront
+// kernel counts the digits of all passes from one read of the keys; then, per pass, each
+// block ranks its chunk, publishes its digit counts, sums its predecessors' published
+// counts for its global offsets (waiting, with a spin limit, on any predecessor that has
+// not published yet), stages the chunk in LDS in digit order and writes it out in runs.
+// Block ranking uses wave ballots to group equal digits and LDS counters per (wave,
+// digit), so no LDS atomics contend on popular digits. Every kernel is sized from
+// host-known capacities and reads its element count from device memory, and the
+// look-back state is cleared by a kernel at the start of each call, so the whole sequence
+// replays unchanged inside a captured HIP graph.
 #include "common.h"
 
 namespace gsx {
@@ -159,6 +164,7 @@ constexpr int kSortItems = 16;                       // keys per lane
 constexpr int kSortChunk = kSortBlock * kSortItems;  // keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+static_assert(kSortBlock == kRadix, "one thread per digit in the single-pass sort");
 
 __device__ inline int64_t sort_count(const int64_t *counter, int64_t cap)
 {
@@ -196,54 +202,80 @@ __device__ inline void count_digits(const uint32_t (&key)[kSortItems], int64_t c
     }
 }
 
-__global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys,
-                                                                const int64_t *__restrict__ count, int64_t cap,
-                                                                int shift, int nblocks, unsigned *__restrict__ hist)
-{
-    __shared__ unsigned cnt[kSortWaves][kRadix];
-    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
-    __syncthreads();
-    const int64_t kvalid = sort_count(count, cap);
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-    if (base < kvalid) {
-        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-        uint32_t key[kSortItems];
-#pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-            key[r] = idx < kvalid ? keys[idx] : 0u;
-        }
-        count_digits(key, base, kvalid, shift, cnt);
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
-        unsigned s = 0;
-#pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) s += cnt[w][d];
-        hist[(int64_t)d * nblocks + blockIdx.x] = s;
-    }
-}
-
-// hist_scan holds, digit-major, the exclusive prefix of the histogram table: the output
-// position of the first key with digit d in block b. When keys64_out is set (the last tile
-// pass), the scatter writes the 64-bit output key (tile << 32 | depth bits of the value)
-// there instead of the 32-bit key.
-__global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
-                                                                   const int32_t *__restrict__ vals_in,
-                                                                   const int64_t *__restrict__ count, int64_t cap,
-                                                                   int shift, int nblocks,
-                                                                   const unsigned *__restrict__ hist_scan,
-                                                                   uint32_t *__restrict__ keys_out,
-                                                                   int32_t *__restrict__ vals_out,
-                                                                   uint64_t *__restrict__ keys64_out,
-                                                                   const float *__restrict__ depth)
+// Digit histograms of every pass from one read of the keys: ghist[pass][digit].
+__global__ __launch_bounds__(kSortBlock) void radix_global_hist_kernel(const uint32_t *__restrict__ keys,
+                                                                       const int64_t *__restrict__ count, int64_t cap,
+                                                                       int passes, unsigned *__restrict__ ghist)
 {
     __shared__ unsigned cnt[kSortWaves][kRadix];
     const int64_t kvalid = sort_count(count, cap);
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     if (base >= kvalid) return;   // uniform over the block
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t key[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
+        key[r] = idx < kvalid ? keys[idx] : 0u;
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
+        __syncthreads();
+        count_digits(key, base, kvalid, pass * kRadixBits, cnt);
+        __syncthreads();
+        const int d = threadIdx.x;   // kSortBlock == kRadix
+        unsigned tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) tot += cnt[w][d];
+        if (tot) atomicAdd(&ghist[pass * kRadix + d], tot);
+        __syncthreads();
+    }
+}
+
+// Status word of one (block, digit) in a single-pass sort: 0 = not yet published,
+// kStatAgg | count of the block's own keys, kStatInc | inclusive prefix (global position
+// one past the block's last key with that digit).
+constexpr uint64_t kStatAgg = 1ull << 62;
+constexpr uint64_t kStatInc = 2ull << 62;
+constexpr uint64_t kStatValue = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 24;   // bounded wait: a predecessor that never publishes ends the wait
+
+// One stable LSD pass with decoupled look-back (chained scan over blocks), in one launch.
+// Blocks take chunk indices from a ticket counter in launch order, so every chunk a block
+// waits on belongs to a block that is already running. Each block ranks its chunk (wave
+// ballots, per-(wave, digit) LDS counters), publishes its digit counts, looks back over its
+// predecessors' published counts for its global offsets, stages the chunk in LDS in digit
+// order and writes it out in runs. The last tile pass writes ids and the 64-bit keys
+// (tile << 32 | depth bits of the value) instead of 32-bit keys.
+__global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__restrict__ keys_in,
+                                                              const int32_t *__restrict__ vals_in,
+                                                              const int64_t *__restrict__ count, int64_t cap,
+                                                              int shift, const unsigned *__restrict__ ghist,
+                                                              uint64_t *__restrict__ status,
+                                                              int32_t *__restrict__ ticket,
+                                                              uint32_t *__restrict__ keys_out,
+                                                              int32_t *__restrict__ vals_out,
+                                                              uint64_t *__restrict__ keys64_out,
+                                                              const float *__restrict__ depth,
+                                                              int64_t *__restrict__ err_flag)
+{
+    __shared__ unsigned cnt[kSortWaves][kRadix];
+    __shared__ unsigned lstart[kRadix];
+    __shared__ int64_t gbase[kRadix];
+    __shared__ uint32_t skey[kSortChunk];
+    __shared__ int32_t sval[kSortChunk];
+    __shared__ int chunk, gave_up;
+    if (threadIdx.x == 0) {
+        chunk = atomicAdd(ticket, 1);
+        gave_up = 0;
+    }
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
     __syncthreads();
+    const int b = chunk;
+    const int64_t kvalid = sort_count(count, cap);
+    const int64_t base = (int64_t)b * kSortChunk;
+    if (base >= kvalid) return;   // uniform over the block; no valid chunk waits on it
+    const int n_here = (int)min((int64_t)kSortChunk, kvalid - base);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     uint32_t key[kSortItems];
     int32_t val[kSortItems];
@@ -256,36 +288,91 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(const uint32_
     }
     count_digits(key, base, kvalid, shift, cnt);
     __syncthreads();
-    // turn counts into this block's per-(wave, digit) output cursors
-    for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
-        unsigned run = hist_scan[(int64_t)d * nblocks + blockIdx.x];
+
+    // thread d owns digit d
+    const int d = threadIdx.x;
+    unsigned tot = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            const unsigned c = cnt[w][d];
-            cnt[w][d] = run;
-            run += c;
+    for (int w = 0; w < kSortWaves; ++w) tot += cnt[w][d];
+    int64_t gtot;
+    const int64_t dstart = block_exclusive_scan<int64_t>((int64_t)ghist[d], &gtot);   // first slot of digit d
+    uint64_t *my = status + (int64_t)b * kRadix + d;
+    int64_t excl = dstart;
+    if (b == 0) {
+        __hip_atomic_store(my, kStatInc | (uint64_t)(dstart + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(my, kStatAgg | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t acc = 0;
+        int j = b - 1;
+        int spins = 0;
+        while (true) {
+            const uint64_t st = __hip_atomic_load(status + (int64_t)j * kRadix + d, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = st & ~kStatValue;
+            if (flag == 0) {
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    gave_up = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            acc += (int64_t)(st & kStatValue);
+            if (flag == kStatInc) break;
+            --j;
         }
+        excl = acc;
+        __hip_atomic_store(my, kStatInc | (uint64_t)(acc + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    gbase[d] = excl;
+    unsigned ltot;
+    const unsigned ls = block_exclusive_scan<unsigned>(tot, &ltot);
+    lstart[d] = ls;
+    // per-(wave, digit) cursors into the staging buffer
+    unsigned run = ls;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+        const unsigned c = cnt[w][d];
+        cnt[w][d] = run;
+        run += c;
     }
     __syncthreads();
+    if (gave_up) return;   // offsets unknown: write nothing (the error word is set)
+
+    // stage the chunk in digit order (stable: waves in order, lanes in order within a wave)
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
         const bool ok = idx < kvalid;
         const uint64_t valid = __ballot(ok);
         if (valid == 0) break;
-        const unsigned d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid);
-        const unsigned pos = cnt[wave][d] + (unsigned)__popcll(peers & lanemask_lt());
+        const unsigned dg = (key[r] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(dg, valid);
+        const unsigned pos = cnt[wave][dg] + (unsigned)__popcll(peers & lanemask_lt());
         __builtin_amdgcn_wave_barrier();
-        if (ok && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
+        if (ok && (peers & lanemask_lt()) == 0) cnt[wave][dg] += (unsigned)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
         if (ok) {
-            vals_out[pos] = val[r];
-            if (keys64_out)
-                keys64_out[pos] = ((uint64_t)key[r] << 32) | (uint64_t)__float_as_uint(depth[val[r]]);
-            else
-                keys_out[pos] = key[r];
+            skey[pos] = key[r];
+            sval[pos] = val[r];
         }
+    }
+    __syncthreads();
+
+    // write out: consecutive threads take consecutive staged keys, so each digit's run of
+    // this chunk is written by consecutive lanes to consecutive addresses
+    for (int i = threadIdx.x; i < n_here; i += kSortBlock) {
+        const uint32_t k = skey[i];
+        const int32_t v = sval[i];
+        const unsigned dg = (k >> shift) & (kRadix - 1);
+        const int64_t g = gbase[dg] + (i - (int)lstart[dg]);
+        if (g < 0 || g >= kvalid) continue;   // unreachable when the counts are consistent
+        vals_out[g] = v;
+        if (keys64_out)
+            keys64_out[g] = ((uint64_t)k << 32) | (uint64_t)__float_as_uint(depth[v]);
+        else
+            keys_out[g] = k;
     }
 }
 
@@ -374,10 +461,14 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *__restrict__ p, 
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ counters,
-                                                     int64_t cap, int32_t n_tiles, int32_t *__restrict__ ranges)
+// [start, end) of each tile's run. Thread 0 also folds the sort's error word into the
+// overflow flag (value 2: a look-back wait gave up; the list is not valid).
+__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict__ keys, int64_t *__restrict__ counters,
+                                                     int64_t cap, int32_t n_tiles, int32_t *__restrict__ ranges,
+                                                     const int64_t *__restrict__ err)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && *err) counters[1] |= *err;
     const int64_t kv = sort_count(counters, cap);
     if (k >= kv) return;
     const uint64_t t = keys[k] >> 32;
@@ -387,9 +478,6 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict_
 }
 
 // ------------------------------------------------------------------------ work list
-
-// Tiles with at least this many list entries are split into four quarter items.
-constexpr int kSplitLen = 256;
 
 __device__ inline int length_bucket(int len)
 {
@@ -405,7 +493,7 @@ __global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ s
 
 // Per-block bucket histogram in LDS, then one global atomic per non-empty bucket.
 __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restrict__ ranges, int n_tiles,
-                                                          int32_t *__restrict__ sched)
+                                                          int split_len, int split_parts, int32_t *__restrict__ sched)
 {
     __shared__ int cnt[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
@@ -413,7 +501,7 @@ __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restr
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_tiles) {
         const int len = ranges[2 * t + 1] - ranges[2 * t];
-        atomicAdd(&cnt[length_bucket(len)], len >= kSplitLen ? 4 : 1);
+        atomicAdd(&cnt[length_bucket(len)], len >= split_len ? split_parts : 1);
     }
     __syncthreads();
     if (threadIdx.x < kSchedNumBuckets && cnt[threadIdx.x])
@@ -423,7 +511,7 @@ __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restr
 // Each block reserves one contiguous run per bucket (one global atomic per bucket), then
 // hands out positions inside its runs with LDS atomics. Order inside a bucket is free.
 __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restrict__ ranges, int n_tiles,
-                                                         int32_t *__restrict__ sched)
+                                                         int split_len, int split_parts, int32_t *__restrict__ sched)
 {
     __shared__ int cnt[kSchedNumBuckets], base[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
@@ -433,7 +521,7 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
     if (t < n_tiles) {
         len = ranges[2 * t + 1] - ranges[2 * t];
         b = length_bucket(len);
-        n = len >= kSplitLen ? 4 : 1;
+        n = len >= split_len ? split_parts : 1;
         atomicAdd(&cnt[b], n);
     }
     __syncthreads();
@@ -447,11 +535,12 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
             int tot = 0;
             for (int j = 0; j < kSchedNumBuckets; ++j) tot += sched[kSchedBuckets + j];
             sched[kSchedItems] = tot;
+            sched[kSchedParts] = split_parts;
         }
     }
     __syncthreads();
     if (t >= n_tiles) return;
-    const int split = len >= kSplitLen;
+    const int split = len >= split_len;
     const int pos = base[b] + atomicAdd(&cnt[b], n);
     int32_t *items = sched + kSchedHeader;
     for (int part = 0; part < n; ++part) items[pos + part] = (t << 3) | (split << 2) | part;
@@ -462,36 +551,19 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 // Workspace: depth-sort buffers (two key/value pairs over P splats), per-rank emit offsets,
 // scan partial sums, one 32-bit key/value pair over the capacity (the other pair of the
 // tile-sort ping-pong lives in bins->keys / bins->ids until the last pass overwrites them),
-// and the radix histogram table.
+// then a region cleared at the start of every call: the look-back status words of every
+// pass, the digit histograms, the chunk tickets and an error word.
+constexpr int kDepthPasses = 4;
+constexpr int kMaxTilePasses = 4;
+
 struct BinLayout {
-    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, scan_sums, tkey, tval, hist, hist_sums, total;
-    int64_t depth_nb, tile_nb, hist_n;
+    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, scan_sums, tkey, tval;
+    size_t zero_begin, stat_depth, stat_tile, ghist_depth, ghist_tile, tickets, err, total;
+    int64_t depth_nb, tile_nb;
+    int tile_passes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-static BinLayout bin_layout(int64_t n_splats, int64_t cap)
-{
-    BinLayout L{};
-    L.depth_nb = (n_splats + kSortChunk - 1) / kSortChunk;
-    L.tile_nb = (cap + kSortChunk - 1) / kSortChunk;
-    L.hist_n = (L.depth_nb > L.tile_nb ? L.depth_nb : L.tile_nb) * kRadix;
-    const size_t p4 = align256((size_t)n_splats * 4);
-    size_t o = 0;
-    L.dkeyA = o;     o += p4;
-    L.dvalA = o;     o += p4;
-    L.dkeyB = o;     o += p4;
-    L.dvalB = o;     o += p4;
-    L.dcount = o;    o += 256;
-    L.offsets = o;   o += align256((size_t)n_splats * sizeof(int64_t));
-    L.scan_sums = o; o += align256((size_t)(scan_blocks(n_splats) + 1) * sizeof(int64_t));
-    L.tkey = o;      o += align256((size_t)cap * 4);
-    L.tval = o;      o += align256((size_t)cap * 4);
-    L.hist = o;      o += align256((size_t)L.hist_n * sizeof(unsigned));
-    L.hist_sums = o; o += align256((size_t)(scan_blocks(L.hist_n) + 1) * sizeof(unsigned));
-    L.total = o;
-    return L;
-}
 
 static int tile_bits(int32_t n_tiles)
 {
@@ -500,20 +572,38 @@ static int tile_bits(int32_t n_tiles)
     return tb;
 }
 
-// One stable LSD pass: histogram, scan of the digit-major table, scatter.
-static int radix_pass(const uint32_t *kin, const int32_t *vin, const int64_t *count, int64_t cap, int shift,
-                      int64_t nb, unsigned *hist, unsigned *hist_sums, uint32_t *kout, int32_t *vout,
-                      uint64_t *keys64, const float *depth, hipStream_t st)
+static int tile_passes_for(int32_t n_tiles)
 {
-    if (nb == 0) return GS_OK;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortBlock), 0, st, kin, count, cap, shift,
-                       (int)nb, hist);
-    const int rc = scan_exclusive<unsigned, unsigned>(ArrayLoad<unsigned>{hist}, nb * kRadix, hist, hist_sums,
-                                                      nullptr, nullptr, -1, st);
-    if (rc != GS_OK) return rc;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortBlock), 0, st, kin, vin, count, cap,
-                       shift, (int)nb, hist, kout, vout, keys64, depth);
-    return check_launch("radix pass");
+    return max(1, (tile_bits(n_tiles) + kRadixBits - 1) / kRadixBits);
+}
+
+static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
+{
+    BinLayout L{};
+    L.depth_nb = (n_splats + kSortChunk - 1) / kSortChunk;
+    L.tile_nb = (cap + kSortChunk - 1) / kSortChunk;
+    L.tile_passes = tile_passes_for(n_tiles);
+    const size_t p4 = align256((size_t)n_splats * 4);
+    const size_t stat_row = (size_t)kRadix * sizeof(uint64_t);
+    size_t o = 0;
+    L.dkeyA = o;       o += p4;
+    L.dvalA = o;       o += p4;
+    L.dkeyB = o;       o += p4;
+    L.dvalB = o;       o += p4;
+    L.dcount = o;      o += 256;
+    L.offsets = o;     o += align256((size_t)n_splats * sizeof(int64_t));
+    L.scan_sums = o;   o += align256((size_t)(scan_blocks(n_splats) + 1) * sizeof(int64_t));
+    L.tkey = o;        o += align256((size_t)cap * 4);
+    L.tval = o;        o += align256((size_t)cap * 4);
+    L.zero_begin = o;
+    L.stat_depth = o;  o += align256((size_t)kDepthPasses * L.depth_nb * stat_row);
+    L.stat_tile = o;   o += align256((size_t)L.tile_passes * L.tile_nb * stat_row);
+    L.ghist_depth = o; o += align256((size_t)kDepthPasses * kRadix * sizeof(unsigned));
+    L.ghist_tile = o;  o += align256((size_t)kMaxTilePasses * kRadix * sizeof(unsigned));
+    L.tickets = o;     o += 256;
+    L.err = o;         o += 256;
+    L.total = o;
+    return L;
 }
 
 }  // namespace gsx
@@ -524,8 +614,11 @@ static int build_schedule(gs_bins *bins, hipStream_t st)
 {
     const unsigned g = grid_for(bins->n_tiles, 256);
     hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule);
-    hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, bins->schedule);
-    hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, bins->schedule);
+    const gs_tuning &tu = current_tuning();
+    hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
+                       tu.split_parts, bins->schedule);
+    hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
+                       tu.split_parts, bins->schedule);
     return check_launch("gs_bin_and_sort");
 }
 
@@ -536,9 +629,8 @@ extern "C" int64_t gs_schedule_size(int32_t n_tiles)
 
 extern "C" size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles)
 {
-    (void)n_tiles;
-    if (n_splats < 0 || capacity < 1) return 0;
-    return bin_layout(n_splats, capacity).total;
+    if (n_splats < 0 || capacity < 1 || n_tiles < 1) return 0;
+    return bin_layout(n_splats, capacity, n_tiles).total;
 }
 
 extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
@@ -555,7 +647,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
     const int64_t cap = bins->capacity;
-    const BinLayout L = bin_layout(n_splats, cap);
+    const BinLayout L = bin_layout(n_splats, cap, bins->n_tiles);
     if (!workspace || workspace_bytes < L.total)
         return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort: workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -565,8 +657,10 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int64_t *dcount = (int64_t *)(ws + L.dcount);
     int64_t *offsets = (int64_t *)(ws + L.offsets);
     int64_t *scan_sums = (int64_t *)(ws + L.scan_sums);
-    unsigned *hist = (unsigned *)(ws + L.hist);
-    unsigned *hist_sums = (unsigned *)(ws + L.hist_sums);
+    uint64_t *stat_depth = (uint64_t *)(ws + L.stat_depth), *stat_tile = (uint64_t *)(ws + L.stat_tile);
+    unsigned *ghist_depth = (unsigned *)(ws + L.ghist_depth), *ghist_tile = (unsigned *)(ws + L.ghist_tile);
+    int32_t *tickets = (int32_t *)(ws + L.tickets);
+    int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
     // ranges start empty: (0, 0)
@@ -576,16 +670,23 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, st, (int32_t *)bins->counters, 4, 0);
         return build_schedule(bins, st);
     }
+    int rc = gs_zero(ws + L.zero_begin, L.total - L.zero_begin, st);
+    if (rc != GS_OK) return rc;
 
     // 1. depth order of the splats (four 8-bit passes: the result is back in A)
     hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, s->tiles_touched,
                        s->depth, n_splats, dkeyA, dvalA, dcount);
-    int rc = GS_OK;
-    for (int pass = 0; pass < 4 && rc == GS_OK; ++pass) {
+    hipLaunchKernelGGL(radix_global_hist_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, dkeyA,
+                       (const int64_t *)dcount, n_splats, kDepthPasses, ghist_depth);
+    for (int pass = 0; pass < kDepthPasses; ++pass) {
         const bool even = (pass & 1) == 0;
-        rc = radix_pass(even ? dkeyA : dkeyB, even ? dvalA : dvalB, dcount, n_splats, pass * kRadixBits, L.depth_nb,
-                        hist, hist_sums, even ? dkeyB : dkeyA, even ? dvalB : dvalA, nullptr, nullptr, st);
+        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st,
+                           even ? dkeyA : dkeyB, even ? dvalA : dvalB, (const int64_t *)dcount, n_splats,
+                           pass * kRadixBits, ghist_depth + pass * kRadix,
+                           stat_depth + (int64_t)pass * L.depth_nb * kRadix, tickets + pass, even ? dkeyB : dkeyA,
+                           even ? dvalB : dvalA, (uint64_t *)nullptr, (const float *)nullptr, err);
     }
+    rc = check_launch("depth sort");
     if (rc != GS_OK) return rc;
     const int32_t *rank_ids = dvalA;
 
@@ -596,7 +697,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
 
     // 3-4. emit, then stable passes by tile id. The last pass reads the workspace pair W and
     // writes bins; earlier passes alternate between W and the pair stored in bins' buffers.
-    const int passes = max(1, (tile_bits(bins->n_tiles) + kRadixBits - 1) / kRadixBits);
+    const int passes = L.tile_passes;
     uint32_t *kW = (uint32_t *)(ws + L.tkey), *kX = (uint32_t *)bins->keys;
     int32_t *vW = (int32_t *)(ws + L.tval), *vX = bins->ids;
     const bool emit_to_W = ((passes - 1) & 1) == 0;
@@ -604,20 +705,25 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int32_t *vin = emit_to_W ? vW : vX;
     hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
                        s->tiles_touched, (const int4 *)s->rect, cams, (int)n_cams, n_splats, cap, kin, vin);
-    rc = check_launch("emit");
-    for (int pass = 0; pass < passes && rc == GS_OK; ++pass) {
+    hipLaunchKernelGGL(radix_global_hist_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, kin, K, cap,
+                       passes, ghist_tile);
+    for (int pass = 0; pass < passes; ++pass) {
         const bool last = pass == passes - 1;
         uint32_t *kout = kin == kW ? kX : kW;
         int32_t *vout = vin == vW ? vX : vW;
-        rc = radix_pass(kin, vin, K, cap, pass * kRadixBits, L.tile_nb, hist, hist_sums, last ? nullptr : kout,
-                        last ? bins->ids : vout, last ? bins->keys : nullptr, s->depth, st);
+        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, kin, vin, K, cap,
+                           pass * kRadixBits, ghist_tile + pass * kRadix,
+                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, tickets + kDepthPasses + pass,
+                           last ? (uint32_t *)nullptr : kout, last ? bins->ids : vout,
+                           last ? bins->keys : (uint64_t *)nullptr, s->depth, err);
         kin = kout;
         vin = vout;
     }
+    rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
 
     // 5. tile ranges and the work list
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys, K, cap, bins->n_tiles,
-                       bins->ranges);
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys, bins->counters, cap,
+                       bins->n_tiles, bins->ranges, (const int64_t *)err);
     return build_schedule(bins, st);
 }

@@ -40,6 +40,7 @@ constexpr int kSchedItems = 0;      // number of items
 constexpr int kSchedFwd = 1;        // forward kernel: next item, then finished-wave count
 constexpr int kSchedBwd = 3;        // backward kernel: next item, then finished-wave count
 constexpr int kSchedFused = 5;      // fused kernel: next item, then finished-wave count
+constexpr int kSchedParts = 7;      // parts per split tile (2 or 4) the list was built with
 constexpr int kSchedBuckets = 8;    // 16 bucket counts
 constexpr int kSchedCursors = 24;   // 16 bucket cursors
 constexpr int kSchedHeader = 64;
@@ -47,6 +48,7 @@ constexpr int kSchedNumBuckets = 16;
 
 // Workgroups for a persistent launch: enough waves to fill every SIMD of the device.
 unsigned persistent_blocks(int waves_per_block);
+const gs_tuning &current_tuning();
 
 // ------------------------------------------------------------------ host-side status
 
@@ -101,23 +103,33 @@ __device__ inline float wave_sum_to_lane63(float v)
     return v;
 }
 
-// The same reduction for float64 values: DPP moves 32 bits, so each half moves separately.
-template <int kCtrl, int kRowMask>
-__device__ inline double dpp_f64(double v)
+// Sums within each row of 16 lanes (every lane of the row ends with its row's total),
+// with butterflies whose DPP patterns write every lane, so no lane keeps an old value.
+// float64 values move as two 32-bit halves.
+template <int kCtrl>
+__device__ inline double dpp_all_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRowMask, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRowMask, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline double wave_sum_to_lane63(double v)
+__device__ inline double row_sum(double v)
 {
-    v += dpp_f64<0xB1, 0xF>(v);
-    v += dpp_f64<0x4E, 0xF>(v);
-    v += dpp_f64<0x141, 0xF>(v);
-    v += dpp_f64<0x140, 0xF>(v);
-    v += dpp_f64<0x142, 0xA>(v);
-    v += dpp_f64<0x143, 0xC>(v);
+    v += dpp_all_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_all_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_all_f64<0x141>(v);   // row_half_mirror
+    v += dpp_all_f64<0x140>(v);   // row_mirror
+    return v;
+}
+
+__device__ inline float row_sum(float v)
+{
+    // these forms fold into v_add_f32 with a DPP operand
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
     return v;
 }
 

@@ -3,12 +3,14 @@
 //
 // Work items. gs_bin_and_sort leaves a work list of tiles in decreasing list length
 // (longest first). A tile with a short list is one item: one wave64, four horizontally
-// adjacent pixels per lane. A tile with a long list is four items, each a 16x4-pixel
-// quarter at one pixel per lane, so that its walk, the critical path of the launch, is
-// split over four waves. The kernels are persistent: every wave takes items from an
+// adjacent pixels per lane. A tile with a long list (the length threshold and the split
+// are launch tuning, gs_tuning) is two 16x8-pixel halves at two pixels per lane or four
+// 16x4-pixel quarters at one pixel per lane, so that its walk, the critical path of the
+// launch, is split over several waves. The kernels are persistent: every wave takes items from an
 // atomic counter until the list is exhausted, and the last wave out resets the counter
-// so the next launch (or graph replay) starts from zero. A wave raises its issue priority
-// (s_setprio) while it works on a quarter item, so that the longest walks keep their SIMD.
+// so the next launch (or graph replay) starts from zero. A wave may raise its issue
+// priority (s_setprio) while it works on a split item, so that the longest walks keep
+// their SIMD.
 //
 // Records. A wave walks its list in batches of 64 entries. For each batch every lane
 // gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
@@ -34,6 +36,9 @@ namespace gsx {
 
 constexpr int kBlockWaves = 4;
 constexpr int kBatch = kWave;   // list entries staged per wave and batch
+// Up to this many contributing lanes, a splat's gradient terms are added into its LDS slot
+// with atomics; above it the wave reduces them with DPP first.
+constexpr int kLdsAtomicLanes = 8;
 
 // The wave's LDS slice for one batch of records.
 __device__ inline RasterRec *wave_slice()
@@ -81,26 +86,24 @@ struct ItemPixels {
     int64_t pix0;        // packed index of (row, col0)
 };
 
-// Decodes item = tile << 3 | quarter << 2 | part into this lane's pixels.
+// Decodes item = tile << 3 | split << 2 | part into this lane's pixels. A whole tile (PX = 4)
+// is 16 rows of 4 lanes with 4 adjacent pixels each; a split tile's part is 16 / (4 PX)
+// of its rows: halves (PX = 2, 8 rows of 8 lanes) or quarters (PX = 1, 4 rows of 16 lanes).
 template <int PX>
 __device__ inline ItemPixels item_pixels(const gs_camera *__restrict__ cams, int n_cams,
                                          const int32_t *__restrict__ ranges, int item, int lane)
 {
+    constexpr int kLanesPerRow = kTile / PX;
     ItemPixels t;
-    const int tile = item >> 3, part = item & 3;
+    const int tile = item >> 3, part = PX == 4 ? 0 : (item & 3);
     const int c = camera_of_tile(cams, n_cams, tile);
     const int local = tile - cams[c].tile_offset;
     const int tx_n = cams[c].tiles_x;
     const int ty = local / tx_n, tx = local - ty * tx_n;
     t.W = cams[c].width;
     t.H = cams[c].height;
-    if (PX == 4) {
-        t.row = ty * kTile + (lane >> 2);
-        t.col0 = tx * kTile + (lane & 3) * 4;
-    } else {
-        t.row = ty * kTile + part * 4 + (lane >> 4);
-        t.col0 = tx * kTile + (lane & 15);
-    }
+    t.row = ty * kTile + part * (kWave / kLanesPerRow) + lane / kLanesPerRow;
+    t.col0 = tx * kTile + (lane % kLanesPerRow) * PX;
     t.pix0 = cams[c].pixel_offset + (int64_t)t.row * t.W + t.col0;
     t.start = ranges[2 * tile];
     t.end = ranges[2 * tile + 1];
@@ -181,13 +184,17 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
 #pragma unroll
         for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
         if (__ballot(tmax >= 0.f) == 0) break;          // every pixel of the item is finished
-        for (int j = 0; j < nb; ++j) {
-            if ((j & 7) == 7) {
+        // groups of 8 entries, with the all-finished test between groups, so that the inner
+        // loop has a single exit
+        for (int j0 = 0; j0 < nb; j0 += 8) {
+            if (j0 > 0) {
                 float m = ps.T[0];
 #pragma unroll
                 for (int q = 1; q < PX; ++q) m = fmaxf(m, ps.T[q]);
                 if (__ballot(m >= 0.f) == 0) break;
             }
+            const int j1 = min(j0 + 8, nb);
+            for (int j = j0; j < j1; ++j) {
             const RasterRec r = slice[j];
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
@@ -196,7 +203,7 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
 #pragma unroll
             for (int q = 0; q < PX; ++q) {
                 const double dx = (double)r.mx - ps.pxd[q];
-                float a = fminf(prm.alpha_max, alpha_raw(r, dx, bdy, cdl));
+                float a = __builtin_amdgcn_fmed3f(alpha_raw(r, dx, bdy, cdl), 0.f, prm.alpha_max);
                 a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
                 if (kVisited) ps.vis[q] += ps.T[q] >= 0.f ? 1 : 0;
                 const float Tn = ps.T[q] * (1.f - a);
@@ -207,6 +214,7 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 ps.c2[q] = __builtin_fmaf(r.c2, w, ps.c2[q]);
                 ps.last[q] = w > 0.f ? pos1 : ps.last[q];
                 ps.T[q] = stop ? -fabsf(ps.T[q]) : Tn;
+            }
             }
         }
     }
@@ -227,6 +235,77 @@ struct BwdOut {
     float *d_colors, *d_opac;
 };
 
+// Per-wave gradient sums of the batch being walked: one slot per staged record, holding
+//   sum v, sum v dx, sum v dy, sum v dx^2, sum v dx dy, sum v dy^2   (float64)
+//   sum alpha T dL/dC(k), k = 0..2                                 (float32)
+// over the wave's pixels. After each splat the wave fills that splat's slot in one of two
+// ways, chosen by the number of lanes with a composited pixel (wave-uniform):
+//   few lanes (small splats, the common case at 1M Gaussians): those lanes add their
+//     terms into the slot with LDS atomics, which conflict only among themselves;
+//   many lanes (large splats): a DPP reduction within each row of 16 lanes, and one lane
+//     per row adds the row's totals into the slot.
+// When the batch is done, lane j moves slot j to global memory with one atomic per term,
+// so the global atomics of a batch are 9 instructions with up to 64 distinct addresses.
+struct WaveAcc {
+    double d[6][kBatch];
+    float f[3][kBatch];
+};
+
+__device__ inline WaveAcc *wave_acc()
+{
+    __shared__ WaveAcc acc[kBlockWaves];
+    return &acc[__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
+}
+
+__device__ inline void acc_clear(WaveAcc *acc, int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc->d[k][lane] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc->f[k][lane] = 0.f;
+}
+
+__device__ inline void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline void lds_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Lane j < nb moves slot j (the splat of staged record j) to the global gradients and
+// clears it:
+//   dL/dmu' = -Y sum v Delta, with Y = -(2A, B; B, 2C) / log2(e)
+//   dL/dY = -1/2 sum v Delta Delta^T,  dL/dc(k) = sum alpha T dL/dC(k),  dL/do = sum v / o
+__device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nb, int lane, const BwdOut &out)
+{
+    // LDS operations of one wave complete in order, so the slot reads below see every add
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nb) {
+        const double s_v = acc->d[0][lane], s_x = acc->d[1][lane], s_y = acc->d[2][lane];
+        const double s_xx = acc->d[3][lane], s_xy = acc->d[4][lane], s_yy = acc->d[5][lane];
+        const float s_c0 = acc->f[0][lane], s_c1 = acc->f[1][lane], s_c2 = acc->f[2][lane];
+        if (s_v != 0.0 || s_xx != 0.0 || s_c0 != 0.f || s_c1 != 0.f || s_c2 != 0.f) {
+            const RasterRec r = slice[lane];
+            const int id = r.pad;
+            const double il = 1.0 / kLog2eD;
+            atomic_add_f64(&out.d_mean2d[id], (2.0 * r.A * s_x + r.B * s_y) * il);
+            atomic_add_f64(&out.d_mean2d[out.n_splats + id], (r.B * s_x + 2.0 * r.C * s_y) * il);
+            atomic_add_f64(&out.d_conic[id], -0.5 * s_xx);
+            atomic_add_f64(&out.d_conic[out.n_splats + id], -0.5 * s_xy);
+            atomic_add_f64(&out.d_conic[2 * out.n_splats + id], -0.5 * s_yy);
+            atomic_add_f32(&out.d_colors[r.src], s_c0);
+            atomic_add_f32(&out.d_colors[out.n_gauss + r.src], s_c1);
+            atomic_add_f32(&out.d_colors[2 * out.n_gauss + r.src], s_c2);
+            atomic_add_f32(&out.d_opac[r.src], (float)(s_v / (double)r.o));
+        }
+    }
+    acc_clear(acc, lane);
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Back-to-front walk (Sec. 3.1). On entry T holds T_final, last the start positions and
 // g0..g2 the upstream gradient dL/dC of each pixel.
 template <int PX>
@@ -245,6 +324,8 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
 #pragma unroll
     for (int q = 0; q < PX; ++q) gS[q] = 0.f;
     RasterRec *slice = wave_slice();
+    WaveAcc *acc = wave_acc();
+    acc_clear(acc, lane);
     const int kend = t.start + maxlast;
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
     Gathered next = gather(rr, ids, max(t.start, kend - kBatch), kend - max(t.start, kend - kBatch), lane);
@@ -259,14 +340,13 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         for (int j = nb - 1; j >= 0; --j) {
             const int pos = bstart + j - t.start;
             const RasterRec r = slice[j];
-            const int id = r.pad;
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
             // per-lane sums over the lane's pixels; the lane's pixels share one row, so the
-            // dy-weighted sums follow from sum v and sum v dx after the loop. The position
-            // sums are float64: dL/dY along the thin axis of a needle-like splat is a small
-            // difference of these sums, which float32 rounding would swamp.
+            // dy-weighted sums follow from sum v and sum v dx. The position sums are float64:
+            // dL/dY along the thin axis of a needle-like splat is a small difference of
+            // these sums, which float32 rounding would swamp.
             double s_v = 0.0, s_x = 0.0, s_xx = 0.0;
             float s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
             float live_sum = 0.f;
@@ -276,7 +356,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 // w = 0 and v = 0, and the pair changes nothing
                 const double dx = (double)r.mx - ps.pxd[q];
                 const float a_raw = alpha_raw(r, dx, bdy, cdl);
-                float a = fminf(prm.alpha_max, a_raw);
+                float a = __builtin_amdgcn_fmed3f(a_raw, 0.f, prm.alpha_max);
                 a = pos < ps.last[q] ? a : 0.f;
                 a = a < prm.alpha_min ? 0.f : a;
                 live_sum += a;
@@ -296,32 +376,47 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 s_x += vx;
                 s_xx = __builtin_fma(vx, dx, s_xx);
             }
-            if (__ballot(live_sum > 0.f) == 0) continue;
+            const uint64_t live = __ballot(live_sum > 0.f);
+            if (live == 0) continue;
             double s_y = s_v * dy, s_xy = s_x * dy;
             double s_yy = s_y * dy;
-            s_v = wave_sum_to_lane63(s_v);
-            s_x = wave_sum_to_lane63(s_x);
-            s_y = wave_sum_to_lane63(s_y);
-            s_xx = wave_sum_to_lane63(s_xx);
-            s_xy = wave_sum_to_lane63(s_xy);
-            s_yy = wave_sum_to_lane63(s_yy);
-            s_c0 = wave_sum_to_lane63(s_c0);
-            s_c1 = wave_sum_to_lane63(s_c1);
-            s_c2 = wave_sum_to_lane63(s_c2);
-            if (lane == kWave - 1) {
-                // Y = -(2A, B; B, 2C) / log2(e); dL/dmu' = -Y sum v Delta; dL/dY = -1/2 sum v Delta Delta^T
-                const double il = 1.0 / kLog2eD;
-                atomic_add_f64(&out.d_mean2d[id], (2.0 * r.A * s_x + r.B * s_y) * il);
-                atomic_add_f64(&out.d_mean2d[out.n_splats + id], (r.B * s_x + 2.0 * r.C * s_y) * il);
-                atomic_add_f64(&out.d_conic[id], -0.5 * s_xx);
-                atomic_add_f64(&out.d_conic[out.n_splats + id], -0.5 * s_xy);
-                atomic_add_f64(&out.d_conic[2 * out.n_splats + id], -0.5 * s_yy);
-                atomic_add_f32(&out.d_colors[r.src], s_c0);
-                atomic_add_f32(&out.d_colors[out.n_gauss + r.src], s_c1);
-                atomic_add_f32(&out.d_colors[2 * out.n_gauss + r.src], s_c2);
-                atomic_add_f32(&out.d_opac[r.src], (float)(s_v / (double)r.o));
+            if (__popcll(live) <= kLdsAtomicLanes) {
+                if (live_sum > 0.f) {
+                    lds_add(&acc->d[0][j], s_v);
+                    lds_add(&acc->d[1][j], s_x);
+                    lds_add(&acc->d[2][j], s_y);
+                    lds_add(&acc->d[3][j], s_xx);
+                    lds_add(&acc->d[4][j], s_xy);
+                    lds_add(&acc->d[5][j], s_yy);
+                    lds_add(&acc->f[0][j], s_c0);
+                    lds_add(&acc->f[1][j], s_c1);
+                    lds_add(&acc->f[2][j], s_c2);
+                }
+            } else {
+                // reduce within rows of 16 lanes; one lane per row adds its row's totals
+                s_v = row_sum(s_v);
+                s_x = row_sum(s_x);
+                s_y = row_sum(s_y);
+                s_xx = row_sum(s_xx);
+                s_xy = row_sum(s_xy);
+                s_yy = row_sum(s_yy);
+                s_c0 = row_sum(s_c0);
+                s_c1 = row_sum(s_c1);
+                s_c2 = row_sum(s_c2);
+                if ((lane & 15) == 15) {
+                    lds_add(&acc->d[0][j], s_v);
+                    lds_add(&acc->d[1][j], s_x);
+                    lds_add(&acc->d[2][j], s_y);
+                    lds_add(&acc->d[3][j], s_xx);
+                    lds_add(&acc->d[4][j], s_xy);
+                    lds_add(&acc->d[5][j], s_yy);
+                    lds_add(&acc->f[0][j], s_c0);
+                    lds_add(&acc->f[1][j], s_c1);
+                    lds_add(&acc->f[2][j], s_c2);
+                }
             }
         }
+        acc_flush(slice, acc, nb, lane, out);
     }
 }
 
@@ -357,16 +452,20 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
 template <bool kVisited>
 __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o)
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     for (;;) {
         const int item = next_item(sched, kSchedFwd, n_items, lane);
         if (item < 0) break;
         if (item & 4) {
-            __builtin_amdgcn_s_setprio(2);
-            fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o);
+            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (parts == 4)
+                fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o);
+            else
+                fwd_item<2, kVisited>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o);
             __builtin_amdgcn_s_setprio(0);
         } else {
             fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o);
@@ -403,18 +502,23 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
     bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
 }
 
-__global__ __launch_bounds__(kWave * kBlockWaves) void raster_bwd_kernel(
+__global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_bwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out)
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out,
+    int prio)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     for (;;) {
         const int item = next_item(sched, kSchedBwd, n_items, lane);
         if (item < 0) break;
         if (item & 4) {
-            __builtin_amdgcn_s_setprio(2);
-            bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
+            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (parts == 4)
+                bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
+            else
+                bwd_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
             bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
@@ -468,19 +572,23 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
     bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
 }
 
-__global__ __launch_bounds__(kWave * kBlockWaves) void raster_fused_kernel(
+__global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_fused_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FusedIO io,
-    BwdOut out)
+    BwdOut out, int prio)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
+    const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     for (;;) {
         const int item = next_item(sched, kSchedFused, n_items, lane);
         if (item < 0) break;
         if (item & 4) {
-            __builtin_amdgcn_s_setprio(2);
-            fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out);
+            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (parts == 4)
+                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out);
+            else
+                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
             fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out);
@@ -516,10 +624,10 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     const FwdOut o{n_pixels, image, T_final, last, visited};
     if (visited)
         hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority);
     else
         hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority);
     return check_launch("gs_rasterize_fwd");
 }
 
@@ -550,7 +658,7 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, in, out);
+                       (int)n_cams, *prm, in, out, current_tuning().split_priority);
     return check_launch("gs_rasterize_bwd");
 }
 
@@ -571,6 +679,6 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
     hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, io, out);
+                       (int)n_cams, *prm, io, out, current_tuning().split_priority);
     return check_launch("gs_rasterize_fused_l2");
 }

@@ -34,6 +34,10 @@ int check_hip(hipError_t e, const char *what)
 
 int check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
 
+static gs_tuning g_tuning = {256, 4, 32, 1};
+
+const gs_tuning &current_tuning() { return g_tuning; }
+
 unsigned persistent_blocks(int waves_per_block)
 {
     static int cached_dev = -1, cached_cus = 0;
@@ -46,11 +50,7 @@ unsigned persistent_blocks(int waves_per_block)
         cached_cus = cus;
         cached_dev = dev;
     }
-    // GSX_PERSISTENT_BLOCKS overrides the grid (tuning and diagnosis)
-    static const char *env = getenv("GSX_PERSISTENT_BLOCKS");
-    if (env && atoi(env) > 0) return (unsigned)atoi(env);
-    // 4 SIMDs per CU, up to 8 resident waves per SIMD
-    return (unsigned)((cached_cus * 32 + waves_per_block - 1) / waves_per_block);
+    return (unsigned)((cached_cus * g_tuning.waves_per_cu + waves_per_block - 1) / waves_per_block);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(uint4 *__restrict__ p16, int64_t n16, unsigned char *__restrict__ tail,
@@ -210,4 +210,23 @@ extern "C" int gs_graph_destroy(gs_graph *graph)
     delete graph;
     const int rc = check_hip(e1, "hipGraphExecDestroy");
     return rc != GS_OK ? rc : check_hip(e2, "hipGraphDestroy");
+}
+
+extern "C" int gs_set_tuning(const gs_tuning *t)
+{
+    clear_error();
+    if (!t) return set_error(GS_ERR_INVALID, "gs_set_tuning: null argument");
+    if (t->split_len < 1 || (t->split_parts != 2 && t->split_parts != 4) || t->waves_per_cu < 4 ||
+        t->waves_per_cu > 64)
+        return set_error(GS_ERR_INVALID, "gs_set_tuning: split_len >= 1, split_parts in {2, 4}, waves_per_cu in [4, 64]");
+    g_tuning = *t;
+    return GS_OK;
+}
+
+extern "C" int gs_get_tuning(gs_tuning *t)
+{
+    clear_error();
+    if (!t) return set_error(GS_ERR_INVALID, "gs_get_tuning: null argument");
+    *t = g_tuning;
+    return GS_OK;
 }

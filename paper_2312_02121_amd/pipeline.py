@@ -30,6 +30,12 @@ def make_params(alpha_min: float = STANDARD_PARAMS["alpha_min"], alpha_max: floa
     return abi.GsParams(float(np.float32(alpha_min)), float(np.float32(alpha_max)), float(np.float32(T_min)), 0)
 
 
+def check_sort_flag(flag: int):
+    """gs_bin_and_sort sets bit 2 of counters[1] when a look-back wait of its sort gave up."""
+    if flag & 2:
+        raise RuntimeError("gs_bin_and_sort: the single-pass sort's look-back did not complete; the list is invalid")
+
+
 def current_stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
@@ -233,8 +239,10 @@ class Rasterizer:
                              _ptr(self.visited), stream)
 
     def read_count(self) -> tuple[int, bool]:
+        """(K, overflowed). Raises if the sort reported an internal failure (flag bit 2)."""
         c = self.bins.counters.cpu()
-        return int(c[0]), bool(c[1])
+        check_sort_flag(int(c[1]))
+        return int(c[0]), bool(int(c[1]) & 1)
 
     def forward(self, g: GaussianSet, check_overflow: bool = True) -> ForwardState:
         self.project(g)
@@ -389,7 +397,9 @@ class TrainStep:
             events[len(self.STAGES)].record()
 
     def overflowed(self) -> bool:
-        return bool(self.r.bins.counters[1].item())
+        flag = int(self.r.bins.counters[1].item())
+        check_sort_flag(flag)
+        return bool(flag & 1)
 
 
 class GraphStep:

@@ -70,3 +70,19 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(abi, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         abi.lib()
+
+
+def test_tuning_is_validated_and_round_trips(lib):
+    before = abi.gs_get_tuning().as_dict()
+    assert before == {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1}
+    for bad in ({"split_len": 0}, {"split_parts": 3}, {"waves_per_cu": 2}, {"waves_per_cu": 65}):
+        t = abi.GsTuning(**{**before, **bad})
+        with pytest.raises(abi.GsError):
+            abi.gs_set_tuning(t)
+        assert abi.gs_get_tuning().as_dict() == before
+    want = {"split_len": 1024, "split_parts": 2, "waves_per_cu": 16, "split_priority": 0}
+    abi.gs_set_tuning(abi.GsTuning(**want))
+    try:
+        assert abi.gs_get_tuning().as_dict() == want
+    finally:
+        abi.gs_set_tuning(abi.GsTuning(**before))
