@@ -109,7 +109,7 @@ typedef struct gs_splats {
     float *rec;              /* [P][12], 16-byte aligned */
     float *raster;           /* [P][16], 64-byte aligned: compositing record written by gs_project and
                                 read by the rasterizer; its layout is private to the library */
-    float *depth;            /* [P] t_z, 0 when culled */
+    float *depth;            /* [P] t_z (not written for a culled slot) */
     int32_t *rect;           /* [P][4] tile box x0, y0, x1, y1, inclusive, camera-local */
     int32_t *tiles_touched;  /* [P] tiles in the box; 0 = culled */
     int64_t capacity;        /* P */
@@ -142,8 +142,9 @@ typedef struct gs_bins {
 
 /*
  * Launch tuning of the rasterizer (not part of the method: results do not depend on it).
- * gs_bin_and_sort builds the work list with split_len and split_parts; the rasterize
- * calls launch with waves_per_cu and split_priority. The setting is process-wide and is
+ * gs_bin_and_sort builds the work list with split_len and split_parts and picks its first
+ * sort pass with generate_entries; the rasterize calls launch with waves_per_cu and
+ * split_priority. The setting is process-wide and is
  * read when a call is made, so a captured graph keeps the tuning it was captured with.
  */
 typedef struct gs_tuning {
@@ -153,6 +154,10 @@ typedef struct gs_tuning {
                                 4 (16x4-pixel quarters, 1 pixel per lane) */
     int32_t waves_per_cu;    /* persistent grid: waves launched per compute unit, 4..64 */
     int32_t split_priority;  /* nonzero: a wave raises its issue priority on a split item */
+    int32_t generate_entries;/* nonzero: the first tile-sort pass generates the list entries from
+                                the boxes itself instead of reading them from an emitted list
+                                (less traffic when splats cover many tiles) */
+    int32_t reserved[3];
 } gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */
@@ -200,7 +205,9 @@ int gs_l2_grad(const float *image, const float *target, int64_t n, float *dL_dim
  * pair: R(q), Sigma = R S S^T R^T, t = T_cw [mu; 1], t' = P t, mu', J, Sigma' =
  * J R_cw Sigma R_cw^T J^T, Y = Sigma'^{-1}, box and tile count.
  * g: Gaussian planes. cams: device array of n_cams cameras whose proj_offset ranges
- * tile [0, n_splats). out: splat buffers of capacity >= n_splats.
+ * tile [0, n_splats). out: splat buffers of capacity >= n_splats; tiles_touched is written
+ * for every slot, the other fields only for slots with tiles_touched > 0 (a culled slot's
+ * record, depth and box are left as they were).
  * Errors: GS_ERR_INVALID for null pointers, n_cams < 1, n_splats < 0 or
  * n_splats > out->capacity.
  */
@@ -220,9 +227,10 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * (tiles in decreasing list length, long ones split into four parts). The sort is done as
  * a stable depth sort of the splats followed by a stable tile-id sort of the entries
  * emitted in depth order, which yields the same list. K is written to
- * bins->counters[0]; if K exceeds bins->capacity only the first `capacity` entries (in
- * depth order of their splats) are kept, counters[1] is set to 1 and the list is
- * incomplete: the caller reads the flag, regrows and calls again. counters[1] & 2 means a
+ * bins->counters[0]; if K exceeds bins->capacity the list is not built (every tile's
+ * range is empty, so a rasterize call made before the caller looks renders nothing and
+ * reads nothing from the list), counters[1] is set to 1, and the caller regrows and calls
+ * again. counters[1] & 2 means a
  * wait inside the single-pass sort gave up after its spin limit (the list is invalid; this
  * indicates a fault, not a capacity problem). workspace: device
  * memory of at least gs_bin_and_sort_workspace_size() bytes, contents free on entry and

@@ -1,9 +1,10 @@
 """Autotuner of the rasterizer's launch tuning (gs_tuning) for one batch of cameras.
 
-The work list and the persistent launch have four knobs (see gs_tuning in the C header):
-the list length at which a tile is split, the number of parts (16x8 halves or 16x4
-quarters), the persistent grid size in waves per compute unit, and whether a wave raises
-its priority on split items. None of them changes a result, only the time.
+The work list, the sort and the persistent launch have five knobs (see gs_tuning in the
+C header): the list length at which a tile is split, the number of parts (16x8 halves or
+16x4 quarters), the persistent grid size in waves per compute unit, whether a wave raises
+its priority on split items, and whether the first tile-sort pass generates the list
+entries itself. None of them changes a result, only the time.
 
 ``tune`` times a full training step (project, bin and sort, fused forward + loss +
 backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
@@ -30,11 +31,12 @@ KNOBS = {
     "split_parts": (2, 4),
     "waves_per_cu": (16, 32),
     "split_priority": (0, 1),
+    "generate_entries": (0, 1),
 }
 
 
 def default_tuning() -> dict:
-    return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1}
+    return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0}
 
 
 def apply(t: dict):

@@ -123,13 +123,16 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
             }
         }
     }
-    rec[3 * p + 0] = r0;
-    rec[3 * p + 1] = r1;
-    rec[3 * p + 2] = r2;
-    rrec[p] = rr;
-    depth_out[p] = dep;
-    rect_out[p] = box;
+    // a culled slot (tiles_touched = 0) is never listed, so only its count is written
     tiles_out[p] = tiles;
+    if (tiles > 0) {
+        rec[3 * p + 0] = r0;
+        rec[3 * p + 1] = r1;
+        rec[3 * p + 2] = r2;
+        rrec[p] = rr;
+        depth_out[p] = dep;
+        rect_out[p] = box;
+    }
 }
 
 }  // namespace gsx

@@ -142,10 +142,10 @@ def test_results_do_not_depend_on_launch_tuning(name):
     wl = {"c2_20k": lambda: synth.make_config(2, n_override=20_000), "c5_small": small_c5}[name]()
     ref_img = ref = None
     try:
-        for t in ({"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1},
-                  {"split_len": 1 << 30, "split_parts": 4, "waves_per_cu": 16, "split_priority": 0},
-                  {"split_len": 64, "split_parts": 2, "waves_per_cu": 16, "split_priority": 1},
-                  {"split_len": 1, "split_parts": 4, "waves_per_cu": 64, "split_priority": 0}):
+        for t in ({"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0},
+                  {"split_len": 1 << 30, "split_parts": 4, "waves_per_cu": 16, "split_priority": 0, "generate_entries": 1},
+                  {"split_len": 64, "split_parts": 2, "waves_per_cu": 16, "split_priority": 1, "generate_entries": 0},
+                  {"split_len": 1, "split_parts": 4, "waves_per_cu": 64, "split_priority": 0, "generate_entries": 1}):
             autotune.apply(t)
             _, _, _, step = build(wl, "fused")
             step()

@@ -1,8 +1,8 @@
 """Parity at the full benchmark sizes, in the launch configuration the benchmark times.
 
 The whole training step (project, bin and sort, fused forward + L2 gradient + backward,
-project_bwd) is captured once in a HIP graph and replayed, exactly as bench.py runs it,
-and then compared with the FP64 oracle:
+project_bwd) is autotuned, captured once in a HIP graph and replayed, exactly as bench.py
+runs it, and then compared with the FP64 oracle:
 
 * 1M Gaussians at 1920x1080 (one view): every splat field and the whole tile list
   bit-exact, the whole image within 1e-5, and every scene gradient -- all 14 parameters
@@ -35,17 +35,21 @@ def _print_case(name, **kw):
 
 
 def graph_step(wl):
-    """The benchmark's configuration: fused TrainStep captured in a HIP graph, replayed twice."""
-    from paper_2312_02121_amd import pipeline
+    """The benchmark's configuration: fused TrainStep with its autotuned launch tuning,
+    captured in a HIP graph, replayed twice."""
+    from paper_2312_02121_amd import autotune, pipeline
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
     step = pipeline.TrainStep(g, cams, tgt, mode="fused")
+    tuned = autotune.tune(step, steps=2, warmup=1)
+    print(f"autotuned: {tuned['tuning']}")
     graph = pipeline.GraphStep(step)
     for _ in range(2):
         graph()
     torch.cuda.synchronize()
     assert not step.overflowed()
+    autotune.apply(autotune.default_tuning())
     return step, graph
 
 

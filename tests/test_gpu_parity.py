@@ -52,11 +52,18 @@ def test_projection_bit_exact(name):
     check_projection(wl, r)
 
 
+@pytest.mark.parametrize("generate", [0, 1])
 @pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
-def test_bins_bit_exact(name):
-    _print_case("bins", wl=name)
+def test_bins_bit_exact(name, generate):
+    """Both first tile-sort passes (emitted list, or entries generated inside the pass)."""
+    _print_case("bins", wl=name, generate_entries=generate)
+    from paper_2312_02121_amd import autotune
     wl = wl_cache()[name]
-    r, st = gpu_forward(wl)
+    autotune.apply({**autotune.default_tuning(), "generate_entries": generate})
+    try:
+        r, st = gpu_forward(wl)
+    finally:
+        autotune.apply(autotune.default_tuning())
     toffs = tile_offsets(wl)
     okeys, oids, oranges = [], [], []
     for k, cam in enumerate(wl.cameras):
@@ -170,6 +177,33 @@ def test_capacity_overflow_regrows():
     r2, st2 = gpu_forward(wl)
     assert st.K == st2.K
     assert torch.equal(st.image, st2.image)
+
+
+def test_overflow_builds_no_list():
+    """A list capacity below K: the call reports overflow, leaves every tile range empty and
+    writes nothing from the unsorted buffers, which are filled with garbage first (a first
+    pass that sorted only the entries below the capacity once left slots of its output
+    unwritten, and the next pass gathered depth through them)."""
+    _print_case("overflow_garbage", wl="c2_20k")
+    from paper_2312_02121_amd import abi, pipeline
+    wl = wl_cache()["c2_20k"]
+    g = pipeline.GaussianSet(wl.scenes)
+    cams = pipeline.CameraSet(wl.cameras, g.sizes)
+    r = pipeline.Rasterizer(cams, capacity=4096)
+    r.project(g)
+    b = r.bins
+    for t in (b.keys, b.ids, b.ranges, b.workspace):
+        t.view(torch.uint8).fill_(0x7F)
+    abi.gs_bin_and_sort(r.splats.struct(cams.n_splats), cams.n_splats, cams.ptr, cams.n_cams, b.struct(),
+                        b.workspace.data_ptr(), b.workspace.numel(), pipeline.current_stream())
+    r.rasterize_fwd()
+    torch.cuda.synchronize()
+    K, over = r.read_count()
+    assert over and K > 4096
+    assert int(b.ranges.abs().max()) == 0
+    assert float(r.image.abs().max()) == 0.0
+    st = r.forward(g)                         # regrows and builds the full list
+    assert st.K == K and not r.read_count()[1]
 
 
 def test_deterministic_lists_and_image():
