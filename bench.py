@@ -104,17 +104,18 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
     step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_image=False)
-    tb = autotune.tune(step) if tune else None
+    tb = autotune.tune(step, cache_path=autotune.DEFAULT_CACHE) if tune else None
     graph = pipeline.GraphStep(step)
     ms_b = time_steps(graph, steps, warmup)
     if step.overflowed():
         raise SystemExit(f"config {cfg}: list overflow in the captured step")
-    E = step.E_fwd
+    E, K = step.E_fwd, step.K
     del graph, step
     torch.cuda.empty_cache()
     targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
     per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
-    tv = autotune.search(lambda: autotune.time_eager(per_view, 2, 1)) if tune else None
+    tv = (autotune.tune_callable("per_view:" + autotune.signature_of(g, cams, K), per_view,
+                                 cache_path=autotune.DEFAULT_CACHE) if tune else None)
     ms_v = time_steps(per_view, steps, warmup)
     del per_view
     torch.cuda.empty_cache()
@@ -155,6 +156,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch tuning")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="JSON launch tuning to apply instead of searching (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (a known-size kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -188,11 +191,14 @@ def main():
     step = pipeline.TrainStep(g, cams, targets, mode=args.mode)
     log(f"K={step.K} E_fwd={step.E_fwd} E_bwd={step.E_bwd} P={cams.n_splats} pixels={cams.n_pixels}")
     tuned = None
-    if not args.no_tune:
-        # launch tuning for this workload, searched before anything is timed
-        tuned = autotune.tune(step)
+    if args.tuning:
+        autotune.apply({**autotune.default_tuning(), **json.loads(args.tuning)})
+    elif not args.no_tune:
+        # launch tuning for this workload: recorded in the package's tuning cache, else
+        # searched, before anything is timed
+        tuned = autotune.tune(step, cache_path=autotune.DEFAULT_CACHE)
         log(f"autotuned {tuned['tuning']}: {tuned['default_ms']:.4f} -> {tuned['ms']:.4f} ms "
-            f"({tuned['evaluated']} candidates, {tuned['seconds']:.1f} s)")
+            f"({tuned['evaluated']} candidates, {tuned['seconds']:.1f} s, cached {tuned['cached']})")
 
     # per-stage times (eager launches, events between stages on the launch stream)
     n_st = len(step.STAGES)
@@ -235,7 +241,8 @@ def main():
                    "parallelism": "single-gpu", "tuning": autotune.current()},
         "stages_ms": stage_ms,
         "roofline": roofline,
-        "autotune": None if tuned is None else {k: tuned[k] for k in ("default_ms", "ms", "evaluated", "seconds")},
+        "autotune": None if tuned is None else {k: tuned[k] for k in ("default_ms", "ms", "evaluated", "seconds",
+                                                                     "cached")},
     }
     del runner
     if not args.no_autograd and args.config == 3:

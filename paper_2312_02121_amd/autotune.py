@@ -9,10 +9,11 @@ entries itself. None of them changes a result, only the time.
 ``tune`` times a full training step (project, bin and sort, fused forward + loss +
 backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
 The search is a coordinate descent from the library default: one knob at a time over its
-values, keeping the best value before moving to the next knob, two rounds. Results can be
+values, keeping the best value before moving to the next knob, two rounds. Results are
 cached in a JSON file keyed by a signature of the workload (cameras, resolutions, Gaussian
 count, and the list length rounded to a power of two), so a later process with the same
-kind of batch skips the search.
+kind of batch applies the recorded tuning without searching; ``python -m
+paper_2312_02121_amd.autotune`` records the benchmark workloads.
 """
 from __future__ import annotations
 
@@ -47,13 +48,16 @@ def current() -> dict:
     return abi.gs_get_tuning().as_dict()
 
 
-def signature(step) -> str:
+def signature_of(g, cams, K: int) -> str:
     """Workload key: camera count, sizes, Gaussians, splats and log2 of the list length."""
-    cams = step.cams
     sizes = sorted({(int(c["width"]), int(c["height"])) for c in cams.host})
-    return json.dumps({"views": int(cams.n_cams), "sizes": sizes, "gaussians": int(step.g.n),
-                       "splats": int(cams.n_splats), "log2K": int(round(math.log2(max(step.K, 1))))},
+    return json.dumps({"views": int(cams.n_cams), "sizes": sizes, "gaussians": int(g.n),
+                       "splats": int(cams.n_splats), "log2K": int(round(math.log2(max(K, 1))))},
                       sort_keys=True)
+
+
+def signature(step) -> str:
+    return signature_of(step.g, step.cams, step.K)
 
 
 def _time_graph(step, steps: int, warmup: int) -> float:
@@ -122,22 +126,97 @@ def search(measure: Callable[[], float], rounds: int = 2, log: Callable[[str], N
             "seconds": time.perf_counter() - t0}
 
 
-def tune(step, steps: int = 5, warmup: int = 2, rounds: int = 2, cache_path: str | None = None,
-         log: Callable[[str], None] | None = None) -> dict:
-    """Finds the fastest tuning for `step` (a pipeline.TrainStep, timed as a captured graph),
-    applies it and returns {"tuning", "ms", "default_ms", "evaluated", "seconds", "cached"}."""
-    key = signature(step)
-    cache = {}
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def _load(cache_path: str | None) -> dict:
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
-            cache = json.load(fh)
-        if key in cache:
-            apply(cache[key]["tuning"])
-            return {**cache[key], "cached": True}
+            return json.load(fh)
+    return {}
+
+
+def _store(cache_path: str, cache: dict):
+    os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+    with open(cache_path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+
+
+def tune(step, steps: int = 5, warmup: int = 2, rounds: int = 2, cache_path: str | None = None,
+         update_cache: bool = False, log: Callable[[str], None] | None = None) -> dict:
+    """Finds the fastest tuning for `step` (a pipeline.TrainStep, timed as a captured graph),
+    applies it and returns {"tuning", "ms", "default_ms", "evaluated", "seconds", "cached"}.
+    A tuning cached under the step's signature in `cache_path` is applied without a search;
+    with update_cache a fresh search result is written back."""
+    key = signature(step)
+    cache = _load(cache_path)
+    if key in cache:
+        apply(cache[key]["tuning"])
+        return {**cache[key], "cached": True}
     res = search(lambda: _time_graph(step, steps, warmup), rounds=rounds, log=log)
-    if cache_path:
+    if cache_path and update_cache:
         cache[key] = res
-        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
-        with open(cache_path, "w") as fh:
-            json.dump(cache, fh, indent=1)
+        _store(cache_path, cache)
     return {**res, "cached": False}
+
+
+def tune_callable(key: str, fn, steps: int = 2, warmup: int = 1, cache_path: str | None = None,
+                  update_cache: bool = False, log: Callable[[str], None] | None = None) -> dict:
+    """As tune, for any callable step (timed eagerly), cached under `key`."""
+    cache = _load(cache_path)
+    if key in cache:
+        apply(cache[key]["tuning"])
+        return {**cache[key], "cached": True}
+    res = search(lambda: time_eager(fn, steps, warmup), log=log)
+    if cache_path and update_cache:
+        cache[key] = res
+        _store(cache_path, cache)
+    return {**res, "cached": False}
+
+
+def main():
+    """Searches the launch tuning of the benchmark workloads on this GPU and records it in
+    the cache (default: tuned.json beside this file), for the batched step and, with
+    --per-view, for the one-view-per-launch form."""
+    import argparse
+
+    import numpy as np
+
+    from . import pipeline, synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--configs", type=int, nargs="+", default=[3, 4, 5])
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--per-view", action="store_true")
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    for cfg in args.configs:
+        wl = synth.make_config(cfg)
+        g = pipeline.GaussianSet(wl.scenes)
+        cams = pipeline.CameraSet(wl.cameras, g.sizes)
+        tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
+        apply(default_tuning())
+        step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_image=False)
+        key = signature(step)
+        cache = _load(args.out)
+        cache.pop(key, None)
+        _store(args.out, cache)
+        res = tune(step, cache_path=args.out, update_cache=True, log=print)
+        print(f"c{cfg}: {res['tuning']} {res['default_ms']:.4f} -> {res['ms']:.4f} ms", flush=True)
+        if args.per_view:
+            del step
+            torch.cuda.empty_cache()
+            targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
+            per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
+            pkey = "per_view:" + key
+            cache = _load(args.out)
+            cache.pop(pkey, None)
+            _store(args.out, cache)
+            res = tune_callable(pkey, per_view, cache_path=args.out, update_cache=True, log=print)
+            print(f"c{cfg} per view: {res['tuning']} {res['default_ms']:.4f} -> {res['ms']:.4f} ms", flush=True)
+            del per_view
+        torch.cuda.empty_cache()
+    apply(default_tuning())
+
+
+if __name__ == "__main__":
+    main()
