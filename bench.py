@@ -23,7 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd Gaussian-pixel evals/s and ms/view at 1M Gaussians 1080p; batched vs per-view"
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12     # fp32 VALU lane-ops/s, non-packed: 39.3 T
+# fp32 VALU lane-operations/s: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T, i.e. the
+# published 157.3 TFLOP/s fp32 vector peak with an FMA counted as one operation (gfx950 issues a
+# non-packed wave64 fp32 instruction every 2 clocks per SIMD)
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # algorithmic VALU lane-operations per Gaussian-pixel pair (exp2 and rcp count 4)
 SLOTS_FWD = 21

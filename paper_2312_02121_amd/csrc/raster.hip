@@ -143,8 +143,7 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
 // transmittance.
 template <int PX>
 struct PixState {
-    double pyd;
-    double pxd[PX];
+    double pyd, px0;   // centre of the lane's row and of its first pixel; pixel q is at px0 + q
     float T[PX], c0[PX], c1[PX], c2[PX];
     int last[PX], vis[PX];
 };
@@ -159,9 +158,9 @@ template <int PX>
 __device__ inline void init_state(const ItemPixels &t, PixState<PX> &ps)
 {
     ps.pyd = (double)t.row + 0.5;
+    ps.px0 = (double)t.col0 + 0.5;
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
-        ps.pxd[q] = (double)(t.col0 + q) + 0.5;
         ps.T[q] = pixel_inside<PX>(t, q) ? 1.f : -1.f;
         ps.c0[q] = ps.c1[q] = ps.c2[q] = 0.f;
         ps.last[q] = ps.vis[q] = 0;
@@ -194,15 +193,19 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 if (__ballot(m >= 0.f) == 0) break;
             }
             const int j1 = min(j0 + 8, nb);
+            RasterRec rn = slice[j0];
             for (int j = j0; j < j1; ++j) {
-            const RasterRec r = slice[j];
+            // the next record is read while this one is composited (index kept inside the slice)
+            const RasterRec r = rn;
+            rn = slice[min(j + 1, kBatch - 1)];
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
+            const double dx0 = (double)r.mx - ps.px0;
             const int pos1 = b + j - t.start + 1;
 #pragma unroll
             for (int q = 0; q < PX; ++q) {
-                const double dx = (double)r.mx - ps.pxd[q];
+                const double dx = dx0 - (double)q;   // exact: both sides are small binary fractions
                 float a = __builtin_amdgcn_fmed3f(alpha_raw(r, dx, bdy, cdl), 0.f, prm.alpha_max);
                 a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
                 if (kVisited) ps.vis[q] += ps.T[q] >= 0.f ? 1 : 0;
@@ -341,6 +344,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             const int pos = bstart + j - t.start;
             const RasterRec r = slice[j];
             const double dy = (double)r.my - ps.pyd;
+            const double dx0 = (double)r.mx - ps.px0;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
             // per-lane sums over the lane's pixels; the lane's pixels share one row, so the
@@ -354,7 +358,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             for (int q = 0; q < PX; ++q) {
                 // inactive (past `last`) or skipped pairs get alpha = 0: then rcp(1 - alpha) = 1,
                 // w = 0 and v = 0, and the pair changes nothing
-                const double dx = (double)r.mx - ps.pxd[q];
+                const double dx = dx0 - (double)q;
                 const float a_raw = alpha_raw(r, dx, bdy, cdl);
                 float a = __builtin_amdgcn_fmed3f(a_raw, 0.f, prm.alpha_max);
                 a = pos < ps.last[q] ? a : 0.f;
