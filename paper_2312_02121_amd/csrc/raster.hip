@@ -38,7 +38,7 @@ constexpr int kBlockWaves = 4;
 constexpr int kBatch = kWave;   // list entries staged per wave and batch
 // Up to this many contributing lanes, a splat's gradient terms are added into its LDS slot
 // with atomics; above it the wave reduces them with DPP first.
-constexpr int kLdsAtomicLanes = 8;
+constexpr int kLdsAtomicLanes = 4;
 
 // The wave's LDS slice for one batch of records.
 __device__ inline RasterRec *wave_slice()
@@ -194,6 +194,7 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             }
             const int j1 = min(j0 + 8, nb);
             RasterRec rn = slice[j0];
+#pragma unroll 2
             for (int j = j0; j < j1; ++j) {
             // the next record is read while this one is composited (index kept inside the slice)
             const RasterRec r = rn;
@@ -340,9 +341,12 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             const int pb = max(t.start, bstart - kBatch);
             next = gather(rr, ids, pb, bstart - pb, lane);
         }
+        RasterRec rn = slice[nb - 1];
         for (int j = nb - 1; j >= 0; --j) {
             const int pos = bstart + j - t.start;
-            const RasterRec r = slice[j];
+            // the next record (j - 1) is read while this one is processed
+            const RasterRec r = rn;
+            rn = slice[max(j - 1, 0)];
             const double dy = (double)r.my - ps.pyd;
             const double dx0 = (double)r.mx - ps.px0;
             const double bdy = r.B * dy;
