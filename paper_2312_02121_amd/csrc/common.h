@@ -27,7 +27,7 @@ struct alignas(64) RasterRec {
     float c0, c1, c2;
     float o;
     int src;          // scene Gaussian index
-    int pad;          // unused in HBM; the rasterizer's LDS copy keeps the splat slot here
+    int slot;         // the record's own splat slot (the gradient index of dL/dmu' and dL/dY)
 };
 static_assert(sizeof(RasterRec) == 64, "RasterRec must be 64 bytes");
 

@@ -120,6 +120,7 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
                 rr.c2 = r2.x;
                 rr.o = o;
                 rr.src = (int)i;
+                rr.slot = (int)p;
             }
         }
     }

@@ -47,23 +47,29 @@ __device__ inline RasterRec *wave_slice()
     return slice[__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
 }
 
-// Gathers the records of list entries [b, b + n) into registers, one per lane.
+// A batch is gathered in two dependent steps, each issued one batch ahead of its use: the
+// list entries' splat slots (load_ids), then their 64-byte records (gather) into registers,
+// one per lane. The records carry their own slot, so nothing is merged into the loads'
+// destination registers while the loads are in flight.
 struct Gathered {
     float4 q0, q1, q2, q3;
 };
 
-__device__ inline Gathered gather(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, int b, int n,
-                                  int lane)
+// Splat slots of list entries [b, b + n), one per lane; -1 for lanes >= n.
+__device__ inline int load_ids(const int32_t *__restrict__ ids, int b, int n, int lane)
+{
+    return lane < n ? ids[b + lane] : -1;
+}
+
+__device__ inline Gathered gather(const RasterRec *__restrict__ rr, int id)
 {
     Gathered g;
-    if (lane < n) {
-        const int id = ids[b + lane];
+    if (id >= 0) {
         const float4 *p = (const float4 *)(rr + id);
         g.q0 = p[0];
         g.q1 = p[1];
         g.q2 = p[2];
         g.q3 = p[3];
-        g.q3.w = __int_as_float(id);   // the record's spare word carries the splat slot
     } else {
         g.q0 = g.q1 = g.q2 = g.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -174,11 +180,15 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
 {
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
-    Gathered next = gather(rr, ids, t.start, min(kBatch, t.end - t.start), lane);
+    // batch k covers entries [t.start + 64 k, ...): its slots are loaded two batches ahead,
+    // its records one batch ahead
+    Gathered next = gather(rr, load_ids(ids, t.start, t.end - t.start, lane));
+    int nid = load_ids(ids, t.start + kBatch, t.end - t.start - kBatch, lane);
     for (int b = t.start; b < t.end; b += kBatch) {
         const int nb = min(kBatch, t.end - b);
         stage(slice, next, lane);
-        if (b + kBatch < t.end) next = gather(rr, ids, b + kBatch, min(kBatch, t.end - b - kBatch), lane);
+        if (b + kBatch < t.end) next = gather(rr, nid);
+        if (b + 2 * kBatch < t.end) nid = load_ids(ids, b + 2 * kBatch, t.end - b - 2 * kBatch, lane);
         float tmax = ps.T[0];
 #pragma unroll
         for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
@@ -293,7 +303,7 @@ __device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nb, i
         const float s_c0 = acc->f[0][lane], s_c1 = acc->f[1][lane], s_c2 = acc->f[2][lane];
         if (s_v != 0.0 || s_xx != 0.0 || s_c0 != 0.f || s_c1 != 0.f || s_c2 != 0.f) {
             const RasterRec r = slice[lane];
-            const int id = r.pad;
+            const int id = r.slot;
             const double il = 1.0 / kLog2eD;
             atomic_add_f64(&out.d_mean2d[id], (2.0 * r.A * s_x + r.B * s_y) * il);
             atomic_add_f64(&out.d_mean2d[out.n_splats + id], (r.B * s_x + 2.0 * r.C * s_y) * il);
@@ -332,14 +342,24 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     acc_clear(acc, lane);
     const int kend = t.start + maxlast;
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
-    Gathered next = gather(rr, ids, max(t.start, kend - kBatch), kend - max(t.start, kend - kBatch), lane);
+    // batch k covers entries [max(t.start, e_k - 64), e_k) with e_k = kend - 64 k: its slots
+    // are loaded two batches ahead, its records one batch ahead
+    const int s0 = max(t.start, kend - kBatch);
+    Gathered next = gather(rr, load_ids(ids, s0, kend - s0, lane));
+    int nid = -1;
+    if (s0 > t.start) {
+        const int s1 = max(t.start, s0 - kBatch);
+        nid = load_ids(ids, s1, s0 - s1, lane);
+    }
     for (int bend = kend; bend > t.start; bend -= kBatch) {
         const int bstart = max(t.start, bend - kBatch);
         const int nb = bend - bstart;
         stage(slice, next, lane);
-        if (bstart > t.start) {
-            const int pb = max(t.start, bstart - kBatch);
-            next = gather(rr, ids, pb, bstart - pb, lane);
+        if (bstart > t.start) next = gather(rr, nid);
+        const int e2 = bstart - kBatch;   // end of the batch after next
+        if (e2 > t.start) {
+            const int s2 = max(t.start, e2 - kBatch);
+            nid = load_ids(ids, s2, e2 - s2, lane);
         }
         RasterRec rn = slice[nb - 1];
         for (int j = nb - 1; j >= 0; --j) {
