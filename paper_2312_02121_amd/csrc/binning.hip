@@ -5,9 +5,10 @@
 // stable LSD radix sort of those 64-bit keys produces. It is computed as two stable
 // LDS-histogram radix sorts whose traffic does not grow with the 32 depth bits per entry:
 //
-//   1. depth sort of the P splats: 32-bit keys (float bits of t_z, culled splats last),
-//      values = splat slot; four 8-bit passes over P keys. Ties keep slot order.
-//   2. exclusive scan of tiles_touched in depth-rank order -> per-splat emit offsets and
+//   1. depth sort of the V splats that touch a tile: one pass compacts them in slot order
+//      (32-bit keys = float bits of t_z, values = splat slot) and counts the digits of
+//      every pass; then four 8-bit passes over V keys. Ties keep slot order.
+//   2. exclusive scan of tiles_touched in depth-rank order -> per-rank emit offsets and
 //      K = total intersections (an overflow flag is raised when K exceeds the capacity).
 //   3. emit in depth-rank order: each splat writes (global tile id, slot) for every tile of
 //      its box, row-major. A lane emits its own splat when the box is small; splats with
@@ -23,11 +24,12 @@
 // views with near-plane splats (hundreds of millions of entries) the sort is HBM-bound and
 // the difference is the whole cost.
 //
-// Each pass is one launch of a single-pass LSD sort with decoupled look-back: one upfront
-// kernel counts the digits of all passes from one read of the keys; then, per pass, each
-// block ranks its chunk, publishes its digit counts, sums its predecessors' published
-// counts for its global offsets (waiting, with a spin limit, on any predecessor that has
-// not published yet), stages the chunk in LDS in digit order and writes it out in runs.
+// The compaction, the offset scan and every sort pass are single-pass launches with
+// decoupled look-back: each block publishes its chunk's count(s), sums its predecessors'
+// published counts for its global offsets (waiting, with a spin limit, on any predecessor
+// that has not published yet) and writes its part. A sort pass ranks its chunk, stages it
+// in LDS in digit order and writes it out in runs; the digit counts of all its passes come
+// from one earlier read of the keys.
 // Block ranking uses wave ballots to group equal digits and LDS counters per (wave,
 // digit), so no LDS atomics contend on popular digits. Every kernel is sized from
 // host-known capacities and reads its element count from device memory, and the
@@ -40,8 +42,6 @@ namespace gsx {
 // ------------------------------------------------------------------------------ scan
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanChunk = kScanBlock * kScanItems;
 
 // Block-wide exclusive scan of one value per thread; returns the exclusive prefix and the
 // block total through *total.
@@ -70,92 +70,6 @@ __device__ inline T block_exclusive_scan(T v, T *total)
     return before + incl - v;
 }
 
-// The scans read their input through a loader: load(i) returns element i (i < n).
-template <typename T>
-struct ArrayLoad {
-    const T *p;
-    __device__ T operator()(int64_t i) const { return p[i]; }
-};
-
-// tiles_touched of the splat at depth rank i
-struct RankTiles {
-    const int32_t *tiles;
-    const int32_t *rank_ids;
-    __device__ int64_t operator()(int64_t i) const { return tiles[rank_ids[i]]; }
-};
-
-template <typename Load, typename TAcc>
-__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(Load in, int64_t n, TAcc *__restrict__ sums)
-{
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    TAcc acc = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) acc += (TAcc)in(base + k);
-    TAcc tot;
-    block_exclusive_scan<TAcc>(acc, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-// Single block: exclusive scan of sums[0..nb) in place; the grand total goes to *total
-// (if not null) and, when cap >= 0, an overflow flag to *flag = (total > cap).
-template <typename TAcc>
-__global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(TAcc *__restrict__ sums, int64_t nb,
-                                                               int64_t *__restrict__ total,
-                                                               int64_t *__restrict__ flag, int64_t cap)
-{
-    TAcc carry = 0;
-    for (int64_t base = 0; base < nb; base += kScanBlock) {
-        const int64_t idx = base + threadIdx.x;
-        const TAcc v = idx < nb ? sums[idx] : (TAcc)0;
-        TAcc tot;
-        const TAcc ex = block_exclusive_scan<TAcc>(v, &tot);
-        if (idx < nb) sums[idx] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        if (total) *total = (int64_t)carry;
-        if (flag) *flag = (cap >= 0 && (int64_t)carry > cap) ? 1 : 0;
-    }
-}
-
-template <typename Load, typename TAcc, typename TOut>
-__global__ __launch_bounds__(kScanBlock) void scan_down_kernel(Load in, int64_t n, const TAcc *__restrict__ sums,
-                                                               TOut *__restrict__ out)
-{
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    TAcc vals[kScanItems];
-    TAcc acc = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        vals[k] = base + k < n ? (TAcc)in(base + k) : (TAcc)0;
-        acc += vals[k];
-    }
-    TAcc tot;
-    TAcc run = block_exclusive_scan<TAcc>(acc, &tot) + sums[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) out[base + k] = (TOut)run;
-        run += vals[k];
-    }
-}
-
-static int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
-
-// Exclusive scan of n loaded values into out; sums needs scan_blocks(n) entries.
-template <typename TAcc, typename TOut, typename Load>
-static int scan_exclusive(Load in, int64_t n, TOut *out, TAcc *sums, int64_t *total, int64_t *flag, int64_t cap,
-                          hipStream_t st)
-{
-    const int64_t nb = scan_blocks(n);
-    if (nb == 0) return GS_OK;
-    hipLaunchKernelGGL((scan_reduce_kernel<Load, TAcc>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, sums);
-    hipLaunchKernelGGL((scan_sums_kernel<TAcc>), dim3(1), dim3(kScanBlock), 0, st, sums, nb, total, flag, cap);
-    hipLaunchKernelGGL((scan_down_kernel<Load, TAcc, TOut>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n,
-                       sums, out);
-    return check_launch("scan");
-}
-
 // ------------------------------------------------------------------------ radix sort
 
 constexpr int kSortBlock = 256;
@@ -165,6 +79,7 @@ constexpr int kSortChunk = kSortBlock * kSortItems;  // keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxTilePassesDev = 4;   // tile ids are int32: at most four 8-bit passes
+constexpr int kDepthPasses = 4;        // depth keys are 32-bit float bits
 static_assert(kSortBlock == kRadix, "one thread per digit in the single-pass sort");
 
 __device__ inline int64_t sort_count(const int64_t *counter, int64_t cap)
@@ -193,61 +108,99 @@ __device__ inline uint64_t match_digit(unsigned digit, uint64_t valid)
     return peers;
 }
 
-// Counts digits of this block's chunk. Wave w owns keys [w*M, (w+1)*M) of the chunk
-// (M = kSortChunk / kSortWaves), walked in order so that ranks are stable.
+// Adds the digit counts of the keys in row r of each wave (lanes set in valid[r]) to
+// cnt[wave][digit]; row r of wave w holds the chunk's keys w * M + 64 r + lane
+// (M = kSortChunk / kSortWaves). The leader lane of each digit group adds its group size.
+__device__ inline void count_digit_rows(const uint32_t (&key)[kSortItems], const uint64_t (&valid)[kSortItems],
+                                        int shift, unsigned (*cnt)[kRadix])
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (valid[r] == 0) continue;
+        const unsigned d = (key[r] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(d, valid[r]);
+        if (((valid[r] >> lane) & 1) && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
+    }
+}
+
+// Counts digits of this block's chunk: keys with chunk index below kvalid - chunk_base.
 __device__ inline void count_digits(const uint32_t (&key)[kSortItems], int64_t chunk_base, int64_t kvalid, int shift,
                                     unsigned (*cnt)[kRadix])
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint64_t valid[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = chunk_base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-        const bool ok = idx < kvalid;
-        const uint64_t valid = __ballot(ok);
-        if (valid == 0) break;
-        const unsigned d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid);
-        if (ok && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
-    }
+    for (int r = 0; r < kSortItems; ++r)
+        valid[r] = __ballot(chunk_base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane < kvalid);
+    count_digit_rows(key, valid, shift, cnt);
 }
 
-// Digit histograms of every pass from one read of the keys: ghist[pass][digit].
-__global__ __launch_bounds__(kSortBlock) void radix_global_hist_kernel(const uint32_t *__restrict__ keys,
-                                                                       const int64_t *__restrict__ count, int64_t cap,
-                                                                       int passes, unsigned *__restrict__ ghist)
-{
-    __shared__ unsigned cnt[kSortWaves][kRadix];
-    const int64_t kvalid = sort_count(count, cap);
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-    if (base >= kvalid) return;   // uniform over the block
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t key[kSortItems];
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-        key[r] = idx < kvalid ? keys[idx] : 0u;
-    }
-    for (int pass = 0; pass < passes; ++pass) {
-        for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
-        __syncthreads();
-        count_digits(key, base, kvalid, pass * kRadixBits, cnt);
-        __syncthreads();
-        const int d = threadIdx.x;   // kSortBlock == kRadix
-        unsigned tot = 0;
-#pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) tot += cnt[w][d];
-        if (tot) atomicAdd(&ghist[pass * kRadix + d], tot);
-        __syncthreads();
-    }
-}
-
-// Status word of one (block, digit) in a single-pass sort: 0 = not yet published,
-// kStatAgg | count of the block's own keys, kStatInc | inclusive prefix (global position
-// one past the block's last key with that digit).
+// Status word of one (block, digit) in a single-pass sort, or of one block in a
+// single-pass scan: 0 = not yet published, kStatAgg | the block's own count, kStatInc |
+// inclusive prefix (for a sort: global position one past the block's last key with that
+// digit).
 constexpr uint64_t kStatAgg = 1ull << 62;
 constexpr uint64_t kStatInc = 2ull << 62;
 constexpr uint64_t kStatValue = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 24;   // bounded wait: a predecessor that never publishes ends the wait
+
+// The block's chunk index from the ticket counter, in the order blocks start, so a block
+// only ever waits on chunks held by blocks already running; -1 when an earlier step of the
+// sequence gave up (the error word is set), and the block then does nothing.
+__device__ inline int take_ticket(int32_t *ticket, const int64_t *err_flag, int *sh_chunk)
+{
+    if (threadIdx.x == 0)
+        *sh_chunk = __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? -1
+                                                                                            : atomicAdd(ticket, 1);
+    __syncthreads();
+    return *sh_chunk;
+}
+
+// Gives up a look-back wait after kSpinLimit polls, or early once another block has given
+// up (checked every 64 polls). Returns true when the wait is to end.
+__device__ inline bool spin_exhausted(int &spins, int64_t *err_flag)
+{
+    ++spins;
+    if (spins > kSpinLimit ||
+        ((spins & 63) == 0 && __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return false;
+}
+
+// Exclusive prefix of chunk b > 0 of a single-pass scan, from the status words of chunks
+// 0 .. b - 1. Executed by one whole wave: lane l reads chunk j - l, so each step looks 64
+// chunks back; the prefix is the sum of the values up to the nearest inclusive one. Every
+// lane returns the prefix, or -1 when the wait gave up.
+__device__ inline int64_t chained_prefix(const uint64_t *status, int b, int64_t *err_flag)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t acc = 0;
+    int j = b - 1;
+    int spins = 0;
+    while (true) {
+        const int idx = j - lane;
+        const uint64_t st =
+            idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStatInc;
+        const uint64_t flag = st & ~kStatValue;
+        const uint64_t inc = __ballot(flag == kStatInc);
+        const uint64_t first = inc & (~inc + 1);                 // nearest inclusive chunk
+        const uint64_t need = inc ? (first | (first - 1)) : ~0ull;
+        if (__ballot(flag == 0) & need) {
+            if (spin_exhausted(spins, err_flag)) return -1;
+            continue;
+        }
+        int64_t v = ((need >> lane) & 1) ? (int64_t)(st & kStatValue) : 0;
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+        acc += v;
+        if (inc) return acc;
+        j -= kWave;
+    }
+}
 
 // LDS of one single-pass sort block.
 struct SweepShared {
@@ -259,15 +212,12 @@ struct SweepShared {
     int chunk, gave_up;
 };
 
-__device__ inline int sweep_ticket(SweepShared &sh, int32_t *ticket)
+// Chunk index of the block (-1: do nothing), with the counters cleared.
+__device__ inline int sweep_ticket(SweepShared &sh, int32_t *ticket, const int64_t *err_flag)
 {
-    if (threadIdx.x == 0) {
-        sh.chunk = atomicAdd(ticket, 1);
-        sh.gave_up = 0;
-    }
+    if (threadIdx.x == 0) sh.gave_up = 0;
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&sh.cnt[0][0])[d] = 0;
-    __syncthreads();
-    return sh.chunk;
+    return take_ticket(ticket, err_flag, &sh.chunk);
 }
 
 // One stable LSD pass over chunk b, keys already in registers in the wave-strided layout
@@ -310,12 +260,10 @@ __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortIt
                                                   __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t flag = st & ~kStatValue;
             if (flag == 0) {
-                if (++spins > kSpinLimit) {
-                    __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (spin_exhausted(spins, err_flag)) {
                     sh.gave_up = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(1);
                 continue;
             }
             acc += (int64_t)(st & kStatValue);
@@ -397,7 +345,8 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__
                                                               int64_t *__restrict__ err_flag)
 {
     __shared__ SweepShared sh;
-    const int b = sweep_ticket(sh, ticket);
+    const int b = sweep_ticket(sh, ticket, err_flag);
+    if (b < 0) return;
     const int64_t kvalid = all_or_none ? tile_sort_count(count, cap) : sort_count(count, cap);
     const int64_t base = (int64_t)b * kSortChunk;
     if (base >= kvalid) return;   // uniform over the block; no valid chunk waits on it
@@ -424,14 +373,15 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__
 __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
     const int32_t *__restrict__ rank_ids, const int64_t *__restrict__ offsets, const int32_t *__restrict__ chunk_rank,
     const int32_t *__restrict__ tiles, const int4 *__restrict__ rect, const gs_camera *__restrict__ cams, int n_cams,
-    int64_t n_splats, const int64_t *__restrict__ count, int64_t cap, const unsigned *__restrict__ ghist,
-    uint64_t *__restrict__ status, int32_t *__restrict__ ticket, uint32_t *__restrict__ keys_out,
-    int32_t *__restrict__ vals_out, uint64_t *__restrict__ keys64_out, const float *__restrict__ depth,
-    int64_t *__restrict__ err_flag)
+    int64_t n_splats, const int64_t *__restrict__ vcount, const int64_t *__restrict__ count, int64_t cap,
+    const unsigned *__restrict__ ghist, uint64_t *__restrict__ status, int32_t *__restrict__ ticket,
+    uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out, uint64_t *__restrict__ keys64_out,
+    const float *__restrict__ depth, int64_t *__restrict__ err_flag)
 {
     __shared__ SweepShared sh;
     __shared__ int n_ranks;
-    const int b = sweep_ticket(sh, ticket);
+    const int b = sweep_ticket(sh, ticket, err_flag);
+    if (b < 0) return;
     const int64_t kvalid = tile_sort_count(count, cap);
     const int64_t base = (int64_t)b * kSortChunk;
     if (base >= kvalid) return;   // uniform over the block
@@ -439,10 +389,11 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
     const int64_t n_chunks = (kvalid + kSortChunk - 1) / kSortChunk;
     const int r0 = chunk_rank[b];
     if (threadIdx.x == 0) {
-        const int64_t r_end = b + 1 < n_chunks ? (int64_t)chunk_rank[b + 1] : n_splats - 1;
+        const int64_t V = *vcount;
+        const int64_t r_end = b + 1 < n_chunks ? (int64_t)chunk_rank[b + 1] : V - 1;
         n_ranks = (int)min((int64_t)kSortChunk, r_end - r0 + 1);
-        // a rank outside [0, n_splats) would mean inconsistent counts: report, write nothing
-        if (r0 < 0 || r0 >= n_splats || r_end < r0 || r_end >= n_splats) {
+        // a rank outside [0, V) would mean inconsistent counts: report, write nothing
+        if (r0 < 0 || r0 >= V || r_end < r0 || r_end >= V || V > n_splats) {
             n_ranks = 0;
             __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -523,18 +474,176 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
 
 // ------------------------------------------------------------------- depth order, emit
 
-// Depth keys of every splat: float bits of t_z (positive, so bit order is value order);
-// culled splats get 0xffffffff and sort last. Thread 0 also stores the key count.
-__global__ __launch_bounds__(256) void depth_keys_kernel(const int32_t *__restrict__ tiles,
-                                                         const float *__restrict__ depth, int64_t n,
-                                                         uint32_t *__restrict__ dkey, int32_t *__restrict__ dval,
-                                                         int64_t *__restrict__ count)
+// Depth keys of the splats that touch at least one tile, compacted in slot order by a
+// single-pass scan over the visibility flags: key = float bits of t_z (positive, so bit
+// order is value order), value = slot. The grid has one block per chunk of kSortChunk
+// slots. Each block also counts the digits of every depth pass over the keys it keeps
+// (ghist[pass][digit]); the block of the last chunk stores the count V.
+__global__ __launch_bounds__(kSortBlock) void visible_keys_kernel(
+    const int32_t *__restrict__ tiles, const float *__restrict__ depth, int64_t n, uint64_t *__restrict__ status,
+    int32_t *__restrict__ ticket, uint32_t *__restrict__ dkey, int32_t *__restrict__ dval,
+    int64_t *__restrict__ count, unsigned *__restrict__ ghist, int64_t *__restrict__ err_flag)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) *count = n;
-    if (p >= n) return;
-    dkey[p] = tiles[p] > 0 ? __float_as_uint(depth[p]) : 0xffffffffu;
-    dval[p] = (int32_t)p;
+    __shared__ unsigned cnt[kSortWaves][kRadix];
+    __shared__ unsigned wave_tot[kSortWaves];
+    __shared__ int64_t prefix;
+    __shared__ int chunk;
+    const int b = take_ticket(ticket, err_flag, &chunk);
+    if (b < 0) return;
+    const int64_t base = (int64_t)b * kSortChunk;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t wbase = base + (int64_t)wave * (kSortChunk / kSortWaves);
+    uint32_t key[kSortItems];
+    uint64_t vis[kSortItems];
+    unsigned mine = 0;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = wbase + r * kWave + lane;
+        const bool ok = idx < n && tiles[idx] > 0;
+        key[r] = ok ? __float_as_uint(depth[idx]) : 0u;
+        vis[r] = __ballot(ok);
+        mine += (unsigned)__popcll(vis[r]);
+    }
+    if (lane == 0) wave_tot[wave] = mine;
+    __syncthreads();
+    unsigned before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+        const unsigned x = wave_tot[w];
+        if (w < wave) before += x;
+        total += x;
+    }
+    if (wave == 0) {
+        int64_t ex = 0;
+        if (b == 0) {
+            if (lane == 0)
+                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            ex = chained_prefix(status, b, err_flag);
+            if (lane == 0 && ex >= 0)
+                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            prefix = ex;
+            if (ex >= 0 && base + kSortChunk >= n) *count = ex + total;
+        }
+    }
+    __syncthreads();
+    if (prefix < 0) return;   // uniform: the wait gave up and the error word is set
+    int64_t pos = prefix + before;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if ((vis[r] >> lane) & 1) {
+            const int64_t q = pos + __popcll(vis[r] & lanemask_lt());
+            dkey[q] = key[r];
+            dval[q] = (int32_t)(wbase + r * kWave + lane);
+        }
+        pos += __popcll(vis[r]);
+    }
+    for (int pass = 0; pass < kDepthPasses; ++pass) {
+        for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
+        __syncthreads();
+        count_digit_rows(key, vis, pass * kRadixBits, cnt);
+        __syncthreads();
+        const int d = threadIdx.x;   // kSortBlock == kRadix
+        unsigned tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) tot += cnt[w][d];
+        if (tot) atomicAdd(&ghist[pass * kRadix + d], tot);
+        __syncthreads();
+    }
+}
+
+// Emit offsets: exclusive scan of tiles_touched in depth-rank order over the V visible
+// splats, as a single-pass scan (one block per chunk of kSortChunk ranks, 16 consecutive
+// ranks per thread). The block of the last chunk stores K = the total in counters[0] and
+// the overflow flag (K > capacity) in counters[1]; chunk 0 always runs, so V = 0 gives
+// K = 0.
+__global__ __launch_bounds__(kSortBlock) void rank_offsets_kernel(
+    const int32_t *__restrict__ tiles, const int32_t *__restrict__ rank_ids, const int64_t *__restrict__ vcount,
+    int64_t n_splats, int64_t cap, uint64_t *__restrict__ status, int32_t *__restrict__ ticket,
+    int64_t *__restrict__ offsets, int64_t *__restrict__ counters, int64_t *__restrict__ err_flag)
+{
+    __shared__ int64_t prefix;
+    __shared__ int chunk;
+    const int b = take_ticket(ticket, err_flag, &chunk);
+    if (b < 0) return;
+    const int64_t V = *vcount;
+    const int64_t base = (int64_t)b * kSortChunk;
+    if (b > 0 && base >= V) return;   // uniform; no chunk below V's last waits on it
+    const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
+    int32_t t[kSortItems];
+    if (i0 + kSortItems <= V) {
+        const int4 *ids4 = reinterpret_cast<const int4 *>(rank_ids + i0);
+        int32_t id[kSortItems];
+#pragma unroll
+        for (int q = 0; q < kSortItems / 4; ++q) {
+            const int4 v = ids4[q];
+            id[4 * q] = v.x; id[4 * q + 1] = v.y; id[4 * q + 2] = v.z; id[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) t[k] = (uint32_t)id[k] < (uint64_t)n_splats ? tiles[id[k]] : 0;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int32_t id = i0 + k < V ? rank_ids[i0 + k] : -1;
+            t[k] = (uint32_t)id < (uint64_t)n_splats ? tiles[id] : 0;
+        }
+    }
+    int64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) mine += t[k];
+    int64_t total;
+    const int64_t ex_thread = block_exclusive_scan<int64_t>(mine, &total);
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        int64_t ex = 0;
+        if (b == 0) {
+            if (lane == 0)
+                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            ex = chained_prefix(status, b, err_flag);
+            if (lane == 0 && ex >= 0)
+                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            prefix = ex;
+            if (ex >= 0 && base + kSortChunk >= V) {
+                const int64_t K = ex + total;
+                counters[0] = K;
+                counters[1] = K > cap ? 1 : 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (prefix < 0) return;   // uniform: the wait gave up and the error word is set
+    int64_t run = prefix + ex_thread;
+    if (i0 + kSortItems <= V) {
+        longlong2 *o2 = reinterpret_cast<longlong2 *>(offsets + i0);
+#pragma unroll
+        for (int q = 0; q < kSortItems / 2; ++q) {
+            longlong2 v;
+            v.x = run;
+            run += t[2 * q];
+            v.y = run;
+            run += t[2 * q + 1];
+            o2[q] = v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            if (i0 + k < V) offsets[i0 + k] = run;
+            run += t[k];
+        }
+    }
 }
 
 // ----------------------------------------------------------- tile-pass histograms, emit
@@ -623,16 +732,18 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
                                                    const int64_t *__restrict__ offsets,
                                                    const int32_t *__restrict__ tiles, const int4 *__restrict__ rect,
                                                    const gs_camera *__restrict__ cams, int n_cams, int64_t n_splats,
+                                                   const int64_t *__restrict__ vcount,
                                                    const int64_t *__restrict__ K, int64_t cap,
-                                                   uint32_t *__restrict__ tkey, int32_t *__restrict__ tval)
+                                                   uint32_t *__restrict__ tkey, int32_t *__restrict__ tval,
+                                                   const int64_t *__restrict__ err_flag)
 {
-    if (*K > cap) return;   // uniform
+    if (*K > cap || *err_flag) return;   // uniform
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     int32_t slot = 0;
     int cnt = 0;
     int64_t k0 = 0;
-    if (r < n_splats) {
+    if (r < *vcount) {
         slot = rank_ids[r];
         cnt = tiles[slot];
         k0 = offsets[r];
@@ -664,9 +775,10 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
 // [start, end) of each tile's run in the sorted list (nothing when the list was not built).
 __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict__ keys,
                                                      const int64_t *__restrict__ K, int64_t cap, int32_t n_tiles,
-                                                     int32_t *__restrict__ ranges)
+                                                     int32_t *__restrict__ ranges, const int64_t *__restrict__ err_flag)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (*err_flag) return;   // the list is incomplete: every range stays empty
     const int64_t kv = tile_sort_count(K, cap);
     if (k >= kv) return;
     const uint64_t t = keys[k] >> 32;
@@ -684,12 +796,14 @@ __global__ __launch_bounds__(64) void err_fold_kernel(int64_t *__restrict__ coun
 // chunk_rank[c] = depth rank of the splat that holds list entry c * kSortChunk.
 __global__ __launch_bounds__(256) void chunk_rank_kernel(const int32_t *__restrict__ rank_ids,
                                                          const int64_t *__restrict__ offsets,
-                                                         const int32_t *__restrict__ tiles, int64_t n_splats,
+                                                         const int32_t *__restrict__ tiles,
+                                                         const int64_t *__restrict__ vcount,
                                                          const int64_t *__restrict__ count, int64_t cap,
-                                                         int32_t *__restrict__ chunk_rank)
+                                                         int32_t *__restrict__ chunk_rank,
+                                                         const int64_t *__restrict__ err_flag)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_splats) return;
+    if (*err_flag || r >= *vcount) return;
     const int n = tiles[rank_ids[r]];
     if (n <= 0) return;
     const int64_t kvalid = tile_sort_count(count, cap);
@@ -775,17 +889,17 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 
 // ------------------------------------------------------------------------ workspace
 
-// Workspace: depth-sort buffers (two key/value pairs over P splats), per-rank emit offsets,
-// scan partial sums, one 32-bit key/value pair over the capacity (the other pair of the
+// Workspace: depth-sort buffers (two key/value pairs over P splats), the visible count,
+// per-rank emit offsets, one 32-bit key/value pair over the capacity (the other pair of the
 // tile-sort ping-pong lives in bins->keys / bins->ids until the last pass overwrites them),
-// then a region cleared at the start of every call: the look-back status words of every
-// pass, the digit histograms, the chunk tickets and an error word.
-constexpr int kDepthPasses = 4;
+// then a region cleared at the start of every call: the look-back status words of the two
+// single-pass scans and of every sort pass, the digit histograms, the chunk tickets and an
+// error word.
 constexpr int kMaxTilePasses = 4;
 
 struct BinLayout {
-    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, scan_sums, tkey, tval, chunk_rank;
-    size_t zero_begin, stat_depth, stat_tile, ghist_depth, ghist_tile, tickets, err, total;
+    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, tkey, tval, chunk_rank;
+    size_t zero_begin, stat_vis, stat_rank, stat_depth, stat_tile, ghist_depth, ghist_tile, tickets, err, total;
     int64_t depth_nb, tile_nb;
     int tile_passes;
 };
@@ -819,11 +933,12 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.dvalB = o;       o += p4;
     L.dcount = o;      o += 256;
     L.offsets = o;     o += align256((size_t)n_splats * sizeof(int64_t));
-    L.scan_sums = o;   o += align256((size_t)(scan_blocks(n_splats) + 1) * sizeof(int64_t));
     L.tkey = o;        o += align256((size_t)cap * 4);
     L.tval = o;        o += align256((size_t)cap * 4);
     L.chunk_rank = o;  o += align256((size_t)(L.tile_nb + 1) * sizeof(int32_t));
     L.zero_begin = o;
+    L.stat_vis = o;    o += align256((size_t)L.depth_nb * sizeof(uint64_t));
+    L.stat_rank = o;   o += align256((size_t)L.depth_nb * sizeof(uint64_t));
     L.stat_depth = o;  o += align256((size_t)kDepthPasses * L.depth_nb * stat_row);
     L.stat_tile = o;   o += align256((size_t)L.tile_passes * L.tile_nb * stat_row);
     L.ghist_depth = o; o += align256((size_t)kDepthPasses * kRadix * sizeof(unsigned));
@@ -884,10 +999,12 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int32_t *dvalA = (int32_t *)(ws + L.dvalA), *dvalB = (int32_t *)(ws + L.dvalB);
     int64_t *dcount = (int64_t *)(ws + L.dcount);
     int64_t *offsets = (int64_t *)(ws + L.offsets);
-    int64_t *scan_sums = (int64_t *)(ws + L.scan_sums);
+    uint64_t *stat_vis = (uint64_t *)(ws + L.stat_vis), *stat_rank = (uint64_t *)(ws + L.stat_rank);
     uint64_t *stat_depth = (uint64_t *)(ws + L.stat_depth), *stat_tile = (uint64_t *)(ws + L.stat_tile);
     unsigned *ghist_depth = (unsigned *)(ws + L.ghist_depth), *ghist_tile = (unsigned *)(ws + L.ghist_tile);
     int32_t *tickets = (int32_t *)(ws + L.tickets);
+    int32_t *tk_depth = tickets, *tk_tile = tickets + kDepthPasses;
+    int32_t *tk_vis = tickets + kDepthPasses + kMaxTilePasses, *tk_rank = tk_vis + 1;
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
@@ -901,17 +1018,16 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int rc = gs_zero(ws + L.zero_begin, L.total - L.zero_begin, st);
     if (rc != GS_OK) return rc;
 
-    // 1. depth order of the splats (four 8-bit passes: the result is back in A)
-    hipLaunchKernelGGL(depth_keys_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, s->tiles_touched,
-                       s->depth, n_splats, dkeyA, dvalA, dcount);
-    hipLaunchKernelGGL(radix_global_hist_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, dkeyA,
-                       (const int64_t *)dcount, n_splats, kDepthPasses, ghist_depth);
+    // 1. depth order of the V visible splats: compacted keys and the digit counts of all
+    // passes, then four 8-bit passes (the result is back in A)
+    hipLaunchKernelGGL(visible_keys_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
+                       s->depth, n_splats, stat_vis, tk_vis, dkeyA, dvalA, dcount, ghist_depth, err);
     for (int pass = 0; pass < kDepthPasses; ++pass) {
         const bool even = (pass & 1) == 0;
         hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st,
                            even ? dkeyA : dkeyB, even ? dvalA : dvalB, (const int64_t *)dcount, n_splats,
                            pass * kRadixBits, ghist_depth + pass * kRadix,
-                           stat_depth + (int64_t)pass * L.depth_nb * kRadix, tickets + pass, even ? dkeyB : dkeyA,
+                           stat_depth + (int64_t)pass * L.depth_nb * kRadix, tk_depth + pass, even ? dkeyB : dkeyA,
                            even ? dvalB : dvalA, (uint64_t *)nullptr, (const float *)nullptr, n_splats, 0, err);
     }
     rc = check_launch("depth sort");
@@ -919,9 +1035,9 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     const int32_t *rank_ids = dvalA;
 
     // 2. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
-    rc = scan_exclusive<int64_t, int64_t>(RankTiles{s->tiles_touched, rank_ids}, n_splats, offsets, scan_sums,
-                                          bins->counters, bins->counters + 1, cap, st);
-    if (rc != GS_OK) return rc;
+    hipLaunchKernelGGL(rank_offsets_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
+                       rank_ids, (const int64_t *)dcount, n_splats, cap, stat_rank, tk_rank, offsets,
+                       bins->counters, err);
 
     // 3. digit histograms of the tile passes, from the boxes
     const int passes = L.tile_passes;
@@ -942,21 +1058,21 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     if (current_tuning().generate_entries) {
         int32_t *chunk_rank = (int32_t *)(ws + L.chunk_rank);
         hipLaunchKernelGGL(chunk_rank_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
-                           s->tiles_touched, n_splats, K, cap, chunk_rank);
+                           s->tiles_touched, (const int64_t *)dcount, K, cap, chunk_rank, (const int64_t *)err);
         hipLaunchKernelGGL(onesweep_emit_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, rank_ids,
                            offsets, (const int32_t *)chunk_rank, s->tiles_touched, (const int4 *)s->rect, cams,
-                           (int)n_cams, n_splats, K, cap, ghist_tile, stat_tile, tickets + kDepthPasses, k0out,
-                           v0out, k64, s->depth, err);
+                           (int)n_cams, n_splats, (const int64_t *)dcount, K, cap, ghist_tile, stat_tile, tk_tile,
+                           k0out, v0out, k64, s->depth, err);
     } else {
         // the emitted entries go to the pair the first pass does not write
         const bool emit_to_X = passes >= 2 && first_to_W;
         uint32_t *ek = emit_to_X ? kX : kW;
         int32_t *ev = emit_to_X ? vX : vW;
         hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
-                           s->tiles_touched, (const int4 *)s->rect, cams, (int)n_cams, n_splats, K, cap, ek, ev);
+                           s->tiles_touched, (const int4 *)s->rect, cams, (int)n_cams, n_splats,
+                           (const int64_t *)dcount, K, cap, ek, ev, (const int64_t *)err);
         hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, ek, ev, K, cap, 0,
-                           ghist_tile, stat_tile, tickets + kDepthPasses, k0out, v0out, k64, s->depth, n_splats, 1,
-                           err);
+                           ghist_tile, stat_tile, tk_tile, k0out, v0out, k64, s->depth, n_splats, 1, err);
     }
     uint32_t *kin = first_to_W ? kW : kX;
     int32_t *vin = first_to_W ? vW : vX;
@@ -966,7 +1082,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         int32_t *vout = vin == vW ? vX : vW;
         hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, kin, vin, K, cap,
                            pass * kRadixBits, ghist_tile + pass * kRadix,
-                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, tickets + kDepthPasses + pass,
+                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, tk_tile + pass,
                            last ? (uint32_t *)nullptr : kout, last ? bins->ids : vout,
                            last ? bins->keys : (uint64_t *)nullptr, s->depth, n_splats, 1, err);
         kin = kout;
@@ -975,7 +1091,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
     hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys, K, cap, bins->n_tiles,
-                       bins->ranges);
+                       bins->ranges, (const int64_t *)err);
 
     // 5. the work list; the sort's error word joins the overflow flag
     hipLaunchKernelGGL(err_fold_kernel, dim3(1), dim3(64), 0, st, bins->counters, (const int64_t *)err);
