@@ -134,7 +134,7 @@ typedef struct gs_bins {
     int32_t *schedule;       /* [gs_schedule_size(n_tiles)] rasterizer work list, written by
                                 gs_bin_and_sort; layout private to the library */
     int64_t *counters;       /* [2]: K = total intersections (may exceed capacity), flags
-                                (1 = overflow, 2 = sort failure) */
+                                (1 = overflow, 2 = sort failure, 4 = camera too wide) */
     int64_t capacity;        /* K_cap, at most 2^31 - 1 */
     int32_t n_tiles;         /* sum over cameras of tiles_x * tiles_y */
     int32_t reserved;
@@ -226,17 +226,20 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * 64-bit keys -- and find each tile's [start, end), then write the rasterizer's work list
  * (tiles in decreasing list length, long ones split into four parts). The sort is done as
  * a stable depth sort of the splats followed by a stable tile-id sort of the entries
- * emitted in depth order, which yields the same list. K is written to
+ * emitted in depth order, which yields the same list; the ranges come from each tile's
+ * list length, counted from the boxes (a 2D difference array per camera). K is written to
  * bins->counters[0]; if K exceeds bins->capacity the list is not built (every tile's
  * range is empty, so a rasterize call made before the caller looks renders nothing and
  * reads nothing from the list), counters[1] is set to 1, and the caller regrows and calls
  * again. counters[1] & 2 means a
- * wait inside the single-pass sort gave up after its spin limit (the list is invalid; this
- * indicates a fault, not a capacity problem). workspace: device
+ * wait inside the single-pass sort gave up after its spin limit, or the counted lengths
+ * disagree with K (the list is invalid and every range empty; this indicates a fault, not
+ * a capacity problem); counters[1] & 4: a camera has more than 8192 tiles in a row (wider
+ * than 131072 pixels), which is not supported (nothing is listed). workspace: device
  * memory of at least gs_bin_and_sort_workspace_size() bytes, contents free on entry and
  * exit. cams: as for gs_project.
  * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1], n_splats outside
- * [0, 2^31 - 1]), GS_ERR_CAPACITY (workspace too small).
+ * [0, 2^31 - 1], more cameras than tiles), GS_ERR_CAPACITY (workspace too small).
  */
 int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
                     gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream);

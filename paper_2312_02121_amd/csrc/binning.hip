@@ -478,13 +478,15 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
 // single-pass scan over the visibility flags: key = float bits of t_z (positive, so bit
 // order is value order), value = slot. The grid has one block per chunk of kSortChunk
 // slots. Each block also counts the digits of every depth pass over the keys it keeps
-// (ghist[pass][digit]); the block of the last chunk stores the count V.
+// (ghist[pass][digit], from the kept keys compacted in LDS); the block of the last chunk
+// stores the count V.
 __global__ __launch_bounds__(kSortBlock) void visible_keys_kernel(
     const int32_t *__restrict__ tiles, const float *__restrict__ depth, int64_t n, uint64_t *__restrict__ status,
     int32_t *__restrict__ ticket, uint32_t *__restrict__ dkey, int32_t *__restrict__ dval,
     int64_t *__restrict__ count, unsigned *__restrict__ ghist, int64_t *__restrict__ err_flag)
 {
-    __shared__ unsigned cnt[kSortWaves][kRadix];
+    __shared__ unsigned cnt[kDepthPasses][kSortWaves][kRadix];
+    __shared__ uint32_t kept[kSortChunk];
     __shared__ unsigned wave_tot[kSortWaves];
     __shared__ int64_t prefix;
     __shared__ int chunk;
@@ -534,27 +536,41 @@ __global__ __launch_bounds__(kSortBlock) void visible_keys_kernel(
     }
     __syncthreads();
     if (prefix < 0) return;   // uniform: the wait gave up and the error word is set
-    int64_t pos = prefix + before;
+    unsigned local = before;   // block-local position of the wave's next kept key
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         if ((vis[r] >> lane) & 1) {
-            const int64_t q = pos + __popcll(vis[r] & lanemask_lt());
-            dkey[q] = key[r];
-            dval[q] = (int32_t)(wbase + r * kWave + lane);
+            const unsigned l = local + (unsigned)__popcll(vis[r] & lanemask_lt());
+            dkey[prefix + l] = key[r];
+            dval[prefix + l] = (int32_t)(wbase + r * kWave + lane);
+            kept[l] = key[r];
         }
-        pos += __popcll(vis[r]);
+        local += (unsigned)__popcll(vis[r]);
     }
+    // digit counts of every depth pass over the kept keys, read back compacted from LDS in
+    // rows of 64 dealt to the waves in turn
+    for (int i = threadIdx.x; i < kDepthPasses * kSortWaves * kRadix; i += kSortBlock) (&cnt[0][0][0])[i] = 0;
+    __syncthreads();
+    for (int row = wave; row * kWave < (int)total; row += kSortWaves) {
+        const int i = row * kWave + lane;
+        const bool ok = i < (int)total;
+        const uint32_t k = ok ? kept[i] : 0u;
+        const uint64_t valid = __ballot(ok);
+#pragma unroll
+        for (int pass = 0; pass < kDepthPasses; ++pass) {
+            const unsigned dg = (k >> (pass * kRadixBits)) & (kRadix - 1);
+            const uint64_t peers = match_digit(dg, valid);
+            if (ok && (peers & lanemask_lt()) == 0) cnt[pass][wave][dg] += (unsigned)__popcll(peers);
+        }
+    }
+    __syncthreads();
+    const int d = threadIdx.x;   // kSortBlock == kRadix
+#pragma unroll
     for (int pass = 0; pass < kDepthPasses; ++pass) {
-        for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&cnt[0][0])[d] = 0;
-        __syncthreads();
-        count_digit_rows(key, vis, pass * kRadixBits, cnt);
-        __syncthreads();
-        const int d = threadIdx.x;   // kSortBlock == kRadix
         unsigned tot = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) tot += cnt[w][d];
+        for (int w = 0; w < kSortWaves; ++w) tot += cnt[pass][w][d];
         if (tot) atomicAdd(&ghist[pass * kRadix + d], tot);
-        __syncthreads();
     }
 }
 
@@ -648,66 +664,225 @@ __global__ __launch_bounds__(kSortBlock) void rank_offsets_kernel(
 
 // ----------------------------------------------------------- tile-pass histograms, emit
 
-// Digit histograms of all tile passes, counted from the boxes without emitting anything:
-// a box row covers the consecutive global tile ids [a, a + L). For the lowest digit those
-// are L consecutive values mod 256 (L / 256 full turns plus a cyclic run, added to a
-// difference array); for a higher digit of weight 256^p the row splits into at most
-// L / 256^p + 2 runs of equal digit. A fixed grid of blocks strides over the splats and
-// adds its LDS histograms to the global ones once. Nothing is counted when K exceeds the
-// capacity (the list is then not built).
-constexpr int kHistBlocks = 1024;
+// ------------------------------------------------------- per-tile list lengths, ranges
 
-__global__ __launch_bounds__(256) void tile_hist_kernel(const int32_t *__restrict__ tiles,
-                                                        const int4 *__restrict__ rect,
-                                                        const gs_camera *__restrict__ cams, int n_cams,
-                                                        int64_t n_splats, const int64_t *__restrict__ K, int64_t cap,
-                                                        int passes, unsigned *__restrict__ ghist)
+// Every listed splat adds one entry to each tile of its box, so the list length of a tile
+// is a 2D box count: per camera, +1 at (y0, x0) and (y1 + 1, x1 + 1) and -1 at (y0, x1 + 1)
+// and (y1 + 1, x0) of a difference array over its tile grid (corners past the grid
+// dropped), then 2D prefix sums. Each splat costs four LDS atomics whatever the size of its
+// box. The lengths give the digit histograms of the tile passes (before them) and every
+// tile's range (after them).
+constexpr int kCountLds = 8192;     // LDS cells: one band of rows of a tile grid (1920x1080: 8160)
+constexpr int kCornerBlock = 1024;
+
+// A block takes `span` consecutive entries of the compacted visible slots (ascending, so
+// each camera's slots are contiguous), adds their corners to an LDS difference array for
+// each camera it meets (a grid of more than kCountLds tiles in bands of rows), and adds
+// the nonzero cells to the global array, indexed by global tile id.
+__global__ __launch_bounds__(kCornerBlock) void tile_corner_kernel(const int32_t *__restrict__ vis_slots,
+                                                                   const int64_t *__restrict__ vcount,
+                                                                   const int4 *__restrict__ rect,
+                                                                   const gs_camera *__restrict__ cams, int n_cams,
+                                                                   int64_t n_splats, int64_t span,
+                                                                   int32_t *__restrict__ gdiff)
 {
-    __shared__ int diff0[kRadix + 1];
-    __shared__ unsigned full0;
+    __shared__ int diff[kCountLds];
+    const int64_t V = *vcount;
+    const int64_t s0 = (int64_t)blockIdx.x * span;
+    if (s0 >= V) return;   // uniform
+    const int64_t s1 = min(s0 + span, V);
+    const int c_first = camera_of_splat(cams, n_cams, vis_slots[s0]);
+    const int c_last = camera_of_splat(cams, n_cams, vis_slots[s1 - 1]);
+    constexpr int kU = 4;   // slots per thread in flight
+    for (int c = c_first; c <= c_last; ++c) {
+        const int64_t p_lo = max(cams[c].proj_offset, (int64_t)0);
+        const int64_t p_hi = min(p_lo + cams[c].gauss_count, n_splats);
+        const int W = cams[c].tiles_x, H = cams[c].tiles_y, toff = cams[c].tile_offset;
+        if (W < 1 || H < 1 || W > kCountLds) continue;   // uniform; tile_count_kernel reports it
+        const int band = kCountLds / W;
+        for (int yb = 0; yb < H; yb += band) {
+            const int rows = min(band, H - yb);
+            for (int i = threadIdx.x; i < rows * W; i += kCornerBlock) diff[i] = 0;
+            __syncthreads();
+            for (int64_t i0 = s0 + threadIdx.x; i0 < s1; i0 += kU * kCornerBlock) {
+                int32_t sl[kU];
+                int4 bx[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kCornerBlock;
+                    sl[u] = i < s1 ? vis_slots[i] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    bx[u] = sl[u] >= p_lo && sl[u] < p_hi ? rect[sl[u]] : make_int4(0, 0, -1, -1);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (bx[u].z < 0) continue;   // not this camera's slot
+                    const int x0 = min(max(bx[u].x, 0), W - 1), x1 = min(max(bx[u].z, 0), W - 1) + 1;
+                    const int y0 = min(max(bx[u].y, 0), H - 1), y1 = min(max(bx[u].w, 0), H - 1) + 1;
+                    if (y0 >= yb && y0 < yb + rows) {
+                        atomicAdd(&diff[(y0 - yb) * W + x0], 1);
+                        if (x1 < W) atomicAdd(&diff[(y0 - yb) * W + x1], -1);
+                    }
+                    if (y1 < H && y1 >= yb && y1 < yb + rows) {
+                        atomicAdd(&diff[(y1 - yb) * W + x0], -1);
+                        if (x1 < W) atomicAdd(&diff[(y1 - yb) * W + x1], 1);
+                    }
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < rows * W; i += kCornerBlock)
+                if (diff[i]) atomicAdd(&gdiff[toff + (int64_t)yb * W + i], diff[i]);
+            __syncthreads();
+        }
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ inline int wave_inclusive_scan(int v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+constexpr int kCountBlock = 1024;
+
+// One block per camera: 2D prefix sums of its difference array (bands of rows in LDS; a
+// wave scans a row, then a column, 64 cells at a time) give the list length of every tile,
+// written over the difference array; the digit histograms of the tile passes are added
+// from the lengths.
+__global__ __launch_bounds__(kCountBlock) void tile_count_kernel(const gs_camera *__restrict__ cams, int passes,
+                                                                 int32_t *__restrict__ cnt,
+                                                                 unsigned *__restrict__ ghist,
+                                                                 int64_t *__restrict__ err_flag)
+{
+    __shared__ int cells[kCountLds];
+    __shared__ int col_run[kCountLds];
     __shared__ unsigned h[kMaxTilePassesDev][kRadix];
-    for (int i = threadIdx.x; i < kRadix + 1; i += blockDim.x) diff0[i] = 0;
-    for (int i = threadIdx.x; i < kMaxTilePassesDev * kRadix; i += blockDim.x) (&h[0][0])[i] = 0;
-    if (threadIdx.x == 0) full0 = 0;
-    __syncthreads();
-    if (*K > cap) return;   // uniform: every thread reads the same K
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_splats;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        if (tiles[p] <= 0) continue;
-        const int c = camera_of_splat(cams, n_cams, p);
-        const int toff = cams[c].tile_offset, TX = cams[c].tiles_x;
-        const int4 bx = rect[p];
-        const int L = bx.z - bx.x + 1;
-        for (int y = bx.y; y <= bx.w; ++y) {
-            const int64_t a = (int64_t)toff + (int64_t)y * TX + bx.x, e = a + L - 1;
-            const int s0 = (int)(a & (kRadix - 1)), r = L & (kRadix - 1);
-            if (L >> kRadixBits) atomicAdd(&full0, (unsigned)(L >> kRadixBits));
-            if (r) {
-                atomicAdd(&diff0[s0], 1);
-                if (s0 + r <= kRadix) {
-                    atomicAdd(&diff0[s0 + r], -1);
-                } else {
-                    atomicAdd(&diff0[0], 1);
-                    atomicAdd(&diff0[s0 + r - kRadix], -1);
-                }
+    constexpr int kWaves = kCountBlock / kWave;
+    const int c = blockIdx.x;
+    const int W = cams[c].tiles_x, H = cams[c].tiles_y, toff = cams[c].tile_offset;
+    if (W > kCountLds) {   // uniform: wider than 131072 pixels is not supported
+        if (threadIdx.x == 0) __hip_atomic_store(err_flag, (int64_t)4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    if (W < 1 || H < 1) return;   // uniform: no tiles
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kMaxTilePassesDev * kRadix; i += kCountBlock) (&h[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < W; i += kCountBlock) col_run[i] = 0;
+    const int band = kCountLds / W;
+    for (int yb = 0; yb < H; yb += band) {
+        const int rows = min(band, H - yb), n = rows * W;
+        const int64_t t0 = toff + (int64_t)yb * W;
+        for (int i = threadIdx.x; i < n; i += kCountBlock) cells[i] = cnt[t0 + i];
+        __syncthreads();
+        for (int r = wave; r < rows; r += kWaves) {
+            int carry = 0;
+            for (int x0 = 0; x0 < W; x0 += kWave) {
+                const int x = x0 + lane;
+                const int v = wave_inclusive_scan(x < W ? cells[r * W + x] : 0) + carry;
+                if (x < W) cells[r * W + x] = v;
+                carry = __shfl(v, kWave - 1, kWave);
             }
-            for (int pass = 1; pass < passes; ++pass) {
-                const int sh = pass * kRadixBits;
-                for (int64_t blk = a >> sh; blk <= (e >> sh); ++blk) {
-                    const int64_t lo = max(a, blk << sh), hi = min(e, ((blk + 1) << sh) - 1);
-                    atomicAdd(&h[pass][blk & (kRadix - 1)], (unsigned)(hi - lo + 1));
-                }
+        }
+        __syncthreads();
+        for (int x = wave; x < W; x += kWaves) {
+            int carry = col_run[x];
+            for (int r0 = 0; r0 < rows; r0 += kWave) {
+                const int r = r0 + lane;
+                const int v = wave_inclusive_scan(r < rows ? cells[r * W + x] : 0) + carry;
+                if (r < rows) cells[r * W + x] = v;
+                carry = __shfl(v, kWave - 1, kWave);
             }
+            if (lane == 0) col_run[x] = carry;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kCountBlock) {
+            const int v = cells[i];
+            const int64_t t = t0 + i;
+            cnt[t] = v;
+            if (v)
+                for (int pass = 0; pass < passes; ++pass)
+                    atomicAdd(&h[pass][(t >> (pass * kRadixBits)) & (kRadix - 1)], (unsigned)v);
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < passes * kRadix; i += kCountBlock)
+        if ((&h[0][0])[i]) atomicAdd(&ghist[i], (&h[0][0])[i]);
+}
+
+// Ranges: exclusive scan of the list lengths in global tile order (single pass, chained
+// like the sorts; 16 consecutive tiles per thread), run only when the list was built (K
+// within the capacity, no error). A range is written only when it ends within K, so the
+// rasterizer never reads past the list; a range past K, or a total different from K,
+// marks the lengths inconsistent with the list (error word). Empty tiles get (0, 0).
+__global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__restrict__ cnt, int32_t n_tiles,
+                                                            const int64_t *__restrict__ K, int64_t cap,
+                                                            uint64_t *__restrict__ status,
+                                                            int32_t *__restrict__ ticket,
+                                                            int32_t *__restrict__ ranges,
+                                                            int64_t *__restrict__ err_flag)
+{
+    __shared__ int64_t prefix;
+    __shared__ int chunk;
+    const int64_t k_all = *K;
+    if (k_all > cap) return;   // uniform: the list was not built
+    const int b = take_ticket(ticket, err_flag, &chunk);
+    if (b < 0) return;
+    const int64_t base = (int64_t)b * kSortChunk;
+    const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
+    int32_t n[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) n[k] = i0 + k < n_tiles ? cnt[i0 + k] : 0;
+    int64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) mine += n[k];
+    int64_t total;
+    const int64_t ex_thread = block_exclusive_scan<int64_t>(mine, &total);
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        int64_t ex = 0;
+        if (b == 0) {
+            if (lane == 0)
+                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            ex = chained_prefix(status, b, err_flag);
+            if (lane == 0 && ex >= 0)
+                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            prefix = ex;
+            if (ex >= 0 && base + kSortChunk >= n_tiles && ex + total != k_all)
+                __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
-    const int d = threadIdx.x;   // blockDim.x == kRadix
-    int tot;
-    const int run = block_exclusive_scan<int>(diff0[d], &tot) + diff0[d];
-    const unsigned v0 = full0 + (unsigned)run;
-    if (v0) atomicAdd(&ghist[d], v0);
-    for (int pass = 1; pass < passes; ++pass)
-        if (h[pass][d]) atomicAdd(&ghist[pass * kRadix + d], h[pass][d]);
+    if (prefix < 0) return;
+    int64_t run = prefix + ex_thread;
+    bool past = false;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t e = run + n[k];
+        if (i0 + k < n_tiles) {
+            if (n[k] > 0 && e <= k_all) {
+                ranges[2 * (i0 + k)] = (int32_t)run;
+                ranges[2 * (i0 + k) + 1] = (int32_t)e;
+            } else if (n[k] > 0) {
+                past = true;
+            }
+        }
+        run = e;
+    }
+    if (past) __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Splats whose box has at most this many tiles are emitted by their own lane.
@@ -772,22 +947,8 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
     }
 }
 
-// [start, end) of each tile's run in the sorted list (nothing when the list was not built).
-__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t *__restrict__ keys,
-                                                     const int64_t *__restrict__ K, int64_t cap, int32_t n_tiles,
-                                                     int32_t *__restrict__ ranges, const int64_t *__restrict__ err_flag)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (*err_flag) return;   // the list is incomplete: every range stays empty
-    const int64_t kv = tile_sort_count(K, cap);
-    if (k >= kv) return;
-    const uint64_t t = keys[k] >> 32;
-    if (t >= (uint64_t)n_tiles) return;
-    if (k == 0 || (keys[k - 1] >> 32) != t) ranges[2 * t] = (int32_t)k;
-    if (k == kv - 1 || (keys[k + 1] >> 32) != t) ranges[2 * t + 1] = (int32_t)(k + 1);
-}
-
-// Folds the sort's error word into the overflow flag (value 2: a look-back wait gave up).
+// Folds the sort's error word into the flags (2: a look-back wait gave up or the counts
+// disagree; 4: a camera wider than the count array).
 __global__ __launch_bounds__(64) void err_fold_kernel(int64_t *__restrict__ counters, const int64_t *__restrict__ err)
 {
     if (threadIdx.x == 0 && *err) counters[1] |= *err;
@@ -892,14 +1053,16 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 // Workspace: depth-sort buffers (two key/value pairs over P splats), the visible count,
 // per-rank emit offsets, one 32-bit key/value pair over the capacity (the other pair of the
 // tile-sort ping-pong lives in bins->keys / bins->ids until the last pass overwrites them),
-// then a region cleared at the start of every call: the look-back status words of the two
-// single-pass scans and of every sort pass, the digit histograms, the chunk tickets and an
-// error word.
+// then a region cleared at the start of every call: the per-tile difference array (then
+// list lengths), the look-back status words of the three single-pass scans and of every
+// sort pass, the digit histograms, the chunk tickets and an error word.
 constexpr int kMaxTilePasses = 4;
 
 struct BinLayout {
     size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, tkey, tval, chunk_rank;
-    size_t zero_begin, stat_vis, stat_rank, stat_depth, stat_tile, ghist_depth, ghist_tile, tickets, err, total;
+    size_t zero_begin, gdiff, stat_vis, stat_rank, stat_ranges, stat_depth, stat_tile, ghist_depth, ghist_tile;
+    size_t tickets, err;
+    size_t total;
     int64_t depth_nb, tile_nb;
     int tile_passes;
 };
@@ -937,8 +1100,10 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.tval = o;        o += align256((size_t)cap * 4);
     L.chunk_rank = o;  o += align256((size_t)(L.tile_nb + 1) * sizeof(int32_t));
     L.zero_begin = o;
+    L.gdiff = o;       o += align256((size_t)n_tiles * sizeof(int32_t));
     L.stat_vis = o;    o += align256((size_t)L.depth_nb * sizeof(uint64_t));
     L.stat_rank = o;   o += align256((size_t)L.depth_nb * sizeof(uint64_t));
+    L.stat_ranges = o; o += align256((size_t)((n_tiles + kSortChunk - 1) / kSortChunk) * sizeof(uint64_t));
     L.stat_depth = o;  o += align256((size_t)kDepthPasses * L.depth_nb * stat_row);
     L.stat_tile = o;   o += align256((size_t)L.tile_passes * L.tile_nb * stat_row);
     L.ghist_depth = o; o += align256((size_t)kDepthPasses * kRadix * sizeof(unsigned));
@@ -986,6 +1151,8 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: capacity must be in [1, 2^31-1], n_tiles >= 1");
     if (n_splats > 0x7fffffffll)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: n_splats must be below 2^31");
+    if (n_cams > bins->n_tiles)
+        return set_error(GS_ERR_INVALID, "gs_bin_and_sort: more cameras than tiles");
     if (!bins->keys || !bins->ids || !bins->ranges || !bins->schedule || !bins->counters || !s->rect || !s->depth ||
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
@@ -999,12 +1166,14 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int32_t *dvalA = (int32_t *)(ws + L.dvalA), *dvalB = (int32_t *)(ws + L.dvalB);
     int64_t *dcount = (int64_t *)(ws + L.dcount);
     int64_t *offsets = (int64_t *)(ws + L.offsets);
+    int32_t *tile_cnt = (int32_t *)(ws + L.gdiff);
     uint64_t *stat_vis = (uint64_t *)(ws + L.stat_vis), *stat_rank = (uint64_t *)(ws + L.stat_rank);
+    uint64_t *stat_ranges = (uint64_t *)(ws + L.stat_ranges);
     uint64_t *stat_depth = (uint64_t *)(ws + L.stat_depth), *stat_tile = (uint64_t *)(ws + L.stat_tile);
     unsigned *ghist_depth = (unsigned *)(ws + L.ghist_depth), *ghist_tile = (unsigned *)(ws + L.ghist_tile);
     int32_t *tickets = (int32_t *)(ws + L.tickets);
     int32_t *tk_depth = tickets, *tk_tile = tickets + kDepthPasses;
-    int32_t *tk_vis = tickets + kDepthPasses + kMaxTilePasses, *tk_rank = tk_vis + 1;
+    int32_t *tk_vis = tickets + kDepthPasses + kMaxTilePasses, *tk_rank = tk_vis + 1, *tk_ranges = tk_vis + 2;
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
@@ -1018,10 +1187,20 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int rc = gs_zero(ws + L.zero_begin, L.total - L.zero_begin, st);
     if (rc != GS_OK) return rc;
 
-    // 1. depth order of the V visible splats: compacted keys and the digit counts of all
-    // passes, then four 8-bit passes (the result is back in A)
+    // 1. the V visible splats, compacted in slot order, with the digit counts of the depth
+    // passes; the list length of every tile from their boxes, and the digit counts of the
+    // tile passes from those
+    const int passes = L.tile_passes;
     hipLaunchKernelGGL(visible_keys_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
                        s->depth, n_splats, stat_vis, tk_vis, dkeyA, dvalA, dcount, ghist_depth, err);
+    const int64_t span = max((int64_t)8192, (n_splats + 511) / 512);
+    hipLaunchKernelGGL(tile_corner_kernel, dim3(grid_for(n_splats, (int)span)), dim3(kCornerBlock), 0, st,
+                       (const int32_t *)dvalA, (const int64_t *)dcount, (const int4 *)s->rect, cams, (int)n_cams,
+                       n_splats, span, tile_cnt);
+    hipLaunchKernelGGL(tile_count_kernel, dim3((unsigned)n_cams), dim3(kCountBlock), 0, st, cams, passes, tile_cnt,
+                       ghist_tile, err);
+
+    // 2. depth order: four 8-bit passes over the V keys (the result is back in A)
     for (int pass = 0; pass < kDepthPasses; ++pass) {
         const bool even = (pass & 1) == 0;
         hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st,
@@ -1034,15 +1213,10 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     if (rc != GS_OK) return rc;
     const int32_t *rank_ids = dvalA;
 
-    // 2. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
+    // 3. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
     hipLaunchKernelGGL(rank_offsets_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
                        rank_ids, (const int64_t *)dcount, n_splats, cap, stat_rank, tk_rank, offsets,
                        bins->counters, err);
-
-    // 3. digit histograms of the tile passes, from the boxes
-    const int passes = L.tile_passes;
-    hipLaunchKernelGGL(tile_hist_kernel, dim3(kHistBlocks), dim3(256), 0, st, s->tiles_touched, (const int4 *)s->rect,
-                       cams, (int)n_cams, n_splats, K, cap, passes, ghist_tile);
 
     // 4. stable passes by tile id. The first pass takes the entries in depth-rank order,
     // either emitted into a buffer or generated inside the pass (launch tuning); the last
@@ -1090,10 +1264,11 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     }
     rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, st, bins->keys, K, cap, bins->n_tiles,
-                       bins->ranges, (const int64_t *)err);
+    // 5. ranges from the list lengths, when the list was built
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(bins->n_tiles, kSortChunk)), dim3(kSortBlock), 0, st,
+                       (const int32_t *)tile_cnt, bins->n_tiles, K, cap, stat_ranges, tk_ranges, bins->ranges, err);
 
-    // 5. the work list; the sort's error word joins the overflow flag
+    // 6. the work list; the sort's error word joins the overflow flag
     hipLaunchKernelGGL(err_fold_kernel, dim3(1), dim3(64), 0, st, bins->counters, (const int64_t *)err);
     return build_schedule(bins, st);
 }

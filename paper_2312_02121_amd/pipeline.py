@@ -31,9 +31,12 @@ def make_params(alpha_min: float = STANDARD_PARAMS["alpha_min"], alpha_max: floa
 
 
 def check_sort_flag(flag: int):
-    """gs_bin_and_sort sets bit 2 of counters[1] when a look-back wait of its sort gave up."""
+    """gs_bin_and_sort sets bit 2 of counters[1] when a look-back wait of its sort gave up (or
+    its counts disagree), bit 4 for a camera wider than 8192 tiles."""
     if flag & 2:
         raise RuntimeError("gs_bin_and_sort: the single-pass sort's look-back did not complete; the list is invalid")
+    if flag & 4:
+        raise RuntimeError("gs_bin_and_sort: a camera is wider than 8192 tiles (131072 pixels); nothing was listed")
 
 
 def current_stream() -> int:

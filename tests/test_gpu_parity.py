@@ -31,6 +31,8 @@ def _workloads():
         "tiny_tilted": synth.tilted_camera_scene(40, n=200, width=70, height=45),
         "c2_20k": synth.make_config(2, n_override=20_000),
         "dense_small": synth.tiny_scene(41, n=600, width=100, height=77, log_scale=(-1.5, 0.6), opac_sd=2.5),
+        # 257 x 125 tiles: more than one LDS band of the per-tile length count
+        "wide_4k": synth.tiny_scene(42, n=500, width=4100, height=2000, f=2000.0, log_scale=(-2.0, 0.8)),
     }
 
 
@@ -53,7 +55,7 @@ def test_projection_bit_exact(name):
 
 
 @pytest.mark.parametrize("generate", [0, 1])
-@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small"])
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small", "wide_4k"])
 def test_bins_bit_exact(name, generate):
     """Both first tile-sort passes (emitted list, or entries generated inside the pass)."""
     _print_case("bins", wl=name, generate_entries=generate)
