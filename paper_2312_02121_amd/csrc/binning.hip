@@ -35,6 +35,8 @@
 // host-known capacities and reads its element count from device memory, and the
 // look-back state is cleared by a kernel at the start of each call, so the whole sequence
 // replays unchanged inside a captured HIP graph.
+#include <mutex>
+
 #include "common.h"
 
 namespace gsx {
@@ -143,18 +145,20 @@ __device__ inline void count_digits(const uint32_t (&key)[kSortItems], int64_t c
 constexpr uint64_t kStatAgg = 1ull << 62;
 constexpr uint64_t kStatInc = 2ull << 62;
 constexpr uint64_t kStatValue = (1ull << 62) - 1;
-constexpr int kSpinLimit = 1 << 24;   // bounded wait: a predecessor that never publishes ends the wait
+constexpr int kSpinLimit = 1 << 20;   // bounded wait: a predecessor that never publishes ends the wait
 
-// The block's chunk index from the ticket counter, in the order blocks start, so a block
-// only ever waits on chunks held by blocks already running; -1 when an earlier step of the
-// sequence gave up (the error word is set), and the block then does nothing.
-__device__ inline int take_ticket(int32_t *ticket, const int64_t *err_flag, int *sh_chunk)
+// Chunks of a single-pass launch are dealt to a grid of blocks that are all resident at
+// once: block g takes chunks g, g + G, g + 2G, ... (G = gridDim.x) in turn. A chunk only
+// waits on lower chunks, which are held by running blocks, so every wait ends without a
+// global ticket counter (one atomic per chunk on a single address, which serialises the
+// launch on this device). Called at the top of each turn: returns true when an earlier
+// step of the sequence gave up (the error word is set); the block then stops.
+__device__ inline bool chunk_stop(const int64_t *err_flag, int *sh_flag)
 {
-    if (threadIdx.x == 0)
-        *sh_chunk = __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? -1
-                                                                                            : atomicAdd(ticket, 1);
+    __syncthreads();   // the previous turn's use of LDS has ended
+    if (threadIdx.x == 0) *sh_flag = __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     __syncthreads();
-    return *sh_chunk;
+    return *sh_flag != 0;
 }
 
 // Gives up a look-back wait after kSpinLimit polls, or early once another block has given
@@ -172,33 +176,54 @@ __device__ inline bool spin_exhausted(int &spins, int64_t *err_flag)
 }
 
 // Exclusive prefix of chunk b > 0 of a single-pass scan, from the status words of chunks
-// 0 .. b - 1. Executed by one whole wave: lane l reads chunk j - l, so each step looks 64
-// chunks back; the prefix is the sum of the values up to the nearest inclusive one. Every
-// lane returns the prefix, or -1 when the wait gave up.
+// 0 .. b - 1. Executed by the whole block (kSortBlock threads): thread t reads chunk j - t,
+// so each step looks kSortBlock chunks back; the prefix is the sum of the values up to the
+// nearest inclusive one. Every thread returns the prefix, or -1 when the wait gave up.
 __device__ inline int64_t chained_prefix(const uint64_t *status, int b, int64_t *err_flag)
 {
-    const int lane = threadIdx.x & (kWave - 1);
+    __shared__ uint64_t s_inc[kSortWaves], s_nr[kSortWaves];
+    __shared__ int64_t s_sum[kSortWaves];
+    __shared__ int s_stop;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int64_t acc = 0;
     int j = b - 1;
     int spins = 0;
     while (true) {
-        const int idx = j - lane;
+        const int idx = j - (int)threadIdx.x;
         const uint64_t st =
             idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStatInc;
         const uint64_t flag = st & ~kStatValue;
-        const uint64_t inc = __ballot(flag == kStatInc);
-        const uint64_t first = inc & (~inc + 1);                 // nearest inclusive chunk
-        const uint64_t need = inc ? (first | (first - 1)) : ~0ull;
-        if (__ballot(flag == 0) & need) {
-            if (spin_exhausted(spins, err_flag)) return -1;
+        const uint64_t inc = __ballot(flag == kStatInc), nr = __ballot(flag == 0);
+        if (lane == 0) {
+            s_inc[wave] = inc;
+            s_nr[wave] = nr;
+        }
+        __syncthreads();
+        int first = kSortBlock;   // position of the nearest inclusive chunk in this window
+        bool blocked = false;     // a chunk up to it has not published yet
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            if (first < kSortBlock) break;
+            const uint64_t iw = s_inc[w], low = iw & (~iw + 1);
+            if (s_nr[w] & (iw ? (low | (low - 1)) : ~0ull)) blocked = true;
+            if (iw) first = w * kWave + __builtin_ctzll(iw);
+        }
+        if (blocked) {   // uniform: every thread read the same words
+            if (threadIdx.x == 0) s_stop = spin_exhausted(spins, err_flag) ? 1 : 0;
+            __syncthreads();
+            if (s_stop) return -1;
             continue;
         }
-        int64_t v = ((need >> lane) & 1) ? (int64_t)(st & kStatValue) : 0;
+        int64_t v = (int)threadIdx.x <= first ? (int64_t)(st & kStatValue) : 0;
 #pragma unroll
         for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-        acc += v;
-        if (inc) return acc;
-        j -= kWave;
+        if (lane == 0) s_sum[wave] = v;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) acc += s_sum[w];
+        __syncthreads();   // the window's shared words are rewritten by the next step
+        if (first < kSortBlock) return acc;
+        j -= kSortBlock;
     }
 }
 
@@ -212,12 +237,13 @@ struct SweepShared {
     int chunk, gave_up;
 };
 
-// Chunk index of the block (-1: do nothing), with the counters cleared.
-__device__ inline int sweep_ticket(SweepShared &sh, int32_t *ticket, const int64_t *err_flag)
+// Start of a turn: clears the counters; true when the block is to stop (see chunk_stop).
+__device__ inline bool sweep_begin(SweepShared &sh, const int64_t *err_flag)
 {
+    __syncthreads();
     if (threadIdx.x == 0) sh.gave_up = 0;
     for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortBlock) (&sh.cnt[0][0])[d] = 0;
-    return take_ticket(ticket, err_flag, &sh.chunk);
+    return chunk_stop(err_flag, &sh.chunk);
 }
 
 // One stable LSD pass over chunk b, keys already in registers in the wave-strided layout
@@ -226,12 +252,14 @@ __device__ inline int sweep_ticket(SweepShared &sh, int32_t *ticket, const int64
 // digit counts, looks back over its predecessors' published counts for its global
 // offsets, stages the chunk in LDS in digit order and writes it out in runs. With
 // keys64_out set (the last tile pass) it writes ids and the 64-bit keys
-// (tile << 32 | depth bits of the value) instead of 32-bit keys.
+// (tile << 32 | depth bits of the value) instead of 32-bit keys; with gather_dst set it
+// also writes gather_src[value] there in output order (keys_out may then be null).
 __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortItems],
                                   const int32_t (&val)[kSortItems], int b, int64_t base, int64_t kvalid, int shift,
                                   const unsigned *__restrict__ ghist, uint64_t *__restrict__ status,
                                   uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out,
                                   uint64_t *__restrict__ keys64_out, const float *__restrict__ depth,
+                                  const int32_t *__restrict__ gather_src, int32_t *__restrict__ gather_dst,
                                   int64_t n_splats, int64_t *__restrict__ err_flag)
 {
     const int n_here = (int)min((int64_t)kSortChunk, kvalid - base);
@@ -323,45 +351,47 @@ __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortIt
             const uint32_t dbits = (uint64_t)(uint32_t)v < (uint64_t)n_splats ? __float_as_uint(depth[v]) : 0u;
             keys64_out[g] = ((uint64_t)k << 32) | (uint64_t)dbits;
         } else {
-            keys_out[g] = k;
+            if (keys_out) keys_out[g] = k;
+            if (gather_dst) gather_dst[g] = (uint64_t)(uint32_t)v < (uint64_t)n_splats ? gather_src[v] : 0;
         }
     }
 }
 
-// One stable LSD pass with decoupled look-back (chained scan over blocks), in one launch.
-// Blocks take chunk indices from a ticket counter in launch order, so every chunk a block
-// waits on belongs to a block that is already running.
+// One stable LSD pass with decoupled look-back (chained scan over chunks), in one launch of
+// resident blocks (chunk_stop).
 __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__restrict__ keys_in,
                                                               const int32_t *__restrict__ vals_in,
                                                               const int64_t *__restrict__ count, int64_t cap,
                                                               int shift, const unsigned *__restrict__ ghist,
                                                               uint64_t *__restrict__ status,
-                                                              int32_t *__restrict__ ticket,
                                                               uint32_t *__restrict__ keys_out,
                                                               int32_t *__restrict__ vals_out,
                                                               uint64_t *__restrict__ keys64_out,
                                                               const float *__restrict__ depth,
+                                                              const int32_t *__restrict__ gather_src,
+                                                              int32_t *__restrict__ gather_dst,
                                                               int64_t n_splats, int all_or_none,
                                                               int64_t *__restrict__ err_flag)
 {
     __shared__ SweepShared sh;
-    const int b = sweep_ticket(sh, ticket, err_flag);
-    if (b < 0) return;
     const int64_t kvalid = all_or_none ? tile_sort_count(count, cap) : sort_count(count, cap);
-    const int64_t base = (int64_t)b * kSortChunk;
-    if (base >= kvalid) return;   // uniform over the block; no valid chunk waits on it
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t key[kSortItems];
-    int32_t val[kSortItems];
+    for (int64_t b = blockIdx.x; b * kSortChunk < kvalid; b += gridDim.x) {
+        if (sweep_begin(sh, err_flag)) break;
+        const int64_t base = b * kSortChunk;
+        uint32_t key[kSortItems];
+        int32_t val[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-        const bool ok = idx < kvalid;
-        key[r] = ok ? keys_in[idx] : 0u;
-        val[r] = ok ? vals_in[idx] : 0;
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
+            const bool ok = idx < kvalid;
+            key[r] = ok ? keys_in[idx] : 0u;
+            val[r] = ok ? vals_in[idx] : 0;
+        }
+        sweep_body(sh, key, val, (int)b, base, kvalid, shift, ghist, status, keys_out, vals_out, keys64_out, depth,
+                   gather_src, gather_dst, n_splats, err_flag);
+        if (sh.gave_up) break;   // uniform: set before a barrier inside sweep_body
     }
-    sweep_body(sh, key, val, b, base, kvalid, shift, ghist, status, keys_out, vals_out, keys64_out, depth, n_splats,
-               err_flag);
 }
 
 // The first tile pass, over entries it generates itself: list entry k belongs to the splat
@@ -372,195 +402,241 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__
 // into the strided layout of the ranking.
 __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
     const int32_t *__restrict__ rank_ids, const int64_t *__restrict__ offsets, const int32_t *__restrict__ chunk_rank,
-    const int32_t *__restrict__ tiles, const int4 *__restrict__ rect, const gs_camera *__restrict__ cams, int n_cams,
-    int64_t n_splats, const int64_t *__restrict__ vcount, const int64_t *__restrict__ count, int64_t cap,
-    const unsigned *__restrict__ ghist, uint64_t *__restrict__ status, int32_t *__restrict__ ticket,
-    uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out, uint64_t *__restrict__ keys64_out,
-    const float *__restrict__ depth, int64_t *__restrict__ err_flag)
+    const int32_t *__restrict__ rank_tiles, const int4 *__restrict__ rect, const gs_camera *__restrict__ cams,
+    int n_cams, int64_t n_splats, const int64_t *__restrict__ vcount, const int64_t *__restrict__ count, int64_t cap,
+    const unsigned *__restrict__ ghist, uint64_t *__restrict__ status, uint32_t *__restrict__ keys_out,
+    int32_t *__restrict__ vals_out, uint64_t *__restrict__ keys64_out, const float *__restrict__ depth,
+    int64_t *__restrict__ err_flag)
 {
     __shared__ SweepShared sh;
     __shared__ int n_ranks;
-    const int b = sweep_ticket(sh, ticket, err_flag);
-    if (b < 0) return;
     const int64_t kvalid = tile_sort_count(count, cap);
-    const int64_t base = (int64_t)b * kSortChunk;
-    if (base >= kvalid) return;   // uniform over the block
-    const int n_here = (int)min((int64_t)kSortChunk, kvalid - base);
     const int64_t n_chunks = (kvalid + kSortChunk - 1) / kSortChunk;
-    const int r0 = chunk_rank[b];
-    if (threadIdx.x == 0) {
-        const int64_t V = *vcount;
-        const int64_t r_end = b + 1 < n_chunks ? (int64_t)chunk_rank[b + 1] : V - 1;
-        n_ranks = (int)min((int64_t)kSortChunk, r_end - r0 + 1);
-        // a rank outside [0, V) would mean inconsistent counts: report, write nothing
-        if (r0 < 0 || r0 >= V || r_end < r0 || r_end >= V || V > n_splats) {
-            n_ranks = 0;
-            __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    __syncthreads();
-    const int nr = n_ranks;
-    if (nr == 0) return;   // uniform; successors waiting on this chunk give up after the spin limit
-    // rank start offsets relative to the chunk (the first one is <= 0)
-    int32_t *roff = (int32_t *)sh.skey;
-    for (int i = threadIdx.x; i < nr; i += kSortBlock) roff[i] = (int32_t)(offsets[r0 + i] - base);
-    __syncthreads();
-
-    uint32_t gk[kSortItems];
-    int32_t gv[kSortItems];
-    const int e0 = threadIdx.x * kSortItems;   // chunk-relative index of this thread's first entry
-    if (e0 < n_here) {
-        int lo = 0, hi = nr - 1;               // last rank with roff <= e0
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (roff[mid] <= e0) lo = mid; else hi = mid - 1;
-        }
-        int ri = lo;
-        int slot = rank_ids[r0 + ri];
-        int4 bx = rect[slot];
-        int c = camera_of_splat(cams, n_cams, slot);
-        int toff = cams[c].tile_offset, tx_n = cams[c].tiles_x;
-        int w = bx.z - bx.x + 1;
-        int j = e0 - roff[ri];                 // index within the splat's box
-        int ntile = tiles[slot];
-        int ty = bx.y + j / w, tx = bx.x + j % w;
-#pragma unroll
-        for (int q = 0; q < kSortItems; ++q) {
-            if (j == ntile && e0 + q < n_here) {  // next splat in rank order
-                ++ri;
-                slot = rank_ids[r0 + ri];
-                bx = rect[slot];
-                c = camera_of_splat(cams, n_cams, slot);
-                toff = cams[c].tile_offset;
-                tx_n = cams[c].tiles_x;
-                w = bx.z - bx.x + 1;
-                ntile = tiles[slot];
-                j = 0;
-                ty = bx.y;
-                tx = bx.x;
-            }
-            gk[q] = (uint32_t)(toff + ty * tx_n + tx);
-            gv[q] = slot;
-            ++j;
-            if (++tx > bx.z) {
-                tx = bx.x;
-                ++ty;
-            }
-        }
-    }
-    __syncthreads();   // roff is no longer read
-    if (e0 < n_here) {
-#pragma unroll
-        for (int q = 0; q < kSortItems; ++q) {
-            sh.skey[e0 + q] = gk[q];
-            sh.sval[e0 + q] = gv[q];
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t key[kSortItems];
-    int32_t val[kSortItems];
+    for (int64_t b = blockIdx.x; b < n_chunks; b += gridDim.x) {
+        if (sweep_begin(sh, err_flag)) break;
+        const int64_t base = b * kSortChunk;
+        const int n_here = (int)min((int64_t)kSortChunk, kvalid - base);
+        const int r0 = chunk_rank[b];
+        if (threadIdx.x == 0) {
+            const int64_t V = *vcount;
+            const int64_t r_end = b + 1 < n_chunks ? (int64_t)chunk_rank[b + 1] : V - 1;
+            n_ranks = (int)min((int64_t)kSortChunk, r_end - r0 + 1);
+            // a rank outside [0, V) would mean inconsistent counts: report, write nothing
+            if (r0 < 0 || r0 >= V || r_end < r0 || r_end >= V || V > n_splats) {
+                n_ranks = 0;
+                __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        const int nr = n_ranks;
+        if (nr == 0) break;   // uniform; blocks waiting on this chunk see the error word and stop
+        // rank start offsets relative to the chunk (the first one is <= 0)
+        int32_t *roff = (int32_t *)sh.skey;
+        for (int i = threadIdx.x; i < nr; i += kSortBlock) roff[i] = (int32_t)(offsets[r0 + i] - base);
+        __syncthreads();
+
+        uint32_t gk[kSortItems];
+        int32_t gv[kSortItems];
+        const int e0 = threadIdx.x * kSortItems;   // chunk-relative index of this thread's first entry
+        if (e0 < n_here) {
+            int lo = 0, hi = nr - 1;               // last rank with roff <= e0
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (roff[mid] <= e0) lo = mid; else hi = mid - 1;
+            }
+            int ri = lo;
+            int slot = rank_ids[r0 + ri];
+            int4 bx = rect[slot];
+            int c = camera_of_splat(cams, n_cams, slot);
+            int toff = cams[c].tile_offset, tx_n = cams[c].tiles_x;
+            int w = bx.z - bx.x + 1;
+            int j = e0 - roff[ri];                 // index within the splat's box
+            int ntile = rank_tiles[r0 + ri];
+            int ty = bx.y + j / w, tx = bx.x + j % w;
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int i = wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-        const bool ok = i < n_here;
-        key[r] = ok ? sh.skey[i] : 0u;
-        val[r] = ok ? sh.sval[i] : 0;
+            for (int q = 0; q < kSortItems; ++q) {
+                if (j == ntile && e0 + q < n_here) {  // next splat in rank order
+                    ++ri;
+                    slot = rank_ids[r0 + ri];
+                    bx = rect[slot];
+                    c = camera_of_splat(cams, n_cams, slot);
+                    toff = cams[c].tile_offset;
+                    tx_n = cams[c].tiles_x;
+                    w = bx.z - bx.x + 1;
+                    ntile = rank_tiles[r0 + ri];
+                    j = 0;
+                    ty = bx.y;
+                    tx = bx.x;
+                }
+                gk[q] = (uint32_t)(toff + ty * tx_n + tx);
+                gv[q] = slot;
+                ++j;
+                if (++tx > bx.z) {
+                    tx = bx.x;
+                    ++ty;
+                }
+            }
+        }
+        __syncthreads();   // roff is no longer read
+        if (e0 < n_here) {
+#pragma unroll
+            for (int q = 0; q < kSortItems; ++q) {
+                sh.skey[e0 + q] = gk[q];
+                sh.sval[e0 + q] = gv[q];
+            }
+        }
+        __syncthreads();
+        uint32_t key[kSortItems];
+        int32_t val[kSortItems];
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const int i = wave * (kSortChunk / kSortWaves) + r * kWave + lane;
+            const bool ok = i < n_here;
+            key[r] = ok ? sh.skey[i] : 0u;
+            val[r] = ok ? sh.sval[i] : 0;
+        }
+        __syncthreads();   // the staging arrays are reused by the ranking
+        sweep_body(sh, key, val, (int)b, base, kvalid, 0, ghist, status, keys_out, vals_out, keys64_out, depth,
+                   (const int32_t *)nullptr, (int32_t *)nullptr, n_splats, err_flag);
+        if (sh.gave_up) break;
     }
-    __syncthreads();   // the staging arrays are reused by the ranking
-    sweep_body(sh, key, val, b, base, kvalid, 0, ghist, status, keys_out, vals_out, keys64_out, depth, n_splats,
-               err_flag);
 }
 
 // ------------------------------------------------------------------- depth order, emit
 
-// Depth keys of the splats that touch at least one tile, compacted in slot order by a
-// single-pass scan over the visibility flags: key = float bits of t_z (positive, so bit
-// order is value order), value = slot. The grid has one block per chunk of kSortChunk
-// slots. Each block also counts the digits of every depth pass over the keys it keeps
-// (ghist[pass][digit], from the kept keys compacted in LDS); the block of the last chunk
-// stores the count V.
-__global__ __launch_bounds__(kSortBlock) void visible_keys_kernel(
-    const int32_t *__restrict__ tiles, const float *__restrict__ depth, int64_t n, uint64_t *__restrict__ status,
-    int32_t *__restrict__ ticket, uint32_t *__restrict__ dkey, int32_t *__restrict__ dval,
-    int64_t *__restrict__ count, unsigned *__restrict__ ghist, int64_t *__restrict__ err_flag)
+// Depth keys of the splats that touch at least one tile, compacted in slot order: key =
+// float bits of t_z (positive, so bit order is value order), value = slot. Three launches
+// in which no block waits on another: per-chunk counts of the visible slots (chunks of
+// kSortChunk slots), their exclusive scan (one block, which also stores V), then every
+// chunk writes its kept keys at its offset; depth_hist_kernel then counts the digits of
+// every depth pass over them.
+
+// Visible slots among chunk c's kSortChunk slots (wave w, row r, lane l holds slot
+// c * kSortChunk + w * M + 64 r + l, M = kSortChunk / kSortWaves).
+__device__ inline unsigned chunk_visible(const int32_t *__restrict__ tiles, int64_t n, int64_t c,
+                                         uint64_t (&vis)[kSortItems])
 {
-    __shared__ unsigned cnt[kDepthPasses][kSortWaves][kRadix];
-    __shared__ uint32_t kept[kSortChunk];
-    __shared__ unsigned wave_tot[kSortWaves];
-    __shared__ int64_t prefix;
-    __shared__ int chunk;
-    const int b = take_ticket(ticket, err_flag, &chunk);
-    if (b < 0) return;
-    const int64_t base = (int64_t)b * kSortChunk;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int64_t wbase = base + (int64_t)wave * (kSortChunk / kSortWaves);
-    uint32_t key[kSortItems];
-    uint64_t vis[kSortItems];
+    const int64_t wbase = c * kSortChunk + (int64_t)wave * (kSortChunk / kSortWaves);
     unsigned mine = 0;
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = wbase + r * kWave + lane;
-        const bool ok = idx < n && tiles[idx] > 0;
-        key[r] = ok ? __float_as_uint(depth[idx]) : 0u;
-        vis[r] = __ballot(ok);
+        vis[r] = __ballot(idx < n && tiles[idx] > 0);
         mine += (unsigned)__popcll(vis[r]);
     }
-    if (lane == 0) wave_tot[wave] = mine;
-    __syncthreads();
-    unsigned before = 0, total = 0;
+    return mine;   // this wave's count
+}
+
+__global__ __launch_bounds__(kSortBlock) void visible_count_kernel(const int32_t *__restrict__ tiles, int64_t n,
+                                                                   int32_t *__restrict__ chunk_cnt)
+{
+    __shared__ unsigned wave_tot[kSortWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t n_chunks = (n + kSortChunk - 1) / kSortChunk;
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        uint64_t vis[kSortItems];
+        const unsigned mine = chunk_visible(tiles, n, c, vis);
+        __syncthreads();
+        if (lane == 0) wave_tot[wave] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned t = 0;
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-        const unsigned x = wave_tot[w];
-        if (w < wave) before += x;
-        total += x;
-    }
-    if (wave == 0) {
-        int64_t ex = 0;
-        if (b == 0) {
-            if (lane == 0)
-                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            ex = chained_prefix(status, b, err_flag);
-            if (lane == 0 && ex >= 0)
-                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            prefix = ex;
-            if (ex >= 0 && base + kSortChunk >= n) *count = ex + total;
+            for (int w = 0; w < kSortWaves; ++w) t += wave_tot[w];
+            chunk_cnt[c] = (int32_t)t;
         }
     }
-    __syncthreads();
-    if (prefix < 0) return;   // uniform: the wait gave up and the error word is set
-    unsigned local = before;   // block-local position of the wave's next kept key
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        if ((vis[r] >> lane) & 1) {
-            const unsigned l = local + (unsigned)__popcll(vis[r] & lanemask_lt());
-            dkey[prefix + l] = key[r];
-            dval[prefix + l] = (int32_t)(wbase + r * kWave + lane);
-            kept[l] = key[r];
-        }
-        local += (unsigned)__popcll(vis[r]);
+}
+
+// One block: exclusive scan in place of the per-chunk values of n_items items (chunks of
+// kSortChunk; n_items from *n_dev when given), a contiguous run of chunks per thread. The
+// total goes to *total and, when flag is given, (total > cap) to *flag.
+template <typename T>
+__global__ __launch_bounds__(kScanBlock) void chunk_scan_kernel(T *__restrict__ val, int64_t n_items,
+                                                                const int64_t *__restrict__ n_dev,
+                                                                int64_t *__restrict__ total,
+                                                                int64_t *__restrict__ flag, int64_t cap)
+{
+    const int64_t items = n_dev ? *n_dev : n_items;
+    const int64_t n_chunks = (items + kSortChunk - 1) / kSortChunk;
+    const int64_t per = (n_chunks + kScanBlock - 1) / kScanBlock;
+    const int64_t s0 = min(n_chunks, (int64_t)threadIdx.x * per), s1 = min(n_chunks, s0 + per);
+    int64_t sum = 0;
+    for (int64_t i = s0; i < s1; ++i) sum += val[i];
+    int64_t tot;
+    int64_t run = block_exclusive_scan<int64_t>(sum, &tot);
+    for (int64_t i = s0; i < s1; ++i) {
+        const T v = val[i];
+        val[i] = (T)run;
+        run += v;
     }
-    // digit counts of every depth pass over the kept keys, read back compacted from LDS in
-    // rows of 64 dealt to the waves in turn
-    for (int i = threadIdx.x; i < kDepthPasses * kSortWaves * kRadix; i += kSortBlock) (&cnt[0][0][0])[i] = 0;
-    __syncthreads();
-    for (int row = wave; row * kWave < (int)total; row += kSortWaves) {
-        const int i = row * kWave + lane;
-        const bool ok = i < (int)total;
-        const uint32_t k = ok ? kept[i] : 0u;
-        const uint64_t valid = __ballot(ok);
+    if (threadIdx.x == 0) {
+        *total = tot;
+        if (flag) *flag = tot > cap ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void visible_write_kernel(
+    const int32_t *__restrict__ tiles, const float *__restrict__ depth, int64_t n,
+    const int32_t *__restrict__ chunk_off, uint32_t *__restrict__ dkey, int32_t *__restrict__ dval)
+{
+    __shared__ unsigned wave_tot[kSortWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t n_chunks = (n + kSortChunk - 1) / kSortChunk;
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        uint64_t vis[kSortItems];
+        const unsigned mine = chunk_visible(tiles, n, c, vis);
+        __syncthreads();   // the previous chunk's use of wave_tot has ended
+        if (lane == 0) wave_tot[wave] = mine;
+        __syncthreads();
+        unsigned before = 0;
 #pragma unroll
-        for (int pass = 0; pass < kDepthPasses; ++pass) {
-            const unsigned dg = (k >> (pass * kRadixBits)) & (kRadix - 1);
-            const uint64_t peers = match_digit(dg, valid);
-            if (ok && (peers & lanemask_lt()) == 0) cnt[pass][wave][dg] += (unsigned)__popcll(peers);
+        for (int w = 0; w < kSortWaves; ++w)
+            if (w < wave) before += wave_tot[w];
+        const int64_t prefix = chunk_off[c];
+        const int64_t wbase = c * kSortChunk + (int64_t)wave * (kSortChunk / kSortWaves);
+        unsigned local = before;   // block-local position of the wave's next kept key
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            if ((vis[r] >> lane) & 1) {
+                const int64_t idx = wbase + r * kWave + lane;
+                const unsigned l = local + (unsigned)__popcll(vis[r] & lanemask_lt());
+                dkey[prefix + l] = __float_as_uint(depth[idx]);
+                dval[prefix + l] = (int32_t)idx;
+            }
+            local += (unsigned)__popcll(vis[r]);
+        }
+    }
+}
+
+// Digit counts of every depth pass over the V compacted keys: per-wave LDS histograms
+// (LDS atomics contend only within a wave), added to ghist[pass][digit] once per block.
+__global__ __launch_bounds__(kSortBlock) void depth_hist_kernel(const uint32_t *__restrict__ dkey,
+                                                                const int64_t *__restrict__ vcount,
+                                                                unsigned *__restrict__ ghist)
+{
+    __shared__ unsigned h[kSortWaves][kDepthPasses][kRadix];
+    const int wave = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kSortWaves * kDepthPasses * kRadix; i += kSortBlock) (&h[0][0][0])[i] = 0;
+    __syncthreads();
+    const int64_t V = *vcount;
+    constexpr int kU = 8;
+    for (int64_t i0 = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i0 < V;
+         i0 += (int64_t)gridDim.x * kSortBlock * kU) {
+        uint32_t k[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = i0 + (int64_t)u * gridDim.x * kSortBlock;
+            k[u] = i < V ? dkey[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (i0 + (int64_t)u * gridDim.x * kSortBlock >= V) continue;
+#pragma unroll
+            for (int pass = 0; pass < kDepthPasses; ++pass)
+                atomicAdd(&h[wave][pass][(k[u] >> (pass * kRadixBits)) & (kRadix - 1)], 1u);
         }
     }
     __syncthreads();
@@ -569,95 +645,80 @@ __global__ __launch_bounds__(kSortBlock) void visible_keys_kernel(
     for (int pass = 0; pass < kDepthPasses; ++pass) {
         unsigned tot = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) tot += cnt[pass][w][d];
+        for (int w = 0; w < kSortWaves; ++w) tot += h[w][pass][d];
         if (tot) atomicAdd(&ghist[pass * kRadix + d], tot);
     }
 }
 
 // Emit offsets: exclusive scan of tiles_touched in depth-rank order over the V visible
-// splats, as a single-pass scan (one block per chunk of kSortChunk ranks, 16 consecutive
-// ranks per thread). The block of the last chunk stores K = the total in counters[0] and
-// the overflow flag (K > capacity) in counters[1]; chunk 0 always runs, so V = 0 gives
-// K = 0.
-__global__ __launch_bounds__(kSortBlock) void rank_offsets_kernel(
-    const int32_t *__restrict__ tiles, const int32_t *__restrict__ rank_ids, const int64_t *__restrict__ vcount,
-    int64_t n_splats, int64_t cap, uint64_t *__restrict__ status, int32_t *__restrict__ ticket,
-    int64_t *__restrict__ offsets, int64_t *__restrict__ counters, int64_t *__restrict__ err_flag)
+// splats (rank_tiles, written in rank order by the last depth pass). Chunks of kSortChunk
+// ranks, 16 consecutive ranks per thread: per-chunk sums, their scan (chunk_scan_kernel,
+// which stores K and the overflow flag), then each chunk writes its offsets.
+__device__ inline void load_rank_tiles(const int32_t *__restrict__ rank_tiles, int64_t i0, int64_t V,
+                                       int32_t (&t)[kSortItems])
 {
-    __shared__ int64_t prefix;
-    __shared__ int chunk;
-    const int b = take_ticket(ticket, err_flag, &chunk);
-    if (b < 0) return;
-    const int64_t V = *vcount;
-    const int64_t base = (int64_t)b * kSortChunk;
-    if (b > 0 && base >= V) return;   // uniform; no chunk below V's last waits on it
-    const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
-    int32_t t[kSortItems];
     if (i0 + kSortItems <= V) {
-        const int4 *ids4 = reinterpret_cast<const int4 *>(rank_ids + i0);
-        int32_t id[kSortItems];
+        const int4 *t4 = reinterpret_cast<const int4 *>(rank_tiles + i0);
 #pragma unroll
         for (int q = 0; q < kSortItems / 4; ++q) {
-            const int4 v = ids4[q];
-            id[4 * q] = v.x; id[4 * q + 1] = v.y; id[4 * q + 2] = v.z; id[4 * q + 3] = v.w;
+            const int4 v = t4[q];
+            t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
         }
-#pragma unroll
-        for (int k = 0; k < kSortItems; ++k) t[k] = (uint32_t)id[k] < (uint64_t)n_splats ? tiles[id[k]] : 0;
     } else {
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
-            const int32_t id = i0 + k < V ? rank_ids[i0 + k] : -1;
-            t[k] = (uint32_t)id < (uint64_t)n_splats ? tiles[id] : 0;
-        }
+        for (int k = 0; k < kSortItems; ++k) t[k] = i0 + k < V ? rank_tiles[i0 + k] : 0;
     }
-    int64_t mine = 0;
+}
+
+__global__ __launch_bounds__(kSortBlock) void rank_sum_kernel(const int32_t *__restrict__ rank_tiles,
+                                                              const int64_t *__restrict__ vcount,
+                                                              int64_t *__restrict__ chunk_sum)
+{
+    const int64_t V = *vcount;
+    for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
+        int32_t t[kSortItems];
+        load_rank_tiles(rank_tiles, c * kSortChunk + (int64_t)threadIdx.x * kSortItems, V, t);
+        int64_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) mine += t[k];
-    int64_t total;
-    const int64_t ex_thread = block_exclusive_scan<int64_t>(mine, &total);
-    if (threadIdx.x < kWave) {
-        const int lane = threadIdx.x;
-        int64_t ex = 0;
-        if (b == 0) {
-            if (lane == 0)
-                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            ex = chained_prefix(status, b, err_flag);
-            if (lane == 0 && ex >= 0)
-                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            prefix = ex;
-            if (ex >= 0 && base + kSortChunk >= V) {
-                const int64_t K = ex + total;
-                counters[0] = K;
-                counters[1] = K > cap ? 1 : 0;
+        for (int k = 0; k < kSortItems; ++k) mine += t[k];
+        int64_t tot;
+        block_exclusive_scan<int64_t>(mine, &tot);
+        if (threadIdx.x == 0) chunk_sum[c] = tot;
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void rank_offsets_kernel(const int32_t *__restrict__ rank_tiles,
+                                                                  const int64_t *__restrict__ vcount,
+                                                                  const int64_t *__restrict__ chunk_off,
+                                                                  int64_t *__restrict__ offsets)
+{
+    const int64_t V = *vcount;
+    for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
+        const int64_t i0 = c * kSortChunk + (int64_t)threadIdx.x * kSortItems;
+        int32_t t[kSortItems];
+        load_rank_tiles(rank_tiles, i0, V, t);
+        int64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) mine += t[k];
+        int64_t tot;
+        int64_t run = block_exclusive_scan<int64_t>(mine, &tot) + chunk_off[c];
+        if (i0 + kSortItems <= V) {
+            longlong2 *o2 = reinterpret_cast<longlong2 *>(offsets + i0);
+#pragma unroll
+            for (int q = 0; q < kSortItems / 2; ++q) {
+                longlong2 v;
+                v.x = run;
+                run += t[2 * q];
+                v.y = run;
+                run += t[2 * q + 1];
+                o2[q] = v;
             }
-        }
-    }
-    __syncthreads();
-    if (prefix < 0) return;   // uniform: the wait gave up and the error word is set
-    int64_t run = prefix + ex_thread;
-    if (i0 + kSortItems <= V) {
-        longlong2 *o2 = reinterpret_cast<longlong2 *>(offsets + i0);
+        } else {
 #pragma unroll
-        for (int q = 0; q < kSortItems / 2; ++q) {
-            longlong2 v;
-            v.x = run;
-            run += t[2 * q];
-            v.y = run;
-            run += t[2 * q + 1];
-            o2[q] = v;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
-            if (i0 + k < V) offsets[i0 + k] = run;
-            run += t[k];
+            for (int k = 0; k < kSortItems; ++k) {
+                if (i0 + k < V) offsets[i0 + k] = run;
+                run += t[k];
+            }
         }
     }
 }
@@ -816,25 +877,24 @@ __global__ __launch_bounds__(kCountBlock) void tile_count_kernel(const gs_camera
         if ((&h[0][0])[i]) atomicAdd(&ghist[i], (&h[0][0])[i]);
 }
 
-// Ranges: exclusive scan of the list lengths in global tile order (single pass, chained
-// like the sorts; 16 consecutive tiles per thread), run only when the list was built (K
+// Ranges: exclusive scan of the list lengths in global tile order (single pass, chunks of
+// kSortChunk tiles, 16 consecutive tiles per thread), run only when the list was built (K
 // within the capacity, no error). A range is written only when it ends within K, so the
 // rasterizer never reads past the list; a range past K, or a total different from K,
 // marks the lengths inconsistent with the list (error word). Empty tiles get (0, 0).
 __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__restrict__ cnt, int32_t n_tiles,
                                                             const int64_t *__restrict__ K, int64_t cap,
                                                             uint64_t *__restrict__ status,
-                                                            int32_t *__restrict__ ticket,
                                                             int32_t *__restrict__ ranges,
                                                             int64_t *__restrict__ err_flag)
 {
     __shared__ int64_t prefix;
-    __shared__ int chunk;
+    __shared__ int stop;
     const int64_t k_all = *K;
     if (k_all > cap) return;   // uniform: the list was not built
-    const int b = take_ticket(ticket, err_flag, &chunk);
-    if (b < 0) return;
-    const int64_t base = (int64_t)b * kSortChunk;
+    for (int64_t b = blockIdx.x; b * kSortChunk < n_tiles; b += gridDim.x) {
+    if (chunk_stop(err_flag, &stop)) break;
+    const int64_t base = b * kSortChunk;
     const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
     int32_t n[kSortItems];
 #pragma unroll
@@ -844,29 +904,20 @@ __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__res
     for (int k = 0; k < kSortItems; ++k) mine += n[k];
     int64_t total;
     const int64_t ex_thread = block_exclusive_scan<int64_t>(mine, &total);
-    if (threadIdx.x < kWave) {
-        const int lane = threadIdx.x;
-        int64_t ex = 0;
-        if (b == 0) {
-            if (lane == 0)
-                __hip_atomic_store(status, kStatInc | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(status + b, kStatAgg | (uint64_t)total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            ex = chained_prefix(status, b, err_flag);
-            if (lane == 0 && ex >= 0)
-                __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            prefix = ex;
-            if (ex >= 0 && base + kSortChunk >= n_tiles && ex + total != k_all)
-                __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(status + b, (b == 0 ? kStatInc : kStatAgg) | (uint64_t)total, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t ex = b == 0 ? 0 : chained_prefix(status, (int)b, err_flag);
+    if (threadIdx.x == 0) {
+        if (b > 0 && ex >= 0)
+            __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        prefix = ex;
+        if (ex >= 0 && base + kSortChunk >= n_tiles && ex + total != k_all)
+            __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (prefix < 0) return;
+    if (prefix < 0) break;
     int64_t run = prefix + ex_thread;
     bool past = false;
 #pragma unroll
@@ -883,6 +934,7 @@ __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__res
         run = e;
     }
     if (past) __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Splats whose box has at most this many tiles are emitted by their own lane.
@@ -905,7 +957,7 @@ __device__ inline void emit_tiles(int64_t k0, int count_begin, int count_step, i
 // the box, row-major, at the rank's offset. Nothing is written when K exceeds the capacity.
 __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ rank_ids,
                                                    const int64_t *__restrict__ offsets,
-                                                   const int32_t *__restrict__ tiles, const int4 *__restrict__ rect,
+                                                   const int32_t *__restrict__ rank_tiles, const int4 *__restrict__ rect,
                                                    const gs_camera *__restrict__ cams, int n_cams, int64_t n_splats,
                                                    const int64_t *__restrict__ vcount,
                                                    const int64_t *__restrict__ K, int64_t cap,
@@ -920,7 +972,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
     int64_t k0 = 0;
     if (r < *vcount) {
         slot = rank_ids[r];
-        cnt = tiles[slot];
+        cnt = rank_tiles[r];
         k0 = offsets[r];
     }
     int toff = 0, tx_n = 1;
@@ -954,10 +1006,11 @@ __global__ __launch_bounds__(64) void err_fold_kernel(int64_t *__restrict__ coun
     if (threadIdx.x == 0 && *err) counters[1] |= *err;
 }
 
-// chunk_rank[c] = depth rank of the splat that holds list entry c * kSortChunk.
+// chunk_rank[c] = depth rank of the splat that holds list entry c * kSortChunk
+// (rank_tiles: tiles_touched in rank order).
 __global__ __launch_bounds__(256) void chunk_rank_kernel(const int32_t *__restrict__ rank_ids,
                                                          const int64_t *__restrict__ offsets,
-                                                         const int32_t *__restrict__ tiles,
+                                                         const int32_t *__restrict__ rank_tiles,
                                                          const int64_t *__restrict__ vcount,
                                                          const int64_t *__restrict__ count, int64_t cap,
                                                          int32_t *__restrict__ chunk_rank,
@@ -965,7 +1018,7 @@ __global__ __launch_bounds__(256) void chunk_rank_kernel(const int32_t *__restri
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (*err_flag || r >= *vcount) return;
-    const int n = tiles[rank_ids[r]];
+    const int n = rank_tiles[r];
     if (n <= 0) return;
     const int64_t kvalid = tile_sort_count(count, cap);
     const int64_t s = offsets[r], e = s + n;
@@ -1050,18 +1103,19 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
 
 // ------------------------------------------------------------------------ workspace
 
-// Workspace: depth-sort buffers (two key/value pairs over P splats), the visible count,
-// per-rank emit offsets, one 32-bit key/value pair over the capacity (the other pair of the
-// tile-sort ping-pong lives in bins->keys / bins->ids until the last pass overwrites them),
-// then a region cleared at the start of every call: the per-tile difference array (then
-// list lengths), the look-back status words of the three single-pass scans and of every
-// sort pass, the digit histograms, the chunk tickets and an error word.
+// Workspace: depth-sort buffers (two key/value pairs over P splats; the last depth pass
+// leaves the tile counts in rank order where the keys were), the visible count, per-rank
+// emit offsets, per-chunk counts and sums of the two scans, one 32-bit key/value pair over
+// the capacity (the other pair of the tile-sort ping-pong lives in bins->keys / bins->ids
+// until the last pass overwrites them), then a region cleared at the start of every call:
+// the per-tile difference array (then list lengths), the look-back status words of the
+// ranges scan and of every sort pass, the digit histograms and an error word.
 constexpr int kMaxTilePasses = 4;
 
 struct BinLayout {
-    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, tkey, tval, chunk_rank;
-    size_t zero_begin, gdiff, stat_vis, stat_rank, stat_ranges, stat_depth, stat_tile, ghist_depth, ghist_tile;
-    size_t tickets, err;
+    size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, chunk_cnt, chunk_sum, tkey, tval, chunk_rank;
+    size_t zero_begin, gdiff, stat_ranges, stat_depth, stat_tile, ghist_depth, ghist_tile;
+    size_t err;
     size_t total;
     int64_t depth_nb, tile_nb;
     int tile_passes;
@@ -1096,22 +1150,53 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.dvalB = o;       o += p4;
     L.dcount = o;      o += 256;
     L.offsets = o;     o += align256((size_t)n_splats * sizeof(int64_t));
+    L.chunk_cnt = o;   o += align256((size_t)L.depth_nb * sizeof(int32_t));
+    L.chunk_sum = o;   o += align256((size_t)L.depth_nb * sizeof(int64_t));
     L.tkey = o;        o += align256((size_t)cap * 4);
     L.tval = o;        o += align256((size_t)cap * 4);
     L.chunk_rank = o;  o += align256((size_t)(L.tile_nb + 1) * sizeof(int32_t));
     L.zero_begin = o;
     L.gdiff = o;       o += align256((size_t)n_tiles * sizeof(int32_t));
-    L.stat_vis = o;    o += align256((size_t)L.depth_nb * sizeof(uint64_t));
-    L.stat_rank = o;   o += align256((size_t)L.depth_nb * sizeof(uint64_t));
     L.stat_ranges = o; o += align256((size_t)((n_tiles + kSortChunk - 1) / kSortChunk) * sizeof(uint64_t));
     L.stat_depth = o;  o += align256((size_t)kDepthPasses * L.depth_nb * stat_row);
     L.stat_tile = o;   o += align256((size_t)L.tile_passes * L.tile_nb * stat_row);
     L.ghist_depth = o; o += align256((size_t)kDepthPasses * kRadix * sizeof(unsigned));
     L.ghist_tile = o;  o += align256((size_t)kMaxTilePasses * kRadix * sizeof(unsigned));
-    L.tickets = o;     o += 256;
     L.err = o;         o += 256;
     L.total = o;
     return L;
+}
+
+// Grid of a single-pass launch whose blocks wait on each other (chunk_stop): no more blocks
+// than the device holds at once for this kernel (its occupancy per CU, at most four), so
+// every block is resident and every wait ends; never more blocks than chunks.
+static unsigned resident_grid(const void *kernel, int block, int64_t chunks)
+{
+    struct Entry {
+        const void *k;
+        int dev, per_cu;
+    };
+    static std::mutex mu;
+    static Entry cache[32];
+    static int n_cache = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (int i = 0; i < n_cache; ++i)
+            if (cache[i].k == kernel && cache[i].dev == dev) per_cu = cache[i].per_cu;
+        if (per_cu == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) {
+                (void)hipGetLastError();
+                per_cu = 1;
+            }
+            per_cu = min(per_cu, 4);
+            if (n_cache < 32) cache[n_cache++] = Entry{kernel, dev, per_cu};
+        }
+    }
+    const int64_t g = (int64_t)device_cu_count() * per_cu;
+    return (unsigned)max((int64_t)1, min(g, chunks));
 }
 
 }  // namespace gsx
@@ -1167,13 +1252,11 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int64_t *dcount = (int64_t *)(ws + L.dcount);
     int64_t *offsets = (int64_t *)(ws + L.offsets);
     int32_t *tile_cnt = (int32_t *)(ws + L.gdiff);
-    uint64_t *stat_vis = (uint64_t *)(ws + L.stat_vis), *stat_rank = (uint64_t *)(ws + L.stat_rank);
+    int32_t *chunk_cnt = (int32_t *)(ws + L.chunk_cnt);
+    int64_t *chunk_sum = (int64_t *)(ws + L.chunk_sum);
     uint64_t *stat_ranges = (uint64_t *)(ws + L.stat_ranges);
     uint64_t *stat_depth = (uint64_t *)(ws + L.stat_depth), *stat_tile = (uint64_t *)(ws + L.stat_tile);
     unsigned *ghist_depth = (unsigned *)(ws + L.ghist_depth), *ghist_tile = (unsigned *)(ws + L.ghist_tile);
-    int32_t *tickets = (int32_t *)(ws + L.tickets);
-    int32_t *tk_depth = tickets, *tk_tile = tickets + kDepthPasses;
-    int32_t *tk_vis = tickets + kDepthPasses + kMaxTilePasses, *tk_rank = tk_vis + 1, *tk_ranges = tk_vis + 2;
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
@@ -1191,8 +1274,17 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     // passes; the list length of every tile from their boxes, and the digit counts of the
     // tile passes from those
     const int passes = L.tile_passes;
-    hipLaunchKernelGGL(visible_keys_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
-                       s->depth, n_splats, stat_vis, tk_vis, dkeyA, dvalA, dcount, ghist_depth, err);
+    // launches without waits between blocks take one block per chunk
+    const unsigned g_chunks = (unsigned)L.depth_nb;
+    const unsigned g_sort = resident_grid((const void *)onesweep_kernel, kSortBlock, L.depth_nb);
+    hipLaunchKernelGGL(visible_count_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, s->tiles_touched, n_splats,
+                       chunk_cnt);
+    hipLaunchKernelGGL(chunk_scan_kernel<int32_t>, dim3(1), dim3(kScanBlock), 0, st, chunk_cnt, n_splats,
+                       (const int64_t *)nullptr, dcount, (int64_t *)nullptr, (int64_t)0);
+    hipLaunchKernelGGL(visible_write_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, s->tiles_touched, s->depth,
+                       n_splats, (const int32_t *)chunk_cnt, dkeyA, dvalA);
+    hipLaunchKernelGGL(depth_hist_kernel, dim3((unsigned)min(L.depth_nb, (int64_t)device_cu_count() * 2)),
+                       dim3(kSortBlock), 0, st, (const uint32_t *)dkeyA, (const int64_t *)dcount, ghist_depth);
     const int64_t span = max((int64_t)8192, (n_splats + 511) / 512);
     hipLaunchKernelGGL(tile_corner_kernel, dim3(grid_for(n_splats, (int)span)), dim3(kCornerBlock), 0, st,
                        (const int32_t *)dvalA, (const int64_t *)dcount, (const int4 *)s->rect, cams, (int)n_cams,
@@ -1200,28 +1292,37 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     hipLaunchKernelGGL(tile_count_kernel, dim3((unsigned)n_cams), dim3(kCountBlock), 0, st, cams, passes, tile_cnt,
                        ghist_tile, err);
 
-    // 2. depth order: four 8-bit passes over the V keys (the result is back in A)
+    // 2. depth order: four 8-bit passes over the V keys (the result is back in A; the last
+    // pass writes the tile counts in rank order over the keys, which are not needed)
+    static_assert(kDepthPasses % 2 == 0, "the depth passes end in A");
+    int32_t *rank_tiles = (int32_t *)dkeyA;
     for (int pass = 0; pass < kDepthPasses; ++pass) {
-        const bool even = (pass & 1) == 0;
-        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st,
-                           even ? dkeyA : dkeyB, even ? dvalA : dvalB, (const int64_t *)dcount, n_splats,
-                           pass * kRadixBits, ghist_depth + pass * kRadix,
-                           stat_depth + (int64_t)pass * L.depth_nb * kRadix, tk_depth + pass, even ? dkeyB : dkeyA,
-                           even ? dvalB : dvalA, (uint64_t *)nullptr, (const float *)nullptr, n_splats, 0, err);
+        const bool even = (pass & 1) == 0, last = pass == kDepthPasses - 1;
+        hipLaunchKernelGGL(onesweep_kernel, dim3(g_sort), dim3(kSortBlock), 0, st, even ? dkeyA : dkeyB,
+                           even ? dvalA : dvalB, (const int64_t *)dcount, n_splats, pass * kRadixBits,
+                           ghist_depth + pass * kRadix, stat_depth + (int64_t)pass * L.depth_nb * kRadix,
+                           last ? (uint32_t *)nullptr : (even ? dkeyB : dkeyA), even ? dvalB : dvalA,
+                           (uint64_t *)nullptr, (const float *)nullptr,
+                           last ? (const int32_t *)s->tiles_touched : (const int32_t *)nullptr,
+                           last ? rank_tiles : (int32_t *)nullptr, n_splats, 0, err);
     }
     rc = check_launch("depth sort");
     if (rc != GS_OK) return rc;
     const int32_t *rank_ids = dvalA;
 
     // 3. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
-    hipLaunchKernelGGL(rank_offsets_kernel, dim3((unsigned)L.depth_nb), dim3(kSortBlock), 0, st, s->tiles_touched,
-                       rank_ids, (const int64_t *)dcount, n_splats, cap, stat_rank, tk_rank, offsets,
-                       bins->counters, err);
+    hipLaunchKernelGGL(rank_sum_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, (const int32_t *)rank_tiles,
+                       (const int64_t *)dcount, chunk_sum);
+    hipLaunchKernelGGL(chunk_scan_kernel<int64_t>, dim3(1), dim3(kScanBlock), 0, st, chunk_sum, (int64_t)0,
+                       (const int64_t *)dcount, bins->counters, bins->counters + 1, cap);
+    hipLaunchKernelGGL(rank_offsets_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, (const int32_t *)rank_tiles,
+                       (const int64_t *)dcount, (const int64_t *)chunk_sum, offsets);
 
     // 4. stable passes by tile id. The first pass takes the entries in depth-rank order,
     // either emitted into a buffer or generated inside the pass (launch tuning); the last
     // reads the workspace pair W and writes bins; in between, passes alternate between W
     // and the pair stored in bins' buffers.
+    const unsigned g_tile = resident_grid((const void *)onesweep_kernel, kSortBlock, L.tile_nb);
     uint32_t *kW = (uint32_t *)(ws + L.tkey), *kX = (uint32_t *)bins->keys;
     int32_t *vW = (int32_t *)(ws + L.tval), *vX = bins->ids;
     // the buffer pass i >= 1 reads: W when (passes - 1 - i) is even
@@ -1232,21 +1333,25 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     if (current_tuning().generate_entries) {
         int32_t *chunk_rank = (int32_t *)(ws + L.chunk_rank);
         hipLaunchKernelGGL(chunk_rank_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
-                           s->tiles_touched, (const int64_t *)dcount, K, cap, chunk_rank, (const int64_t *)err);
-        hipLaunchKernelGGL(onesweep_emit_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, rank_ids,
-                           offsets, (const int32_t *)chunk_rank, s->tiles_touched, (const int4 *)s->rect, cams,
-                           (int)n_cams, n_splats, (const int64_t *)dcount, K, cap, ghist_tile, stat_tile, tk_tile,
-                           k0out, v0out, k64, s->depth, err);
+                           (const int32_t *)rank_tiles, (const int64_t *)dcount, K, cap, chunk_rank,
+                           (const int64_t *)err);
+        hipLaunchKernelGGL(onesweep_emit_kernel,
+                           dim3(resident_grid((const void *)onesweep_emit_kernel, kSortBlock, L.tile_nb)),
+                           dim3(kSortBlock), 0, st, rank_ids, offsets, (const int32_t *)chunk_rank,
+                           (const int32_t *)rank_tiles,
+                           (const int4 *)s->rect, cams, (int)n_cams, n_splats, (const int64_t *)dcount, K, cap,
+                           ghist_tile, stat_tile, k0out, v0out, k64, s->depth, err);
     } else {
         // the emitted entries go to the pair the first pass does not write
         const bool emit_to_X = passes >= 2 && first_to_W;
         uint32_t *ek = emit_to_X ? kX : kW;
         int32_t *ev = emit_to_X ? vX : vW;
         hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
-                           s->tiles_touched, (const int4 *)s->rect, cams, (int)n_cams, n_splats,
+                           (const int32_t *)rank_tiles, (const int4 *)s->rect, cams, (int)n_cams, n_splats,
                            (const int64_t *)dcount, K, cap, ek, ev, (const int64_t *)err);
-        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, ek, ev, K, cap, 0,
-                           ghist_tile, stat_tile, tk_tile, k0out, v0out, k64, s->depth, n_splats, 1, err);
+        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, ek, ev, K, cap, 0, ghist_tile,
+                           stat_tile, k0out, v0out, k64, s->depth, (const int32_t *)nullptr, (int32_t *)nullptr,
+                           n_splats, 1, err);
     }
     uint32_t *kin = first_to_W ? kW : kX;
     int32_t *vin = first_to_W ? vW : vX;
@@ -1254,19 +1359,22 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
         const bool last = pass == passes - 1;
         uint32_t *kout = kin == kW ? kX : kW;
         int32_t *vout = vin == vW ? vX : vW;
-        hipLaunchKernelGGL(onesweep_kernel, dim3((unsigned)L.tile_nb), dim3(kSortBlock), 0, st, kin, vin, K, cap,
+        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, kin, vin, K, cap,
                            pass * kRadixBits, ghist_tile + pass * kRadix,
-                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, tk_tile + pass,
-                           last ? (uint32_t *)nullptr : kout, last ? bins->ids : vout,
-                           last ? bins->keys : (uint64_t *)nullptr, s->depth, n_splats, 1, err);
+                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, last ? (uint32_t *)nullptr : kout,
+                           last ? bins->ids : vout,
+                           last ? bins->keys : (uint64_t *)nullptr, s->depth, (const int32_t *)nullptr,
+                           (int32_t *)nullptr, n_splats, 1, err);
         kin = kout;
         vin = vout;
     }
     rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
     // 5. ranges from the list lengths, when the list was built
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_for(bins->n_tiles, kSortChunk)), dim3(kSortBlock), 0, st,
-                       (const int32_t *)tile_cnt, bins->n_tiles, K, cap, stat_ranges, tk_ranges, bins->ranges, err);
+    hipLaunchKernelGGL(ranges_kernel,
+                       dim3(resident_grid((const void *)ranges_kernel, kSortBlock, grid_for(bins->n_tiles, kSortChunk))),
+                       dim3(kSortBlock), 0, st, (const int32_t *)tile_cnt, bins->n_tiles, K, cap, stat_ranges,
+                       bins->ranges, err);
 
     // 6. the work list; the sort's error word joins the overflow flag
     hipLaunchKernelGGL(err_fold_kernel, dim3(1), dim3(64), 0, st, bins->counters, (const int64_t *)err);

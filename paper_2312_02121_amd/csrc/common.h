@@ -48,6 +48,7 @@ constexpr int kSchedNumBuckets = 16;
 
 // Workgroups for a persistent launch: enough waves to fill every SIMD of the device.
 unsigned persistent_blocks(int waves_per_block);
+int device_cu_count();   // compute units of the current device
 const gs_tuning &current_tuning();
 
 // ------------------------------------------------------------------ host-side status

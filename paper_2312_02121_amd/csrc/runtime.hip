@@ -38,7 +38,7 @@ static gs_tuning g_tuning = {256, 4, 32, 1, 0, {0, 0, 0}};
 
 const gs_tuning &current_tuning() { return g_tuning; }
 
-unsigned persistent_blocks(int waves_per_block)
+int device_cu_count()
 {
     static int cached_dev = -1, cached_cus = 0;
     int dev = 0;
@@ -50,7 +50,12 @@ unsigned persistent_blocks(int waves_per_block)
         cached_cus = cus;
         cached_dev = dev;
     }
-    return (unsigned)((cached_cus * g_tuning.waves_per_cu + waves_per_block - 1) / waves_per_block);
+    return cached_cus;
+}
+
+unsigned persistent_blocks(int waves_per_block)
+{
+    return (unsigned)((device_cu_count() * g_tuning.waves_per_cu + waves_per_block - 1) / waves_per_block);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(uint4 *__restrict__ p16, int64_t n16, unsigned char *__restrict__ tail,
