@@ -157,7 +157,17 @@ typedef struct gs_tuning {
     int32_t generate_entries;/* nonzero: the first tile-sort pass generates the list entries from
                                 the boxes itself instead of reading them from an emitted list
                                 (less traffic when splats cover many tiles) */
-    int32_t reserved[3];
+    int32_t item_grab;       /* work items a wave takes from the work list per atomic on its
+                                counter, 1..16 (fewer atomics on one address when items are
+                                many and short; more imbalance at the end of the list) */
+    int32_t prio_len;        /* a wave also raises its issue priority on an unsplit tile whose
+                                list has at least this many entries; 0: never. Long walks are
+                                the end of the launch: priority keeps them at full speed while
+                                the SIMD is shared */
+    int32_t bwd_segs;        /* 1, 2 or 4: the fused kernel walks the backward of a split tile's
+                                part as this many list segments, one work item each (every
+                                such item repeats the part's forward), so that the longest
+                                walks, the end of the launch, are shorter */
 } gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */

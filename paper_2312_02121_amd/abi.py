@@ -63,10 +63,11 @@ class GsParams(ctypes.Structure):
 class GsTuning(ctypes.Structure):
     _fields_ = [("split_len", ctypes.c_int32), ("split_parts", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("split_priority", ctypes.c_int32), ("generate_entries", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("item_grab", ctypes.c_int32), ("prio_len", ctypes.c_int32),
+                ("bwd_segs", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class GsBins(ctypes.Structure):

@@ -1,10 +1,13 @@
 """Autotuner of the rasterizer's launch tuning (gs_tuning) for one batch of cameras.
 
-The work list, the sort and the persistent launch have five knobs (see gs_tuning in the
+The work list, the sort and the persistent launch have eight knobs (see gs_tuning in the
 C header): the list length at which a tile is split, the number of parts (16x8 halves or
 16x4 quarters), the persistent grid size in waves per compute unit, whether a wave raises
-its priority on split items, and whether the first tile-sort pass generates the list
-entries itself. None of them changes a result, only the time.
+its priority on split items, whether the first tile-sort pass generates the list entries
+itself, how many work items a wave takes per atomic on the work counter, and the list
+length from which a wave raises its priority on an unsplit tile, and the number of list
+segments a split tile's backward is walked in by the fused kernel. None of them changes a
+result beyond the rounding order of gradient sums, only the time.
 
 ``tune`` times a full training step (project, bin and sort, fused forward + loss +
 backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
@@ -33,15 +36,21 @@ KNOBS = {
     "waves_per_cu": (16, 32),
     "split_priority": (0, 1),
     "generate_entries": (0, 1),
+    "item_grab": (1, 2, 4, 8),
+    "prio_len": (0, 256, 512, 1024),
+    "bwd_segs": (1, 2, 4),
 }
 
 
 def default_tuning() -> dict:
-    return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0}
+    return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0,
+            "item_grab": 1, "prio_len": 0, "bwd_segs": 1}
 
 
 def apply(t: dict):
-    abi.gs_set_tuning(abi.GsTuning(**{k: int(v) for k, v in t.items()}))
+    """Sets the tuning; knobs missing from t (e.g. a tuning recorded before a knob existed)
+    take their default."""
+    abi.gs_set_tuning(abi.GsTuning(**{k: int(v) for k, v in {**default_tuning(), **t}.items()}))
 
 
 def current() -> dict:

@@ -1048,7 +1048,7 @@ __global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ s
 
 // Per-block bucket histogram in LDS, then one global atomic per non-empty bucket.
 __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restrict__ ranges, int n_tiles,
-                                                          int split_len, int split_parts, int32_t *__restrict__ sched)
+                                                          int split_len, int split_items, int32_t *__restrict__ sched)
 {
     __shared__ int cnt[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
@@ -1056,7 +1056,7 @@ __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restr
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_tiles) {
         const int len = ranges[2 * t + 1] - ranges[2 * t];
-        atomicAdd(&cnt[length_bucket(len)], len >= split_len ? split_parts : 1);
+        atomicAdd(&cnt[length_bucket(len)], len >= split_len ? split_items : 1);
     }
     __syncthreads();
     if (threadIdx.x < kSchedNumBuckets && cnt[threadIdx.x])
@@ -1066,7 +1066,8 @@ __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restr
 // Each block reserves one contiguous run per bucket (one global atomic per bucket), then
 // hands out positions inside its runs with LDS atomics. Order inside a bucket is free.
 __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restrict__ ranges, int n_tiles,
-                                                         int split_len, int split_parts, int32_t *__restrict__ sched)
+                                                         int split_len, int split_parts, int bwd_segs,
+                                                         int32_t *__restrict__ sched)
 {
     __shared__ int cnt[kSchedNumBuckets], base[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
@@ -1076,7 +1077,7 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
     if (t < n_tiles) {
         len = ranges[2 * t + 1] - ranges[2 * t];
         b = length_bucket(len);
-        n = len >= split_len ? split_parts : 1;
+        n = len >= split_len ? split_parts * bwd_segs : 1;
         atomicAdd(&cnt[b], n);
     }
     __syncthreads();
@@ -1091,14 +1092,21 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
             for (int j = 0; j < kSchedNumBuckets; ++j) tot += sched[kSchedBuckets + j];
             sched[kSchedItems] = tot;
             sched[kSchedParts] = split_parts;
+            sched[kSchedSegs] = bwd_segs;
         }
     }
     __syncthreads();
     if (t >= n_tiles) return;
-    const int split = len >= split_len;
     const int pos = base[b] + atomicAdd(&cnt[b], n);
     int32_t *items = sched + kSchedHeader;
-    for (int part = 0; part < n; ++part) items[pos + part] = (t << 3) | (split << 2) | part;
+    if (n == 1) {
+        items[pos] = t << kItemTileShift;
+    } else {
+        // segment-major, so that the parts of one segment start together
+        for (int seg = 0; seg < bwd_segs; ++seg)
+            for (int part = 0; part < split_parts; ++part)
+                items[pos + seg * split_parts + part] = (t << kItemTileShift) | (seg << 3) | 4 | part;
+    }
 }
 
 // ------------------------------------------------------------------------ workspace
@@ -1209,15 +1217,15 @@ static int build_schedule(gs_bins *bins, hipStream_t st)
     hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule);
     const gs_tuning &tu = current_tuning();
     hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
-                       tu.split_parts, bins->schedule);
+                       tu.split_parts * tu.bwd_segs, bins->schedule);
     hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
-                       tu.split_parts, bins->schedule);
+                       tu.split_parts, tu.bwd_segs, bins->schedule);
     return check_launch("gs_bin_and_sort");
 }
 
 extern "C" int64_t gs_schedule_size(int32_t n_tiles)
 {
-    return n_tiles < 0 ? 0 : (int64_t)kSchedHeader + 4ll * n_tiles;
+    return n_tiles < 0 ? 0 : (int64_t)kSchedHeader + (int64_t)kMaxItemsPerTile * n_tiles;
 }
 
 extern "C" size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles)

@@ -34,13 +34,19 @@ static_assert(sizeof(RasterRec) == 64, "RasterRec must be 64 bytes");
 constexpr double kLog2eD = 1.4426950408889634074;
 
 // Rasterizer work list (gs_bins.schedule, int32). Header words, then the items.
-// An item is tile << 3 | quarter << 2 | part: quarter = 0 covers the whole tile,
-// quarter = 1 covers rows 4 part .. 4 part + 3 of it.
+// An item is tile << 5 | seg << 3 | split << 2 | part: split = 0 covers the whole tile,
+// split = 1 one part of it (rows 16 / parts * part onward). A split tile has parts x segs
+// items: seg is the item's segment of the tile's list in the fused kernel's backward (each
+// such item runs the forward and walks back over its own segment); the forward and backward
+// kernels take the seg 0 items only, over the whole list.
 constexpr int kSchedItems = 0;      // number of items
 constexpr int kSchedFwd = 1;        // forward kernel: next item, then finished-wave count
 constexpr int kSchedBwd = 3;        // backward kernel: next item, then finished-wave count
 constexpr int kSchedFused = 5;      // fused kernel: next item, then finished-wave count
 constexpr int kSchedParts = 7;      // parts per split tile (2 or 4) the list was built with
+constexpr int kSchedSegs = 40;      // backward list segments per split tile (1, 2 or 4)
+constexpr int kItemTileShift = 5;
+constexpr int kMaxItemsPerTile = 16;   // parts x segs
 constexpr int kSchedBuckets = 8;    // 16 bucket counts
 constexpr int kSchedCursors = 24;   // 16 bucket cursors
 constexpr int kSchedHeader = 64;
@@ -131,6 +137,31 @@ __device__ inline float row_sum(float v)
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+    return v;
+}
+
+// Wave totals after row_sum (every lane holds its row's total): rows 0 and 2 are added into
+// rows 1 and 3 (row_bcast:15), then rows 0-1 into rows 2-3 (row_bcast:31); lane 63 ends
+// with the total of all 64 lanes. Lanes outside the broadcast's target rows add zero.
+template <int kCtrl, int kRowMask>
+__device__ inline double bcast_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRowMask, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRowMask, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double rows_to_lane63(double v)
+{
+    v += bcast_f64<0x142, 0xA>(v);   // row_bcast:15
+    v += bcast_f64<0x143, 0xC>(v);   // row_bcast:31
+    return v;
+}
+
+__device__ inline float rows_to_lane63(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
     return v;
 }
 

@@ -101,7 +101,7 @@ __device__ inline ItemPixels item_pixels(const gs_camera *__restrict__ cams, int
 {
     constexpr int kLanesPerRow = kTile / PX;
     ItemPixels t;
-    const int tile = item >> 3, part = PX == 4 ? 0 : (item & 3);
+    const int tile = item >> kItemTileShift, part = PX == 4 ? 0 : (item & 3);
     const int c = camera_of_tile(cams, n_cams, tile);
     const int local = tile - cams[c].tile_offset;
     const int tx_n = cams[c].tiles_x;
@@ -123,13 +123,24 @@ __device__ __forceinline__ float alpha_raw(const RasterRec &r, double dx, double
     return __builtin_amdgcn_exp2f((float)e);
 }
 
-// Next item for this wave, or -1. The counter hands out positions in the work list; the
-// last wave to find the list exhausted resets the counters.
-__device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_items, int lane)
+// Work-list cursor of a wave: positions [pos, end) taken from the counter and not yet used.
+struct ItemCursor {
+    int pos, end;
+};
+
+// Next item for this wave, or -1. The counter hands out positions in the work list, `grab`
+// consecutive ones per atomic (one address serves every wave, so fewer atomics help when
+// items are many and short); the last wave to find the list exhausted resets the counters.
+__device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_items, int grab, ItemCursor &cur,
+                                int lane)
 {
-    int pos = 0;
-    if (lane == 0) pos = atomicAdd(&sched[counter], 1);
-    pos = __builtin_amdgcn_readfirstlane(pos);
+    if (cur.pos >= cur.end) {
+        int p = 0;
+        if (lane == 0) p = atomicAdd(&sched[counter], grab);
+        cur.pos = __builtin_amdgcn_readfirstlane(p);
+        cur.end = cur.pos + grab;
+    }
+    const int pos = cur.pos++;
     if (pos < n_items) return __builtin_amdgcn_readfirstlane(sched[kSchedHeader + pos]);
     if (lane == 0) {
         const int waves = (int)gridDim.x * kBlockWaves;
@@ -139,6 +150,14 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
         }
     }
     return -1;
+}
+
+// An unsplit tile whose list has at least prio_len entries (prio_len > 0): its walk is among
+// the last to finish, so its wave takes issue priority.
+__device__ inline bool long_walk(const int32_t *__restrict__ ranges, int item, int prio_len)
+{
+    const int tile = item >> kItemTileShift;
+    return prio_len > 0 && ranges[2 * tile + 1] - ranges[2 * tile] >= prio_len;
 }
 
 // ----------------------------------------------------------------------------- forward
@@ -173,11 +192,33 @@ __device__ inline void init_state(const ItemPixels &t, PixState<PX> &ps)
     }
 }
 
-// Front-to-back walk of the item's list (eq. 7). On return T holds |T_final|.
+// State of the forward at one list position: T (>= 0) and the colour so far.
+template <int PX>
+struct Snapshot {
+    float T[PX], c0[PX], c1[PX], c2[PX];
+};
+
+template <int PX>
+__device__ inline void take_snapshot(const PixState<PX> &ps, Snapshot<PX> &sn)
+{
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        sn.T[q] = fabsf(ps.T[q]);
+        sn.c0[q] = ps.c0[q];
+        sn.c1[q] = ps.c1[q];
+        sn.c2[q] = ps.c2[q];
+    }
+}
+
+// Front-to-back walk of the item's list (eq. 7). On return T holds |T_final|. With
+// snap_pos set (a list position t.start + 64 m), sn receives the state before entry
+// snap_pos (the final state if the walk ends earlier).
 template <int PX, bool kVisited>
 __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
-                                const gs_params &prm, PixState<PX> &ps)
+                                const gs_params &prm, PixState<PX> &ps, int snap_pos = -1,
+                                Snapshot<PX> *sn = nullptr)
 {
+    bool snapped = snap_pos < 0;
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
     // batch k covers entries [t.start + 64 k, ...): its slots are loaded two batches ahead,
@@ -185,6 +226,10 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     Gathered next = gather(rr, load_ids(ids, t.start, t.end - t.start, lane));
     int nid = load_ids(ids, t.start + kBatch, t.end - t.start - kBatch, lane);
     for (int b = t.start; b < t.end; b += kBatch) {
+        if (!snapped && b == snap_pos) {
+            take_snapshot<PX>(ps, *sn);
+            snapped = true;
+        }
         const int nb = min(kBatch, t.end - b);
         stage(slice, next, lane);
         if (b + kBatch < t.end) next = gather(rr, nid);
@@ -232,6 +277,7 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             }
         }
     }
+    if (!snapped) take_snapshot<PX>(ps, *sn);
 #pragma unroll
     for (int q = 0; q < PX; ++q) ps.T[q] = fabsf(ps.T[q]);
 }
@@ -256,8 +302,8 @@ struct BwdOut {
 // ways, chosen by the number of lanes with a composited pixel (wave-uniform):
 //   few lanes (small splats, the common case at 1M Gaussians): those lanes add their
 //     terms into the slot with LDS atomics, which conflict only among themselves;
-//   many lanes (large splats): a DPP reduction within each row of 16 lanes, and one lane
-//     per row adds the row's totals into the slot.
+//   many lanes (large splats): a DPP reduction over the wave, and lane 63 writes the
+//     totals into the slot (the splat's only writer).
 // When the batch is done, lane j moves slot j to global memory with one atomic per term,
 // so the global atomics of a batch are 9 instructions with up to 64 distinct addresses.
 struct WaveAcc {
@@ -320,45 +366,45 @@ __device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nb, i
     __builtin_amdgcn_wave_barrier();
 }
 
-// Back-to-front walk (Sec. 3.1). On entry T holds T_final, last the start positions and
-// g0..g2 the upstream gradient dL/dC of each pixel.
+// Back-to-front walk (Sec. 3.1) over the list positions [lo, hi) (the whole list: lo =
+// t.start, hi = t.end). On entry T holds each pixel's transmittance after entry hi - 1
+// (T_final for the whole list), gS the sum of dL/dC(k) S(k) over the entries from hi on
+// (zero for the whole list), last the start positions and g0..g2 the upstream gradient
+// dL/dC of each pixel.
 template <int PX>
 __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
-                                const gs_params &prm, const PixState<PX> &ps, float (&T)[PX],
+                                const gs_params &prm, const PixState<PX> &ps, float (&T)[PX], float (&gS)[PX],
                                 const float (&g0)[PX], const float (&g1)[PX], const float (&g2)[PX],
-                                const BwdOut &out)
+                                const BwdOut &out, int lo, int hi)
 {
     const int lane = threadIdx.x & (kWave - 1);
     int maxlast = 0;
 #pragma unroll
     for (int q = 0; q < PX; ++q) maxlast = max(maxlast, ps.last[q]);
     maxlast = __builtin_amdgcn_readfirstlane(wave_max(maxlast));
-    if (maxlast == 0) return;
-    float gS[PX];
-#pragma unroll
-    for (int q = 0; q < PX; ++q) gS[q] = 0.f;
+    const int kend = min(hi, t.start + maxlast);
+    if (kend <= lo) return;
     RasterRec *slice = wave_slice();
     WaveAcc *acc = wave_acc();
     acc_clear(acc, lane);
-    const int kend = t.start + maxlast;
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
-    // batch k covers entries [max(t.start, e_k - 64), e_k) with e_k = kend - 64 k: its slots
+    // batch k covers entries [max(lo, e_k - 64), e_k) with e_k = kend - 64 k: its slots
     // are loaded two batches ahead, its records one batch ahead
-    const int s0 = max(t.start, kend - kBatch);
+    const int s0 = max(lo, kend - kBatch);
     Gathered next = gather(rr, load_ids(ids, s0, kend - s0, lane));
     int nid = -1;
-    if (s0 > t.start) {
-        const int s1 = max(t.start, s0 - kBatch);
+    if (s0 > lo) {
+        const int s1 = max(lo, s0 - kBatch);
         nid = load_ids(ids, s1, s0 - s1, lane);
     }
-    for (int bend = kend; bend > t.start; bend -= kBatch) {
-        const int bstart = max(t.start, bend - kBatch);
+    for (int bend = kend; bend > lo; bend -= kBatch) {
+        const int bstart = max(lo, bend - kBatch);
         const int nb = bend - bstart;
         stage(slice, next, lane);
-        if (bstart > t.start) next = gather(rr, nid);
+        if (bstart > lo) next = gather(rr, nid);
         const int e2 = bstart - kBatch;   // end of the batch after next
-        if (e2 > t.start) {
-            const int s2 = max(t.start, e2 - kBatch);
+        if (e2 > lo) {
+            const int s2 = max(lo, e2 - kBatch);
             nid = load_ids(ids, s2, e2 - s2, lane);
         }
         RasterRec rn = slice[nb - 1];
@@ -421,26 +467,27 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                     lds_add(&acc->f[2][j], s_c2);
                 }
             } else {
-                // reduce within rows of 16 lanes; one lane per row adds its row's totals
-                s_v = row_sum(s_v);
-                s_x = row_sum(s_x);
-                s_y = row_sum(s_y);
-                s_xx = row_sum(s_xx);
-                s_xy = row_sum(s_xy);
-                s_yy = row_sum(s_yy);
-                s_c0 = row_sum(s_c0);
-                s_c1 = row_sum(s_c1);
-                s_c2 = row_sum(s_c2);
-                if ((lane & 15) == 15) {
-                    lds_add(&acc->d[0][j], s_v);
-                    lds_add(&acc->d[1][j], s_x);
-                    lds_add(&acc->d[2][j], s_y);
-                    lds_add(&acc->d[3][j], s_xx);
-                    lds_add(&acc->d[4][j], s_xy);
-                    lds_add(&acc->d[5][j], s_yy);
-                    lds_add(&acc->f[0][j], s_c0);
-                    lds_add(&acc->f[1][j], s_c1);
-                    lds_add(&acc->f[2][j], s_c2);
+                // reduce over the wave (within rows of 16 lanes, then across rows); lane 63
+                // writes the totals: the slot has no other writer for this splat
+                s_v = rows_to_lane63(row_sum(s_v));
+                s_x = rows_to_lane63(row_sum(s_x));
+                s_y = rows_to_lane63(row_sum(s_y));
+                s_xx = rows_to_lane63(row_sum(s_xx));
+                s_xy = rows_to_lane63(row_sum(s_xy));
+                s_yy = rows_to_lane63(row_sum(s_yy));
+                s_c0 = rows_to_lane63(row_sum(s_c0));
+                s_c1 = rows_to_lane63(row_sum(s_c1));
+                s_c2 = rows_to_lane63(row_sum(s_c2));
+                if (lane == kWave - 1) {
+                    acc->d[0][j] = s_v;
+                    acc->d[1][j] = s_x;
+                    acc->d[2][j] = s_y;
+                    acc->d[3][j] = s_xx;
+                    acc->d[4][j] = s_xy;
+                    acc->d[5][j] = s_yy;
+                    acc->f[0][j] = s_c0;
+                    acc->f[1][j] = s_c1;
+                    acc->f[2][j] = s_c2;
                 }
             }
         }
@@ -480,14 +527,16 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
 template <bool kVisited>
 __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio)
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio, int grab, int prio_len)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
+    ItemCursor cur{0, 0};
     for (;;) {
-        const int item = next_item(sched, kSchedFwd, n_items, lane);
+        const int item = next_item(sched, kSchedFwd, n_items, grab, cur, lane);
         if (item < 0) break;
+        if ((item >> 3) & 3) continue;   // a backward segment of the fused kernel
         if (item & 4) {
             if (prio) __builtin_amdgcn_s_setprio(2);
             if (parts == 4)
@@ -496,7 +545,9 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
                 fwd_item<2, kVisited>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o);
             __builtin_amdgcn_s_setprio(0);
         } else {
+            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
             fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o);
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
@@ -527,20 +578,25 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
             g2[q] = in.dL_dimage[2 * in.n_pixels + pix];
         }
     }
-    bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
+    float gS[PX];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) gS[q] = 0.f;
+    bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, t.start, t.end);
 }
 
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_bwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out,
-    int prio)
+    int prio, int grab, int prio_len)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
+    ItemCursor cur{0, 0};
     for (;;) {
-        const int item = next_item(sched, kSchedBwd, n_items, lane);
+        const int item = next_item(sched, kSchedBwd, n_items, grab, cur, lane);
         if (item < 0) break;
+        if ((item >> 3) & 3) continue;   // a backward segment of the fused kernel
         if (item & 4) {
             if (prio) __builtin_amdgcn_s_setprio(2);
             if (parts == 4)
@@ -549,7 +605,9 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
                 bwd_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
+            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
             bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
@@ -564,11 +622,21 @@ struct FusedIO {
 
 template <int PX>
 __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
-                                  const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out)
+                                  const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out,
+                                  int seg, int segs)
 {
+    // segment seg of segs: list positions [lo, hi), boundaries at multiples of 64 entries
+    const int n = t.end - t.start;
+    const int per = ((n + segs - 1) / segs + kBatch - 1) / kBatch * kBatch;
+    const int lo = min(t.end, t.start + seg * per);
+    const int hi = seg == segs - 1 ? t.end : min(t.end, lo + per);
     PixState<PX> ps;
     init_state<PX>(t, ps);
-    fwd_walk<PX, false>(rr, ids, t, prm, ps);
+    Snapshot<PX> sn;
+    if (hi < t.end)
+        fwd_walk<PX, false>(rr, ids, t, prm, ps, hi, &sn);
+    else
+        fwd_walk<PX, false>(rr, ids, t, prm, ps);
     float g0[PX], g1[PX], g2[PX];
     float l2 = 0.f;
 #pragma unroll
@@ -583,43 +651,59 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
             g1[q] = 2.f * d1;
             g2[q] = 2.f * d2;
             l2 += d0 * d0 + d1 * d1 + d2 * d2;
-            if (io.image) {
+            if (io.image && seg == 0) {
                 io.image[pix] = ps.c0[q];
                 io.image[io.n_pixels + pix] = ps.c1[q];
                 io.image[2 * io.n_pixels + pix] = ps.c2[q];
             }
         }
     }
-    if (io.loss) {
+    if (io.loss && seg == 0) {
         l2 = wave_sum_to_lane63(l2);
         if ((threadIdx.x & (kWave - 1)) == kWave - 1) atomic_add_f32(io.loss, l2);
     }
-    float T[PX];
+    // the walk back over [lo, hi) starts from the state after entry hi - 1: for the last
+    // segment T_final and nothing behind; otherwise the snapshot, with the colour added
+    // from hi on carried by gS = dL/dC . (C_final - C(hi))
+    float T[PX], gS[PX];
 #pragma unroll
-    for (int q = 0; q < PX; ++q) T[q] = ps.T[q];
-    bwd_walk<PX>(rr, ids, t, prm, ps, T, g0, g1, g2, out);
+    for (int q = 0; q < PX; ++q) {
+        if (hi < t.end) {
+            T[q] = sn.T[q];
+            gS[q] = g0[q] * (ps.c0[q] - sn.c0[q]) + g1[q] * (ps.c1[q] - sn.c1[q]) + g2[q] * (ps.c2[q] - sn.c2[q]);
+        } else {
+            T[q] = ps.T[q];
+            gS[q] = 0.f;
+        }
+    }
+    bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, lo, hi);
 }
 
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_fused_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FusedIO io,
-    BwdOut out, int prio)
+    BwdOut out, int prio, int grab, int prio_len)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
+    const int segs = __builtin_amdgcn_readfirstlane(sched[kSchedSegs]);
+    ItemCursor cur{0, 0};
     for (;;) {
-        const int item = next_item(sched, kSchedFused, n_items, lane);
+        const int item = next_item(sched, kSchedFused, n_items, grab, cur, lane);
         if (item < 0) break;
         if (item & 4) {
+            const int seg = (item >> 3) & 3;
             if (prio) __builtin_amdgcn_s_setprio(2);
             if (parts == 4)
-                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out);
+                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs);
             else
-                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out);
+                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out);
+            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1);
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
@@ -652,10 +736,12 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     const FwdOut o{n_pixels, image, T_final, last, visited};
     if (visited)
         hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
+                           current_tuning().item_grab, current_tuning().prio_len);
     else
         hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority);
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
+                           current_tuning().item_grab, current_tuning().prio_len);
     return check_launch("gs_rasterize_fwd");
 }
 
@@ -686,7 +772,8 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, in, out, current_tuning().split_priority);
+                       (int)n_cams, *prm, in, out, current_tuning().split_priority,
+                           current_tuning().item_grab, current_tuning().prio_len);
     return check_launch("gs_rasterize_bwd");
 }
 
@@ -707,6 +794,7 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
     hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, io, out, current_tuning().split_priority);
+                       (int)n_cams, *prm, io, out, current_tuning().split_priority,
+                           current_tuning().item_grab, current_tuning().prio_len);
     return check_launch("gs_rasterize_fused_l2");
 }

@@ -143,9 +143,12 @@ def test_results_do_not_depend_on_launch_tuning(name):
     ref_img = ref = None
     try:
         for t in ({"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0},
-                  {"split_len": 1 << 30, "split_parts": 4, "waves_per_cu": 16, "split_priority": 0, "generate_entries": 1},
-                  {"split_len": 64, "split_parts": 2, "waves_per_cu": 16, "split_priority": 1, "generate_entries": 0},
-                  {"split_len": 1, "split_parts": 4, "waves_per_cu": 64, "split_priority": 0, "generate_entries": 1}):
+                  {"split_len": 1 << 30, "split_parts": 4, "waves_per_cu": 16, "split_priority": 0, "generate_entries": 1,
+                   "item_grab": 4},
+                  {"split_len": 64, "split_parts": 2, "waves_per_cu": 16, "split_priority": 1, "generate_entries": 0,
+                   "item_grab": 16, "prio_len": 64, "bwd_segs": 4},
+                  {"split_len": 1, "split_parts": 4, "waves_per_cu": 64, "split_priority": 0, "generate_entries": 1,
+                   "item_grab": 2, "bwd_segs": 2}):
             autotune.apply(t)
             _, _, _, step = build(wl, "fused")
             step()
