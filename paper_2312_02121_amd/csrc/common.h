@@ -121,6 +121,32 @@ __device__ inline double dpp_all_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Partial row sums: levels [kFrom, kTo) of the butterfly below (level 0: pairs, 1: quads,
+// 2: half-rows of 8, 3: rows of 16 lanes).
+template <int kFrom, int kTo>
+__device__ inline double row_levels(double v)
+{
+    if constexpr (kFrom <= 0 && kTo > 0) v += dpp_all_f64<0xB1>(v);
+    if constexpr (kFrom <= 1 && kTo > 1) v += dpp_all_f64<0x4E>(v);
+    if constexpr (kFrom <= 2 && kTo > 2) v += dpp_all_f64<0x141>(v);
+    if constexpr (kFrom <= 3 && kTo > 3) v += dpp_all_f64<0x140>(v);
+    return v;
+}
+
+template <int kFrom, int kTo>
+__device__ inline float row_levels(float v)
+{
+    if constexpr (kFrom <= 0 && kTo > 0)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    if constexpr (kFrom <= 1 && kTo > 1)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    if constexpr (kFrom <= 2 && kTo > 2)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    if constexpr (kFrom <= 3 && kTo > 3)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+    return v;
+}
+
 __device__ inline double row_sum(double v)
 {
     v += dpp_all_f64<0xB1>(v);    // quad_perm [1,0,3,2]

@@ -452,9 +452,9 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             }
             const uint64_t live = __ballot(live_sum > 0.f);
             if (live == 0) continue;
-            double s_y = s_v * dy, s_xy = s_x * dy;
-            double s_yy = s_y * dy;
             if (__popcll(live) <= kLdsAtomicLanes) {
+                const double s_y = s_v * dy, s_xy = s_x * dy;
+                const double s_yy = s_y * dy;
                 if (live_sum > 0.f) {
                     lds_add(&acc->d[0][j], s_v);
                     lds_add(&acc->d[1][j], s_x);
@@ -467,14 +467,22 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                     lds_add(&acc->f[2][j], s_c2);
                 }
             } else {
-                // reduce over the wave (within rows of 16 lanes, then across rows); lane 63
-                // writes the totals: the slot has no other writer for this splat
-                s_v = rows_to_lane63(row_sum(s_v));
-                s_x = rows_to_lane63(row_sum(s_x));
-                s_y = rows_to_lane63(row_sum(s_y));
-                s_xx = rows_to_lane63(row_sum(s_xx));
-                s_xy = rows_to_lane63(row_sum(s_xy));
-                s_yy = rows_to_lane63(row_sum(s_yy));
+                // reduce over the wave: first over the lanes of one pixel row (they share
+                // dy, so the dy-weighted sums follow from the row's sums), then within rows
+                // of 16 lanes and across rows; lane 63 writes the totals: the slot has no
+                // other writer for this splat
+                constexpr int kRowLevels = PX == 4 ? 2 : PX == 2 ? 3 : 4;   // log2 lanes per pixel row
+                s_v = row_levels<0, kRowLevels>(s_v);
+                s_x = row_levels<0, kRowLevels>(s_x);
+                s_xx = row_levels<0, kRowLevels>(s_xx);
+                double s_y = s_v * dy, s_xy = s_x * dy;
+                double s_yy = s_y * dy;
+                s_v = rows_to_lane63(row_levels<kRowLevels, 4>(s_v));
+                s_x = rows_to_lane63(row_levels<kRowLevels, 4>(s_x));
+                s_y = rows_to_lane63(row_levels<kRowLevels, 4>(s_y));
+                s_xx = rows_to_lane63(row_levels<kRowLevels, 4>(s_xx));
+                s_xy = rows_to_lane63(row_levels<kRowLevels, 4>(s_xy));
+                s_yy = rows_to_lane63(row_levels<kRowLevels, 4>(s_yy));
                 s_c0 = rows_to_lane63(row_sum(s_c0));
                 s_c1 = rows_to_lane63(row_sum(s_c1));
                 s_c2 = rows_to_lane63(row_sum(s_c2));
