@@ -12,7 +12,8 @@ result beyond the rounding order of gradient sums, only the time.
 ``tune`` times a full training step (project, bin and sort, fused forward + loss +
 backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
 The search is a coordinate descent from the library default: one knob at a time over its
-values, keeping the best value before moving to the next knob, two rounds. Results are
+values (KNOBS; item_grab stays at 1), keeping the best value before moving to the next
+knob, up to three rounds; each candidate is timed as the best of three runs. Results are
 cached in a JSON file keyed by a signature of the workload (cameras, resolutions, Gaussian
 count, and the list length rounded to a power of two), so a later process with the same
 kind of batch applies the recorded tuning without searching; ``python -m
@@ -36,10 +37,12 @@ KNOBS = {
     "waves_per_cu": (16, 32),
     "split_priority": (0, 1),
     "generate_entries": (0, 1),
-    "item_grab": (1, 2, 4, 8),
     "prio_len": (0, 256, 512, 1024),
     "bwd_segs": (1, 2, 4),
 }
+# item_grab is left at 1: taking several items per atomic put consecutive long items (the
+# head of the longest-first list) on one wave and made the 1M-Gaussian and the 32-view
+# steps 2-6x slower, with no gain at 16 views (measured on MI355X).
 
 
 def default_tuning() -> dict:
@@ -69,22 +72,27 @@ def signature(step) -> str:
     return signature_of(step.g, step.cams, step.K)
 
 
-def _time_graph(step, steps: int, warmup: int) -> float:
+def _time_graph(step, steps: int, warmup: int, repeats: int = 3) -> float:
+    """Mean ms per replay of the step captured as a graph: the best of `repeats` runs of
+    `steps` replays (run-to-run noise on a shared GPU is one-sided)."""
     from .pipeline import GraphStep
     graph = GraphStep(step)
     for _ in range(warmup):
         graph()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(steps):
-        graph()
-    b.record()
-    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            graph()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) / steps)
     if step.overflowed():
         raise RuntimeError("list capacity overflow while tuning")
     del graph
-    return a.elapsed_time(b) / steps
+    return best
 
 
 def time_eager(fn, steps: int, warmup: int) -> float:
@@ -101,7 +109,7 @@ def time_eager(fn, steps: int, warmup: int) -> float:
     return a.elapsed_time(b) / steps
 
 
-def search(measure: Callable[[], float], rounds: int = 2, log: Callable[[str], None] | None = None) -> dict:
+def search(measure: Callable[[], float], rounds: int = 3, log: Callable[[str], None] | None = None) -> dict:
     """Coordinate descent over KNOBS from the default; measure() times the workload under
     the tuning currently applied. Applies and returns the best."""
     t0 = time.perf_counter()
@@ -151,7 +159,7 @@ def _store(cache_path: str, cache: dict):
         json.dump(cache, fh, indent=1, sort_keys=True)
 
 
-def tune(step, steps: int = 5, warmup: int = 2, rounds: int = 2, cache_path: str | None = None,
+def tune(step, steps: int = 10, warmup: int = 2, rounds: int = 3, cache_path: str | None = None,
          update_cache: bool = False, log: Callable[[str], None] | None = None) -> dict:
     """Finds the fastest tuning for `step` (a pipeline.TrainStep, timed as a captured graph),
     applies it and returns {"tuning", "ms", "default_ms", "evaluated", "seconds", "cached"}.
