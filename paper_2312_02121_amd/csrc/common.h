@@ -13,8 +13,8 @@ constexpr int kTilePixels = kTile * kTile;
 constexpr int kWave = 64;                // CDNA wavefront width
 constexpr int kRecFloats = 12;           // floats per splat record
 
-// Compositing record of one splat (64 bytes, gs_splats.raster). The rasterizer reads it with
-// scalar loads, so every lane of a wave gets it in SGPRs without LDS or VALU traffic.
+// Compositing record of one splat (64 bytes, gs_splats.raster). The rasterizer gathers 64 of
+// them per wave (one per lane, four 16-byte loads) into LDS and reads each back broadcast.
 //   alpha_raw(dx, dy) = exp2(lo + A dx^2 + B dx dy + C dy^2),  (dx, dy) = mu' - pixel centre
 // lo = log2(o); A = -log2(e)/2 Y00, B = -log2(e) Y01, C = -log2(e)/2 Y11 from the float32 conic.
 // The quadratic form is evaluated in float64: for thin splats Y is nearly singular and the three

@@ -6,11 +6,13 @@
 // adjacent pixels per lane. A tile with a long list (the length threshold and the split
 // are launch tuning, gs_tuning) is two 16x8-pixel halves at two pixels per lane or four
 // 16x4-pixel quarters at one pixel per lane, so that its walk, the critical path of the
-// launch, is split over several waves. The kernels are persistent: every wave takes items from an
-// atomic counter until the list is exhausted, and the last wave out resets the counter
-// so the next launch (or graph replay) starts from zero. A wave may raise its issue
-// priority (s_setprio) while it works on a split item, so that the longest walks keep
-// their SIMD.
+// launch, is split over several waves; in the fused kernel the backward of a split tile can
+// also be walked as list segments by separate items (each repeating the forward, which
+// snapshots T and the colour at the segment's end). The kernels are persistent: every wave
+// takes items from an atomic counter until the list is exhausted, and the last wave out
+// resets the counter so the next launch (or graph replay) starts from zero. A wave may raise
+// its issue priority (s_setprio) while it works on a split item or a long unsplit tile, so
+// that the longest walks keep their SIMD.
 //
 // Records. A wave walks its list in batches of 64 entries. For each batch every lane
 // gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
@@ -28,7 +30,8 @@
 // G_S = sum_k dL/dC(k) S(k) (eq. 18 summed over channels). Per lane it sums the nine
 // per-pair terms of its pixels,
 //   v = dL/dalpha * alpha, v dx, v dy, v dx^2, v dx dy, v dy^2, alpha T dL/dC(k) (k = 0..2)
-// then the wave adds them across lanes (DPP) and lane 63 issues one atomic per term:
+// which are summed per splat in an LDS slot (see WaveAcc) and moved to memory with one
+// atomic per term and splat at the end of each batch:
 //   dL/do = sum v / o, dL/dmu' = -Y sum v Delta, dL/dY = -1/2 sum v Delta Delta^T, dL/dc.
 #include "common.h"
 
