@@ -1041,9 +1041,21 @@ __device__ inline int length_bucket(int len)
     return kSchedNumBuckets - 1 - min(kSchedNumBuckets - 1, lg);
 }
 
+// Clears the header, except the walk-length stamp.
 __global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ sched)
 {
-    sched[threadIdx.x] = 0;
+    if (threadIdx.x != kSchedWalkStamp) sched[threadIdx.x] = 0;
+}
+
+// The length a tile is scheduled by: its list length, or the walk length of the last
+// rasterization when recorded for this tile count (and not longer than the list).
+__device__ inline int sched_len(const int32_t *__restrict__ ranges, const int32_t *__restrict__ sched, int n_tiles,
+                                int t)
+{
+    const int len = ranges[2 * t + 1] - ranges[2 * t];
+    if (len <= 0 || sched[kSchedWalkStamp] != n_tiles) return len;
+    const int walk = sched[sched_walk_offset(n_tiles) + t];
+    return walk >= 1 && walk < len ? walk : len;
 }
 
 // Per-block bucket histogram in LDS, then one global atomic per non-empty bucket.
@@ -1055,7 +1067,7 @@ __global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restr
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_tiles) {
-        const int len = ranges[2 * t + 1] - ranges[2 * t];
+        const int len = sched_len(ranges, sched, n_tiles, t);
         atomicAdd(&cnt[length_bucket(len)], len >= split_len ? split_items : 1);
     }
     __syncthreads();
@@ -1075,7 +1087,7 @@ __global__ __launch_bounds__(256) void sched_fill_kernel(const int32_t *__restri
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int len = 0, b = 0, n = 0;
     if (t < n_tiles) {
-        len = ranges[2 * t + 1] - ranges[2 * t];
+        len = sched_len(ranges, sched, n_tiles, t);
         b = length_bucket(len);
         n = len >= split_len ? split_parts * bwd_segs : 1;
         atomicAdd(&cnt[b], n);
@@ -1225,7 +1237,7 @@ static int build_schedule(gs_bins *bins, hipStream_t st)
 
 extern "C" int64_t gs_schedule_size(int32_t n_tiles)
 {
-    return n_tiles < 0 ? 0 : (int64_t)kSchedHeader + (int64_t)kMaxItemsPerTile * n_tiles;
+    return n_tiles < 0 ? 0 : sched_walk_offset(n_tiles) + n_tiles;
 }
 
 extern "C" size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_t n_tiles)

@@ -45,12 +45,22 @@ constexpr int kSchedBwd = 3;        // backward kernel: next item, then finished
 constexpr int kSchedFused = 5;      // fused kernel: next item, then finished-wave count
 constexpr int kSchedParts = 7;      // parts per split tile (2 or 4) the list was built with
 constexpr int kSchedSegs = 40;      // backward list segments per split tile (1, 2 or 4)
+constexpr int kSchedWalkStamp = 41; // n_tiles once the walk lengths below have been written
 constexpr int kItemTileShift = 5;
 constexpr int kMaxItemsPerTile = 16;   // parts x segs
 constexpr int kSchedBuckets = 8;    // 16 bucket counts
 constexpr int kSchedCursors = 24;   // 16 bucket cursors
 constexpr int kSchedHeader = 64;
 constexpr int kSchedNumBuckets = 16;
+// After the items: int32 [n_tiles], the forward walk length of each tile (entries its
+// forward evaluated) in the last rasterization with this work list. The next work list is
+// built from min(list length, walk length) when the stamp matches: it orders and splits
+// tiles by the work their walks did rather than by list length (tiles whose pixels saturate
+// early have long lists and short walks). Only the schedule depends on it.
+__host__ __device__ inline int64_t sched_walk_offset(int64_t n_tiles)
+{
+    return (int64_t)kSchedHeader + (int64_t)kMaxItemsPerTile * n_tiles;
+}
 
 // Workgroups for a persistent launch: enough waves to fill every SIMD of the device.
 unsigned persistent_blocks(int waves_per_block);

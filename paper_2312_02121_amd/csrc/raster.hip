@@ -135,7 +135,7 @@ struct ItemCursor {
 // consecutive ones per atomic (one address serves every wave, so fewer atomics help when
 // items are many and short); the last wave to find the list exhausted resets the counters.
 __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_items, int grab, ItemCursor &cur,
-                                int lane)
+                                int lane, int walk_stamp = 0)
 {
     if (cur.pos >= cur.end) {
         int p = 0;
@@ -150,6 +150,7 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
         if (atomicAdd(&sched[counter + 1], 1) == waves - 1) {
             sched[counter] = 0;
             sched[counter + 1] = 0;
+            if (walk_stamp) sched[kSchedWalkStamp] = walk_stamp;   // every item recorded its walk
         }
     }
     return -1;
@@ -215,13 +216,15 @@ __device__ inline void take_snapshot(const PixState<PX> &ps, Snapshot<PX> &sn)
 
 // Front-to-back walk of the item's list (eq. 7). On return T holds |T_final|. With
 // snap_pos set (a list position t.start + 64 m), sn receives the state before entry
-// snap_pos (the final state if the walk ends earlier).
+// snap_pos (the final state if the walk ends earlier). Returns the number of list entries
+// the walk went through (to the batch in which its last pixel finished).
 template <int PX, bool kVisited>
-__device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
+__device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
                                 const gs_params &prm, PixState<PX> &ps, int snap_pos = -1,
                                 Snapshot<PX> *sn = nullptr)
 {
     bool snapped = snap_pos < 0;
+    int walked = t.end - t.start;
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
     // batch k covers entries [t.start + 64 k, ...): its slots are loaded two batches ahead,
@@ -240,7 +243,10 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         float tmax = ps.T[0];
 #pragma unroll
         for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
-        if (__ballot(tmax >= 0.f) == 0) break;          // every pixel of the item is finished
+        if (__ballot(tmax >= 0.f) == 0) {               // every pixel of the item is finished
+            walked = b - t.start;
+            break;
+        }
         // groups of 8 entries, with the all-finished test between groups, so that the inner
         // loop has a single exit
         for (int j0 = 0; j0 < nb; j0 += 8) {
@@ -283,6 +289,15 @@ __device__ inline void fwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     if (!snapped) take_snapshot<PX>(ps, *sn);
 #pragma unroll
     for (int q = 0; q < PX; ++q) ps.T[q] = fabsf(ps.T[q]);
+    return walked;
+}
+
+// Records the forward walk length of the item's tile for the next work list (whole tiles,
+// and part 0 of a split tile).
+__device__ inline void record_walk(int32_t *__restrict__ sched, int n_tiles, int item, int walked)
+{
+    if ((item & 0x1B) == 0 && (threadIdx.x & (kWave - 1)) == 0)   // seg 0 and part 0
+        sched[sched_walk_offset(n_tiles) + (item >> kItemTileShift)] = walked;
 }
 
 __device__ inline int wave_max(int v)
@@ -516,11 +531,12 @@ struct FwdOut {
 
 template <int PX, bool kVisited>
 __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
-                                const ItemPixels &t, const gs_params &prm, const FwdOut &o)
+                                const ItemPixels &t, const gs_params &prm, const FwdOut &o, int32_t *sched,
+                                int n_tiles, int item)
 {
     PixState<PX> ps;
     init_state<PX>(t, ps);
-    fwd_walk<PX, kVisited>(rr, ids, t, prm, ps);
+    record_walk(sched, n_tiles, item, fwd_walk<PX, kVisited>(rr, ids, t, prm, ps));
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
         if (pixel_inside<PX>(t, q)) {
@@ -538,26 +554,30 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
 template <bool kVisited>
 __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
-    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio, int grab, int prio_len)
+    int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio, int grab, int prio_len,
+    int n_tiles)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     ItemCursor cur{0, 0};
     for (;;) {
-        const int item = next_item(sched, kSchedFwd, n_items, grab, cur, lane);
+        const int item = next_item(sched, kSchedFwd, n_items, grab, cur, lane, n_tiles);
         if (item < 0) break;
         if ((item >> 3) & 3) continue;   // a backward segment of the fused kernel
         if (item & 4) {
             if (prio) __builtin_amdgcn_s_setprio(2);
             if (parts == 4)
-                fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o);
+                fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+                                      item);
             else
-                fwd_item<2, kVisited>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o);
+                fwd_item<2, kVisited>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+                                      item);
             __builtin_amdgcn_s_setprio(0);
         } else {
             if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
-            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o);
+            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+                                  item);
             __builtin_amdgcn_s_setprio(0);
         }
     }
@@ -634,7 +654,7 @@ struct FusedIO {
 template <int PX>
 __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
                                   const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out,
-                                  int seg, int segs)
+                                  int seg, int segs, int32_t *sched, int n_tiles, int item)
 {
     // segment seg of segs: list positions [lo, hi), boundaries at multiples of 64 entries
     const int n = t.end - t.start;
@@ -644,10 +664,9 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
     PixState<PX> ps;
     init_state<PX>(t, ps);
     Snapshot<PX> sn;
-    if (hi < t.end)
-        fwd_walk<PX, false>(rr, ids, t, prm, ps, hi, &sn);
-    else
-        fwd_walk<PX, false>(rr, ids, t, prm, ps);
+    const int walked = hi < t.end ? fwd_walk<PX, false>(rr, ids, t, prm, ps, hi, &sn)
+                                  : fwd_walk<PX, false>(rr, ids, t, prm, ps);
+    record_walk(sched, n_tiles, item, walked);
     float g0[PX], g1[PX], g2[PX];
     float l2 = 0.f;
 #pragma unroll
@@ -693,7 +712,7 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_fused_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FusedIO io,
-    BwdOut out, int prio, int grab, int prio_len)
+    BwdOut out, int prio, int grab, int prio_len, int n_tiles)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
@@ -701,19 +720,22 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
     const int segs = __builtin_amdgcn_readfirstlane(sched[kSchedSegs]);
     ItemCursor cur{0, 0};
     for (;;) {
-        const int item = next_item(sched, kSchedFused, n_items, grab, cur, lane);
+        const int item = next_item(sched, kSchedFused, n_items, grab, cur, lane, n_tiles);
         if (item < 0) break;
         if (item & 4) {
             const int seg = (item >> 3) & 3;
             if (prio) __builtin_amdgcn_s_setprio(2);
             if (parts == 4)
-                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs);
+                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
+                              sched, n_tiles, item);
             else
-                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs);
+                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
+                              sched, n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         } else {
             if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
-            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1);
+            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
+                          n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         }
     }
@@ -748,11 +770,11 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     if (visited)
         hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
                            bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len);
+                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     else
         hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
                            bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len);
+                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_fwd");
 }
 
@@ -806,6 +828,6 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
                        (int)n_cams, *prm, io, out, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len);
+                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_fused_l2");
 }

@@ -179,7 +179,7 @@ class Bins:
         return Bins(torch.empty(capacity, dtype=torch.int64, device=device),
                     torch.empty(capacity, dtype=torch.int32, device=device),
                     torch.empty(2 * max(n_tiles, 1), dtype=torch.int32, device=device),
-                    torch.empty(abi.gs_schedule_size(n_tiles), dtype=torch.int32, device=device),
+                    torch.zeros(abi.gs_schedule_size(n_tiles), dtype=torch.int32, device=device),
                     torch.zeros(2, dtype=torch.int64, device=device),
                     torch.empty(max(ws, 1), dtype=torch.uint8, device=device), capacity, n_tiles)
 
