@@ -11,9 +11,10 @@ result beyond the rounding order of gradient sums, only the time.
 
 ``tune`` times a full training step (project, bin and sort, fused forward + loss +
 backward, project_bwd) captured in a HIP graph under each candidate and keeps the fastest.
-The search is a coordinate descent from the library default: one knob at a time over its
-values (KNOBS; item_grab stays at 1), keeping the best value before moving to the next
-knob, up to three rounds; each candidate is timed as the best of three runs. Results are
+The search is a coordinate descent from the best of the library default and a few seeds
+(SEEDS): one knob at a time over its values (KNOBS; item_grab stays at 1), keeping the best
+value before moving to the next knob, up to three rounds; each candidate is timed as the
+best of three runs. Results are
 cached in a JSON file keyed by a signature of the workload (cameras, resolutions, Gaussian
 count, and the list length rounded to a power of two), so a later process with the same
 kind of batch applies the recorded tuning without searching; ``python -m
@@ -43,6 +44,15 @@ KNOBS = {
 # item_grab is left at 1: taking several items per atomic put consecutive long items (the
 # head of the longest-first list) on one wave and made the 1M-Gaussian and the 32-view
 # steps 2-6x slower, with no gain at 16 views (measured on MI355X).
+
+
+# Starting points besides the default: knobs that only pay off together (finer splitting
+# needs the longest walks cut into backward segments and prioritised), which a search that
+# moves one knob at a time does not reach from the default.
+SEEDS = (
+    {"split_len": 512, "split_parts": 4, "split_priority": 1, "prio_len": 256, "bwd_segs": 2},
+    {"split_len": 1024, "split_parts": 4, "split_priority": 1, "bwd_segs": 2},
+)
 
 
 def default_tuning() -> dict:
@@ -126,6 +136,11 @@ def search(measure: Callable[[], float], rounds: int = 3, log: Callable[[str], N
 
     best = default_tuning()
     default_ms = best_ms = run(best)
+    for seed in SEEDS:
+        cand = {**default_tuning(), **seed}
+        ms = run(cand)
+        if ms < best_ms:
+            best, best_ms = cand, ms
     for _ in range(rounds):
         improved = False
         for knob, values in KNOBS.items():
