@@ -156,12 +156,20 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
     return -1;
 }
 
-// An unsplit tile whose list has at least prio_len entries (prio_len > 0): its walk is among
+// An unsplit tile whose walk has at least prio_len entries (prio_len > 0; the list length,
+// or the walk length the last rasterization recorded when it is shorter): its walk is among
 // the last to finish, so its wave takes issue priority.
-__device__ inline bool long_walk(const int32_t *__restrict__ ranges, int item, int prio_len)
+__device__ inline bool long_walk(const int32_t *__restrict__ ranges, const int32_t *__restrict__ sched,
+                                 int n_tiles, int item, int prio_len)
 {
+    if (prio_len <= 0) return false;
     const int tile = item >> kItemTileShift;
-    return prio_len > 0 && ranges[2 * tile + 1] - ranges[2 * tile] >= prio_len;
+    int len = ranges[2 * tile + 1] - ranges[2 * tile];
+    if (sched[kSchedWalkStamp] == n_tiles) {
+        const int walk = sched[sched_walk_offset(n_tiles) + tile];
+        if (walk >= 1 && walk < len) len = walk;
+    }
+    return len >= prio_len;
 }
 
 // ----------------------------------------------------------------------------- forward
@@ -575,7 +583,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
                                       item);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
             fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                   item);
             __builtin_amdgcn_s_setprio(0);
@@ -618,7 +626,7 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_bwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out,
-    int prio, int grab, int prio_len)
+    int prio, int grab, int prio_len, int n_tiles)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
@@ -636,7 +644,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
                 bwd_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
             bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         }
@@ -733,7 +741,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
                               sched, n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
             fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
                           n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
@@ -806,7 +814,7 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
                        (int)n_cams, *prm, in, out, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len);
+                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_bwd");
 }
 
