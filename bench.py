@@ -82,17 +82,37 @@ def cpu_baseline(wl, E_fwd: int, repeats: int = 3):
 
 def time_steps(fn, steps: int, warmup: int) -> float:
     """Mean ms per call over `steps` calls after `warmup`, events around the whole region."""
+    return time_steps_detail(fn, steps, warmup)[0]
+
+
+def time_steps_detail(fn, steps: int, warmup: int):
+    """(mean ms per call over the whole region, [ms of each call]); an event between calls."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
         fn()
-    b.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def e_dense(step) -> int:
+    """Sum over tiles of list length x image pixels in the tile (every pair of the lists)."""
+    import numpy as np
+    rg = step.r.bins.ranges[: 2 * step.cams.n_tiles].view(-1, 2).cpu().numpy().astype(np.int64)
+    length = rg[:, 1] - rg[:, 0]
+    total = 0
+    for c in step.cams.host:
+        w, h, toff, tx = int(c["width"]), int(c["height"]), int(c["tile_offset"]), int(c["tiles_x"])
+        ty = (h + 15) // 16
+        px = np.minimum(16, w - 16 * np.arange(tx))[None, :] * np.minimum(16, h - 16 * np.arange(ty))[:, None]
+        total += int((length[toff: toff + tx * ty].reshape(ty, tx) * px).sum())
+    return total
 
 
 def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
@@ -218,7 +238,7 @@ def main():
 
     # the timed step: the whole path, captured once in a HIP graph and replayed
     runner = step if args.no_graph else pipeline.GraphStep(step)
-    ms_step = time_steps(runner, args.steps, args.warmup)
+    ms_step, per_step = time_steps_detail(runner, args.steps, args.warmup)
     if step.overflowed():
         raise SystemExit("intersection list overflowed its capacity during the timed steps")
     log(f"step {ms_step:.4f} ms ({'eager' if args.no_graph else 'graph'})")
@@ -240,8 +260,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "n_gaussians": g.n, "views": views, "width": int(cams.host[0]["width"]),
                    "height": int(cams.host[0]["height"]), "K": step.K, "E_fwd": step.E_fwd, "E_bwd": step.E_bwd,
-                   "ms_per_view": ms_step / views, "mode": args.mode, "graph": not args.no_graph,
+                   "E_dense": e_dense(step), "ms_per_view": ms_step / views, "mode": args.mode,
+                   "graph": not args.no_graph,
                    "parallelism": "single-gpu", "tuning": autotune.current()},
+        "step_ms_median_p10_p90": [float(np.median(per_step)), float(np.percentile(per_step, 10)),
+                                   float(np.percentile(per_step, 90))],
         "stages_ms": stage_ms,
         "roofline": roofline,
         "autotune": None if tuned is None else {k: tuned[k] for k in ("default_ms", "ms", "evaluated", "seconds",
