@@ -99,43 +99,54 @@ __device__ inline int64_t tile_sort_count(const int64_t *counter, int64_t cap)
 }
 
 // Lanes of the wave whose `digit` equals this lane's, among lanes in `valid`.
+// Per bit: the ballot of the lanes with the bit set, xor this lane's bit spread over 64
+// bits, marks the lanes that differ from this one in that bit.
 __device__ inline uint64_t match_digit(unsigned digit, uint64_t valid)
 {
-    uint64_t peers = valid;
+    uint64_t differ = 0;
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
-        const uint64_t bal = __ballot((digit >> b) & 1u);
-        peers &= ((digit >> b) & 1u) ? bal : ~bal;
+        const int bit = ((int)(digit << (31 - b))) >> 31;   // 0 or -1
+        differ |= __ballot(bit != 0) ^ (uint64_t)(int64_t)bit;
     }
-    return peers;
+    return valid & ~differ;
 }
 
-// Adds the digit counts of the keys in row r of each wave (lanes set in valid[r]) to
-// cnt[wave][digit]; row r of wave w holds the chunk's keys w * M + 64 r + lane
-// (M = kSortChunk / kSortWaves). The leader lane of each digit group adds its group size.
-__device__ inline void count_digit_rows(const uint32_t (&key)[kSortItems], const uint64_t (&valid)[kSortItems],
-                                        int shift, unsigned (*cnt)[kRadix])
+// Ranks the keys of this block's chunk within their wave: rank[r] is the number of the
+// wave's keys with the same digit before row r's key (earlier rows, then lower lanes of the
+// same row); row r of wave w holds the chunk's keys w * M + 64 r + lane (M = kSortChunk /
+// kSortWaves), valid below kvalid - chunk_base. Per row, the leader lane of each digit group
+// adds the group's size to cnt[wave][digit] with an LDS atomic that returns the count
+// before it, and the group takes that value from its leader. The atomics of a wave execute
+// in issue order (the wave barrier keeps the compiler from reordering rows); all rows issue
+// their atomics before any row reads a result back, so the rows do not wait on each other.
+// Afterwards cnt[wave][digit] holds the wave's digit counts.
+__device__ inline void rank_digits(const uint32_t (&key)[kSortItems], int64_t chunk_base, int64_t kvalid, int shift,
+                                   unsigned (*cnt)[kRadix], unsigned (&rank)[kSortItems])
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint64_t lt = lanemask_lt();
+    unsigned group = (unsigned)lane;   // previous row: leader lane | (peers below this lane) << 8
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        if (valid[r] == 0) continue;
-        const unsigned d = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid[r]);
-        if (((valid[r] >> lane) & 1) && (peers & lanemask_lt()) == 0) cnt[wave][d] += (unsigned)__popcll(peers);
+        const bool ok = chunk_base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane < kvalid;
+        const uint64_t valid = __ballot(ok);
+        rank[r] = 0;
+        unsigned g = (unsigned)lane;
+        if (valid != 0) {   // uniform
+            const unsigned d = (key[r] >> shift) & (kRadix - 1);
+            const uint64_t peers = match_digit(d, valid);
+            if (ok && (peers & lt) == 0)
+                rank[r] = __hip_atomic_fetch_add(&cnt[wave][d], (unsigned)__popcll(peers), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_wave_barrier();
+            if (ok) g = (unsigned)__builtin_ctzll(peers) | ((unsigned)__popcll(peers & lt) << 8);
+        }
+        // the previous row's result is taken from its leader once this row's atomic is issued
+        if (r > 0) rank[r - 1] = (unsigned)__shfl((int)rank[r - 1], (int)(group & 0xff), kWave) + (group >> 8);
+        group = g;
     }
-}
-
-// Counts digits of this block's chunk: keys with chunk index below kvalid - chunk_base.
-__device__ inline void count_digits(const uint32_t (&key)[kSortItems], int64_t chunk_base, int64_t kvalid, int shift,
-                                    unsigned (*cnt)[kRadix])
-{
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint64_t valid[kSortItems];
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r)
-        valid[r] = __ballot(chunk_base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane < kvalid);
-    count_digit_rows(key, valid, shift, cnt);
+    rank[kSortItems - 1] = (unsigned)__shfl((int)rank[kSortItems - 1], (int)(group & 0xff), kWave) + (group >> 8);
 }
 
 // Status word of one (block, digit) in a single-pass sort, or of one block in a
@@ -227,11 +238,60 @@ __device__ inline int64_t chained_prefix(const uint64_t *status, int b, int64_t 
     }
 }
 
+// Exclusive prefix, over chunks 0 .. b - 1 (b > 0), of digit d's counts in a single-pass
+// sort, from their status words. The first step reads the nearest predecessor only (when
+// chunks finish in order it is already inclusive, and the walk costs one load); later
+// steps read kLookWindow chunks at once (independent loads whose latencies overlap) and sum
+// down to the nearest inclusive word. When a chunk has not published yet, the sum keeps
+// what lies above it and the next step starts there. Returns -1 when the wait gave up.
+constexpr int kLookWindow = 8;
+
+__device__ inline int64_t digit_lookback(const uint64_t *status, int b, int d, int64_t *err_flag)
+{
+    int64_t acc = 0;
+    int j = b - 1;   // highest chunk not yet summed
+    int window = 1;
+    int spins = 0;
+    while (true) {
+        uint64_t st[kLookWindow];
+#pragma unroll
+        for (int i = 0; i < kLookWindow; ++i) {
+            // chunk 0 always publishes an inclusive word, so the walk never passes below it;
+            // a zero word past the window ends the step like an unpublished chunk
+            st[i] = 0;
+            if (i < window)
+                st[i] = j - i >= 0 ? __hip_atomic_load(status + (int64_t)(j - i) * kRadix + d, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : kStatInc;
+        }
+        int64_t sum = 0;
+        int taken = 0;         // leading chunks of the window summed
+        bool done = false, open = true;
+#pragma unroll
+        for (int i = 0; i < kLookWindow; ++i) {
+            const uint64_t flag = st[i] & ~kStatValue;
+            if (open && flag == 0) open = false;
+            if (open) {
+                sum += (int64_t)(st[i] & kStatValue);
+                ++taken;
+                if (flag == kStatInc) {
+                    done = true;
+                    open = false;
+                }
+            }
+        }
+        acc += sum;
+        if (done) return acc;
+        j -= taken;
+        if (taken < window && spin_exhausted(spins, err_flag)) return -1;
+        window = kLookWindow;
+    }
+}
+
 // LDS of one single-pass sort block.
 struct SweepShared {
     unsigned cnt[kSortWaves][kRadix];   // per-(wave, digit) counts, then staging cursors
-    unsigned lstart[kRadix];            // staging start of each digit
-    int64_t gbase[kRadix];              // global position of the block's first key per digit
+    int64_t gdelta[kRadix];             // global position minus staging index, per digit
     uint32_t skey[kSortChunk];          // staged keys (digit order); first holds rank offsets
     int32_t sval[kSortChunk];
     int chunk, gave_up;
@@ -246,17 +306,79 @@ __device__ inline bool sweep_begin(SweepShared &sh, const int64_t *err_flag)
     return chunk_stop(err_flag, &sh.chunk);
 }
 
+// Global position of the first key with digit d (thread d's value), from the pass's digit
+// histogram; the same for every chunk of a launch.
+__device__ inline int64_t digit_start(const unsigned *__restrict__ ghist)
+{
+    int64_t total;
+    return block_exclusive_scan<int64_t>((int64_t)ghist[threadIdx.x], &total);
+}
+
+// Writes out staged keys q0 * kSortBlock + threadIdx.x, stepping by kSortBlock, kOutGroup of
+// them: consecutive threads take consecutive staged keys, so each digit's run of the chunk
+// is written by consecutive lanes to consecutive addresses, and all reads of the group
+// (LDS, then the gathers) are issued before its writes.
+constexpr int kOutGroup = 8;
+
+__device__ inline void sweep_write(SweepShared &sh, int q0, int n_here, int64_t kvalid, int shift,
+                                   uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out,
+                                   uint64_t *__restrict__ keys64_out, const float *__restrict__ depth,
+                                   const int32_t *__restrict__ gather_src, int32_t *__restrict__ gather_dst,
+                                   int64_t n_splats)
+{
+    uint32_t k_[kOutGroup];
+    int32_t v_[kOutGroup];
+    int64_t g_[kOutGroup];
+#pragma unroll
+    for (int q = 0; q < kOutGroup; ++q) {
+        const int i = (int)threadIdx.x + (q0 + q) * kSortBlock;
+        const bool ok = i < n_here;
+        k_[q] = ok ? sh.skey[i] : 0u;
+        v_[q] = ok ? sh.sval[i] : 0;
+        g_[q] = ok ? sh.gdelta[(k_[q] >> shift) & (kRadix - 1)] + i : -1;
+        if (g_[q] >= kvalid) g_[q] = -1;   // unreachable when the counts are consistent
+    }
+    if (keys64_out) {
+        // v is a splat slot by construction; the test keeps a broken invariant from turning
+        // into a wild read
+        uint32_t dbits[kOutGroup];
+#pragma unroll
+        for (int q = 0; q < kOutGroup; ++q)
+            dbits[q] = g_[q] >= 0 && (uint64_t)(uint32_t)v_[q] < (uint64_t)n_splats ? __float_as_uint(depth[v_[q]]) : 0u;
+#pragma unroll
+        for (int q = 0; q < kOutGroup; ++q) {
+            if (g_[q] < 0) continue;
+            vals_out[g_[q]] = v_[q];
+            keys64_out[g_[q]] = ((uint64_t)k_[q] << 32) | (uint64_t)dbits[q];
+        }
+    } else {
+        int32_t gs[kOutGroup];
+        if (gather_dst) {
+#pragma unroll
+            for (int q = 0; q < kOutGroup; ++q)
+                gs[q] = g_[q] >= 0 && (uint64_t)(uint32_t)v_[q] < (uint64_t)n_splats ? gather_src[v_[q]] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kOutGroup; ++q) {
+            if (g_[q] < 0) continue;
+            vals_out[g_[q]] = v_[q];
+            if (keys_out) keys_out[g_[q]] = k_[q];
+            if (gather_dst) gather_dst[g_[q]] = gs[q];
+        }
+    }
+}
+
 // One stable LSD pass over chunk b, keys already in registers in the wave-strided layout
 // (lane l of wave w holds, in row r, key base + w * kSortChunk / kSortWaves + 64 r + l).
-// The block ranks its chunk (wave ballots, per-(wave, digit) LDS counters), publishes its
-// digit counts, looks back over its predecessors' published counts for its global
-// offsets, stages the chunk in LDS in digit order and writes it out in runs. With
-// keys64_out set (the last tile pass) it writes ids and the 64-bit keys
-// (tile << 32 | depth bits of the value) instead of 32-bit keys; with gather_dst set it
-// also writes gather_src[value] there in output order (keys_out may then be null).
+// The block ranks its chunk (rank_digits), publishes its digit counts, looks back over its
+// predecessors' published counts for its global offsets, stages the chunk in LDS in digit
+// order and writes it out in runs. dstart is digit_start of the pass. With keys64_out set
+// (the last tile pass) it writes ids and the 64-bit keys (tile << 32 | depth bits of the
+// value) instead of 32-bit keys; with gather_dst set it also writes gather_src[value] there
+// in output order (keys_out may then be null).
 __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortItems],
                                   const int32_t (&val)[kSortItems], int b, int64_t base, int64_t kvalid, int shift,
-                                  const unsigned *__restrict__ ghist, uint64_t *__restrict__ status,
+                                  int64_t dstart, uint64_t *__restrict__ status,
                                   uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out,
                                   uint64_t *__restrict__ keys64_out, const float *__restrict__ depth,
                                   const int32_t *__restrict__ gather_src, int32_t *__restrict__ gather_dst,
@@ -264,7 +386,8 @@ __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortIt
 {
     const int n_here = (int)min((int64_t)kSortChunk, kvalid - base);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    count_digits(key, base, kvalid, shift, sh.cnt);
+    unsigned rank[kSortItems];
+    rank_digits(key, base, kvalid, shift, sh.cnt, rank);
     __syncthreads();
 
     // thread d owns digit d
@@ -272,40 +395,21 @@ __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortIt
     unsigned tot = 0;
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w) tot += sh.cnt[w][d];
-    int64_t gtot;
-    const int64_t dstart = block_exclusive_scan<int64_t>((int64_t)ghist[d], &gtot);   // first slot of digit d
     uint64_t *my = status + (int64_t)b * kRadix + d;
     int64_t excl = dstart;
     if (b == 0) {
         __hip_atomic_store(my, kStatInc | (uint64_t)(dstart + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         __hip_atomic_store(my, kStatAgg | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t acc = 0;
-        int j = b - 1;
-        int spins = 0;
-        while (true) {
-            const uint64_t st = __hip_atomic_load(status + (int64_t)j * kRadix + d, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = st & ~kStatValue;
-            if (flag == 0) {
-                if (spin_exhausted(spins, err_flag)) {
-                    sh.gave_up = 1;
-                    break;
-                }
-                continue;
-            }
-            acc += (int64_t)(st & kStatValue);
-            if (flag == kStatInc) break;
-            --j;
-        }
-        excl = acc;
-        __hip_atomic_store(my, kStatInc | (uint64_t)(acc + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t acc = digit_lookback(status, b, d, err_flag);
+        if (acc < 0) sh.gave_up = 1;   // the word below stays well formed; nothing is written
+        excl = acc < 0 ? 0 : acc;
+        __hip_atomic_store(my, kStatInc | (uint64_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    sh.gbase[d] = excl;
     unsigned ltot;
-    const unsigned ls = block_exclusive_scan<unsigned>(tot, &ltot);
-    sh.lstart[d] = ls;
-    // per-(wave, digit) cursors into the staging buffer
+    const unsigned ls = block_exclusive_scan<unsigned>(tot, &ltot);   // staging start of digit d
+    sh.gdelta[d] = excl - (int64_t)ls;
+    // per-(wave, digit) staging bases
     unsigned run = ls;
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w) {
@@ -316,45 +420,23 @@ __device__ inline void sweep_body(SweepShared &sh, const uint32_t (&key)[kSortIt
     __syncthreads();
     if (sh.gave_up) return;   // offsets unknown: write nothing (the error word is set)
 
-    // stage the chunk in digit order (stable: waves in order, lanes in order within a wave)
+    // stage the chunk in digit order (stable: waves in order, then rows, then lanes)
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = base + (int64_t)wave * (kSortChunk / kSortWaves) + r * kWave + lane;
-        const bool ok = idx < kvalid;
-        const uint64_t valid = __ballot(ok);
-        if (valid == 0) break;
-        const unsigned dg = (key[r] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(dg, valid);
-        const unsigned pos = sh.cnt[wave][dg] + (unsigned)__popcll(peers & lanemask_lt());
-        __builtin_amdgcn_wave_barrier();
-        if (ok && (peers & lanemask_lt()) == 0) sh.cnt[wave][dg] += (unsigned)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        if (ok) {
+        if (idx < kvalid) {
+            const unsigned pos = sh.cnt[wave][(key[r] >> shift) & (kRadix - 1)] + rank[r];
             sh.skey[pos] = key[r];
             sh.sval[pos] = val[r];
         }
     }
     __syncthreads();
 
-    // write out: consecutive threads take consecutive staged keys, so each digit's run of
-    // this chunk is written by consecutive lanes to consecutive addresses
-    for (int i = threadIdx.x; i < n_here; i += kSortBlock) {
-        const uint32_t k = sh.skey[i];
-        const int32_t v = sh.sval[i];
-        const unsigned dg = (k >> shift) & (kRadix - 1);
-        const int64_t g = sh.gbase[dg] + (i - (int)sh.lstart[dg]);
-        if (g < 0 || g >= kvalid) continue;   // unreachable when the counts are consistent
-        vals_out[g] = v;
-        if (keys64_out) {
-            // v is a splat slot by construction; the test keeps a broken invariant from
-            // turning into a wild read
-            const uint32_t dbits = (uint64_t)(uint32_t)v < (uint64_t)n_splats ? __float_as_uint(depth[v]) : 0u;
-            keys64_out[g] = ((uint64_t)k << 32) | (uint64_t)dbits;
-        } else {
-            if (keys_out) keys_out[g] = k;
-            if (gather_dst) gather_dst[g] = (uint64_t)(uint32_t)v < (uint64_t)n_splats ? gather_src[v] : 0;
-        }
-    }
+    // write out (sweep_write)
+#pragma unroll 1
+    for (int q0 = 0; q0 < kSortItems; q0 += kOutGroup)
+        sweep_write(sh, q0, n_here, kvalid, shift, keys_out, vals_out, keys64_out, depth, gather_src, gather_dst,
+                    n_splats);
 }
 
 // One stable LSD pass with decoupled look-back (chained scan over chunks), in one launch of
@@ -376,8 +458,9 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__
     __shared__ SweepShared sh;
     const int64_t kvalid = all_or_none ? tile_sort_count(count, cap) : sort_count(count, cap);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t dstart = digit_start(ghist);
     for (int64_t b = blockIdx.x; b * kSortChunk < kvalid; b += gridDim.x) {
-        if (sweep_begin(sh, err_flag)) break;
+        // the keys are loaded first, so their latency overlaps the turn's barriers
         const int64_t base = b * kSortChunk;
         uint32_t key[kSortItems];
         int32_t val[kSortItems];
@@ -388,7 +471,8 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_kernel(const uint32_t *__
             key[r] = ok ? keys_in[idx] : 0u;
             val[r] = ok ? vals_in[idx] : 0;
         }
-        sweep_body(sh, key, val, (int)b, base, kvalid, shift, ghist, status, keys_out, vals_out, keys64_out, depth,
+        if (sweep_begin(sh, err_flag)) break;
+        sweep_body(sh, key, val, (int)b, base, kvalid, shift, dstart, status, keys_out, vals_out, keys64_out, depth,
                    gather_src, gather_dst, n_splats, err_flag);
         if (sh.gave_up) break;   // uniform: set before a barrier inside sweep_body
     }
@@ -413,6 +497,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
     const int64_t kvalid = tile_sort_count(count, cap);
     const int64_t n_chunks = (kvalid + kSortChunk - 1) / kSortChunk;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t dstart = digit_start(ghist);
     for (int64_t b = blockIdx.x; b < n_chunks; b += gridDim.x) {
         if (sweep_begin(sh, err_flag)) break;
         const int64_t base = b * kSortChunk;
@@ -497,7 +582,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_emit_kernel(
             val[r] = ok ? sh.sval[i] : 0;
         }
         __syncthreads();   // the staging arrays are reused by the ranking
-        sweep_body(sh, key, val, (int)b, base, kvalid, 0, ghist, status, keys_out, vals_out, keys64_out, depth,
+        sweep_body(sh, key, val, (int)b, base, kvalid, 0, dstart, status, keys_out, vals_out, keys64_out, depth,
                    (const int32_t *)nullptr, (int32_t *)nullptr, n_splats, err_flag);
         if (sh.gave_up) break;
     }
