@@ -246,10 +246,11 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * disagree with K (the list is invalid and every range empty; this indicates a fault, not
  * a capacity problem); counters[1] & 4: a camera has more than 8192 tiles in a row (wider
  * than 131072 pixels), which is not supported (nothing is listed). workspace: device
- * memory of at least gs_bin_and_sort_workspace_size() bytes, contents free on entry and
- * exit. cams: as for gs_project.
+ * memory of at least gs_bin_and_sort_workspace_size() bytes, 256-byte aligned, contents
+ * free on entry and exit. cams: as for gs_project.
  * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1], n_splats outside
- * [0, 2^31 - 1], more cameras than tiles), GS_ERR_CAPACITY (workspace too small).
+ * [0, 2^31 - 1], more cameras than tiles, workspace not 256-byte aligned), GS_ERR_CAPACITY
+ * (workspace too small).
  */
 int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
                     gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream);

@@ -948,13 +948,25 @@ __global__ __launch_bounds__(kCountBlock) void tile_count_kernel(const gs_camera
             if (lane == 0) col_run[x] = carry;
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kCountBlock) {
-            const int v = cells[i];
+        // a wave holds 64 consecutive tiles: their low digits differ, while a higher digit is
+        // mostly the same across the wave, so it is added once from the wave's sum
+        for (int b = 0; b < n; b += kCountBlock) {
+            const int i = b + (int)threadIdx.x;
+            const bool ok = i < n;
+            const int v = ok ? cells[i] : 0;
             const int64_t t = t0 + i;
-            cnt[t] = v;
-            if (v)
-                for (int pass = 0; pass < passes; ++pass)
-                    atomicAdd(&h[pass][(t >> (pass * kRadixBits)) & (kRadix - 1)], (unsigned)v);
+            if (ok) cnt[t] = v;
+            if (v) atomicAdd(&h[0][t & (kRadix - 1)], (unsigned)v);
+            for (int pass = 1; pass < passes; ++pass) {
+                const unsigned d = (unsigned)(t >> (pass * kRadixBits)) & (kRadix - 1);
+                const unsigned d0 = __builtin_amdgcn_readfirstlane(d);
+                if (__ballot(ok && d != d0) == 0) {   // uniform
+                    const int sum = __shfl(wave_inclusive_scan(v), kWave - 1, kWave);
+                    if (lane == 0 && sum) atomicAdd(&h[pass][d0], (unsigned)sum);
+                } else if (v) {
+                    atomicAdd(&h[pass][d], (unsigned)v);
+                }
+            }
         }
         __syncthreads();
     }
@@ -1084,11 +1096,16 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
     }
 }
 
-// Folds the sort's error word into the flags (2: a look-back wait gave up or the counts
-// disagree; 4: a camera wider than the count array).
-__global__ __launch_bounds__(64) void err_fold_kernel(int64_t *__restrict__ counters, const int64_t *__restrict__ err)
+// Zeroes a[0, na) and b[0, nb) in one launch (grid-stride; consecutive threads take
+// consecutive words).
+__global__ __launch_bounds__(256) void zero_pair_kernel(int32_t *__restrict__ a, int64_t na, int32_t *__restrict__ b,
+                                                        int64_t nb)
 {
-    if (threadIdx.x == 0 && *err) counters[1] |= *err;
+    const int64_t n = na + nb, step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        if (i < na) a[i] = 0;
+        else b[i - na] = 0;
+    }
 }
 
 // chunk_rank[c] = depth rank of the splat that holds list entry c * kSortChunk
@@ -1111,12 +1128,6 @@ __global__ __launch_bounds__(256) void chunk_rank_kernel(const int32_t *__restri
         chunk_rank[c] = (int32_t)r;
 }
 
-__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------------ work list
 
 __device__ inline int length_bucket(int len)
@@ -1127,9 +1138,14 @@ __device__ inline int length_bucket(int len)
 }
 
 // Clears the header, except the walk-length stamp.
-__global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ sched)
+// Clears the work-list header (keeping the walk stamp) and folds the sort's error word, when
+// there is one, into the flags (2: a look-back wait gave up or the counts disagree; 4: a
+// camera wider than the count array).
+__global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ sched, int64_t *__restrict__ counters,
+                                                         const int64_t *__restrict__ err)
 {
     if (threadIdx.x != kSchedWalkStamp) sched[threadIdx.x] = 0;
+    if (threadIdx.x == 0 && err && *err) counters[1] |= *err;
 }
 
 // The length a tile is scheduled by: its list length, or the walk length of the last
@@ -1308,10 +1324,10 @@ static unsigned resident_grid(const void *kernel, int block, int64_t chunks)
 
 using namespace gsx;
 
-static int build_schedule(gs_bins *bins, hipStream_t st)
+static int build_schedule(gs_bins *bins, const int64_t *err, hipStream_t st)
 {
     const unsigned g = grid_for(bins->n_tiles, 256);
-    hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule);
+    hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule, bins->counters, err);
     const gs_tuning &tu = current_tuning();
     hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
                        tu.split_parts * tu.bwd_segs, bins->schedule);
@@ -1350,6 +1366,7 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     const BinLayout L = bin_layout(n_splats, cap, bins->n_tiles);
     if (!workspace || workspace_bytes < L.total)
         return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort: workspace too small");
+    if (((uintptr_t)workspace) & 255) return set_error(GS_ERR_INVALID, "gs_bin_and_sort: workspace not 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
     uint32_t *dkeyA = (uint32_t *)(ws + L.dkeyA), *dkeyB = (uint32_t *)(ws + L.dkeyB);
@@ -1365,15 +1382,18 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
-    // ranges start empty: (0, 0)
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(2ll * bins->n_tiles, 256)), dim3(256), 0, st, bins->ranges,
-                       2ll * bins->n_tiles, 0);
+    // ranges start empty, (0, 0); the look-back state, counts and histograms start at zero
     if (n_splats == 0) {
-        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(256), 0, st, (int32_t *)bins->counters, 4, 0);
-        return build_schedule(bins, st);
+        hipLaunchKernelGGL(zero_pair_kernel, dim3(grid_for(2ll * bins->n_tiles, 256)), dim3(256), 0, st,
+                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)bins->counters, (int64_t)4);
+        return build_schedule(bins, (const int64_t *)nullptr, st);
     }
-    int rc = gs_zero(ws + L.zero_begin, L.total - L.zero_begin, st);
-    if (rc != GS_OK) return rc;
+    {
+        const int64_t nz = (int64_t)((L.total - L.zero_begin) / 4), n = 2ll * bins->n_tiles + nz;
+        hipLaunchKernelGGL(zero_pair_kernel, dim3((unsigned)min(grid_for(n, 256), 4096u)), dim3(256), 0, st,
+                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)(ws + L.zero_begin), nz);
+    }
+    int rc = GS_OK;
 
     // 1. the V visible splats, compacted in slot order, with the digit counts of the depth
     // passes; the list length of every tile from their boxes, and the digit counts of the
@@ -1482,6 +1502,5 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
                        bins->ranges, err);
 
     // 6. the work list; the sort's error word joins the overflow flag
-    hipLaunchKernelGGL(err_fold_kernel, dim3(1), dim3(64), 0, st, bins->counters, (const int64_t *)err);
-    return build_schedule(bins, st);
+    return build_schedule(bins, (const int64_t *)err, st);
 }

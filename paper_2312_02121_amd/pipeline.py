@@ -333,15 +333,22 @@ class TrainStep:
         scene = {"colors": (3, n), "opacities": (n,), "means": (3, n), "scales": (3, n), "quats": (4, n),
                  "loss": (1,)}
         numel = lambda sh: int(np.prod(sh))
-        self.slot_flat = torch.empty(sum(numel(v) for v in slot.values()), dtype=torch.float64, device=cams.device)
+        n_slot = sum(numel(v) for v in slot.values())
+        n_scene = sum(numel(v) for v in scene.values())
+        self.owns_scene_grads = scene_grads is None
+        # one allocation for both parts when this step owns the scene gradients, so that a
+        # single fill zeroes them
+        slot_bytes = n_slot * 8
+        scene_at = (slot_bytes + 255) // 256 * 256
+        total = scene_at + n_scene * 4 if self.owns_scene_grads else slot_bytes
+        self.grad_bytes = torch.empty(total, dtype=torch.uint8, device=cams.device)
+        self.slot_flat = self.grad_bytes[:slot_bytes].view(torch.float64)
         self.grads, o = {}, 0
         for k, sh in slot.items():
             self.grads[k] = self.slot_flat[o:o + numel(sh)].view(sh)
             o += numel(sh)
-        self.owns_scene_grads = scene_grads is None
         if scene_grads is None:
-            self.scene_flat = torch.empty(sum(numel(v) for v in scene.values()), dtype=torch.float32,
-                                          device=cams.device)
+            self.scene_flat = self.grad_bytes[scene_at:].view(torch.float32)
             o = 0
             for k, sh in scene.items():
                 self.grads[k] = self.scene_flat[o:o + numel(sh)].view(sh)
@@ -369,9 +376,8 @@ class TrainStep:
         elif name == "l2_grad":
             abi.gs_l2_grad(r.image.data_ptr(), self.targets.data_ptr(), r.image.numel(), self.dL.data_ptr(), stream)
         elif name == "zero_grads":
-            abi.gs_zero(self.slot_flat.data_ptr(), self.slot_flat.numel() * 8, stream)
-            if self.owns_scene_grads:
-                abi.gs_zero(self.scene_flat.data_ptr(), self.scene_flat.numel() * 4, stream)
+            # the slot gradients, and the scene gradients after them when this step owns them
+            abi.gs_zero(self.grad_bytes.data_ptr(), self.grad_bytes.numel(), stream)
         elif name == "rasterize_bwd":
             abi.gs_rasterize_bwd(r.splats.struct(P), P, r.bins.struct(), cams.ptr, cams.n_cams, r.params,
                                  cams.n_pixels, self.dL.data_ptr(), r.T_final.data_ptr(), r.last.data_ptr(),
