@@ -63,6 +63,11 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
                               16, None)
     assert rc == abi.GS_ERR_INVALID
     assert b"alpha_max" in lib.gs_last_error_message()
+    # a workspace that is large enough but not 256-byte aligned
+    ws = abi.gs_bin_and_sort_workspace_size(10, 10, 1)
+    rc = lib.gs_bin_and_sort(abi._ref(sp), 10, 64, 1, abi._ref(bins), 4096 + 8, ws, None)
+    assert rc == abi.GS_ERR_INVALID
+    assert b"aligned" in lib.gs_last_error_message()
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
