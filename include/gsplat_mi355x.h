@@ -168,6 +168,10 @@ typedef struct gs_tuning {
                                 part as this many list segments, one work item each (every
                                 such item repeats the part's forward), so that the longest
                                 walks, the end of the launch, are shorter */
+    int32_t atomic_lanes;    /* 1..64: in the backward, a splat whose pixels with a nonzero
+                                alpha sit in at most this many lanes of a wave is summed with
+                                LDS atomics from those lanes; otherwise the wave sums it with
+                                DPP row operations (cheaper for large splats) */
 } gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */

@@ -39,9 +39,6 @@ namespace gsx {
 
 constexpr int kBlockWaves = 4;
 constexpr int kBatch = kWave;   // list entries staged per wave and batch
-// Up to this many contributing lanes, a splat's gradient terms are added into its LDS slot
-// with atomics; above it the wave reduces them with DPP first.
-constexpr int kLdsAtomicLanes = 4;
 
 // The wave's LDS slice for one batch of records.
 __device__ inline RasterRec *wave_slice()
@@ -319,6 +316,7 @@ struct BwdOut {
     int64_t n_splats, n_gauss;
     double *d_mean2d, *d_conic;
     float *d_colors, *d_opac;
+    int atomic_lanes;   // up to this many contributing lanes, a splat's slot takes LDS atomics
 };
 
 // Per-wave gradient sums of the batch being walked: one slot per staged record, holding
@@ -326,8 +324,9 @@ struct BwdOut {
 //   sum alpha T dL/dC(k), k = 0..2                                 (float32)
 // over the wave's pixels. After each splat the wave fills that splat's slot in one of two
 // ways, chosen by the number of lanes with a composited pixel (wave-uniform):
-//   few lanes (small splats, the common case at 1M Gaussians): those lanes add their
-//     terms into the slot with LDS atomics, which conflict only among themselves;
+//   few lanes, at most the tuning's atomic_lanes (small splats, the common case at 1M
+//     Gaussians): those lanes add their terms into the slot with LDS atomics, which
+//     conflict only among themselves;
 //   many lanes (large splats): a DPP reduction over the wave, and lane 63 writes the
 //     totals into the slot (the splat's only writer).
 // When the batch is done, lane j moves slot j to global memory with one atomic per term,
@@ -478,7 +477,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             }
             const uint64_t live = __ballot(live_sum > 0.f);
             if (live == 0) continue;
-            if (__popcll(live) <= kLdsAtomicLanes) {
+            if (__popcll(live) <= out.atomic_lanes) {
                 const double s_y = s_v * dy, s_xy = s_x * dy;
                 const double s_yy = s_y * dy;
                 if (live_sum > 0.f) {
@@ -810,7 +809,8 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     if (rc != GS_OK) return rc;
     if (bins->n_tiles == 0) return GS_OK;
     const BwdIn in{n_pixels, dL_dimage, T_final, last};
-    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
+    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac,
+                     current_tuning().atomic_lanes};
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
                        (int)n_cams, *prm, in, out, current_tuning().split_priority,
@@ -832,7 +832,8 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     if (rc != GS_OK) return rc;
     if (bins->n_tiles == 0) return GS_OK;
     const FusedIO io{n_pixels, target, image, loss};
-    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac};
+    const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac,
+                     current_tuning().atomic_lanes};
     hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
                        (int)n_cams, *prm, io, out, current_tuning().split_priority,

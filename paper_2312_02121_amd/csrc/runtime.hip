@@ -34,7 +34,7 @@ int check_hip(hipError_t e, const char *what)
 
 int check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
 
-static gs_tuning g_tuning = {256, 4, 32, 1, 0, 1, 0, 1};
+static gs_tuning g_tuning = {256, 4, 32, 1, 0, 1, 0, 1, 4};
 
 const gs_tuning &current_tuning() { return g_tuning; }
 
@@ -223,10 +223,11 @@ extern "C" int gs_set_tuning(const gs_tuning *t)
     if (!t) return set_error(GS_ERR_INVALID, "gs_set_tuning: null argument");
     if (t->split_len < 1 || (t->split_parts != 2 && t->split_parts != 4) || t->waves_per_cu < 4 ||
         t->waves_per_cu > 64 || (t->generate_entries != 0 && t->generate_entries != 1) || t->item_grab < 1 ||
-        t->item_grab > 16 || t->prio_len < 0 || (t->bwd_segs != 1 && t->bwd_segs != 2 && t->bwd_segs != 4))
+        t->item_grab > 16 || t->prio_len < 0 || (t->bwd_segs != 1 && t->bwd_segs != 2 && t->bwd_segs != 4) ||
+        t->atomic_lanes < 1 || t->atomic_lanes > 64)
         return set_error(GS_ERR_INVALID, "gs_set_tuning: split_len >= 1, split_parts in {2, 4}, waves_per_cu in "
                                          "[4, 64], generate_entries in {0, 1}, item_grab in [1, 16], prio_len >= 0, "
-                                         "bwd_segs in {1, 2, 4}");
+                                         "bwd_segs in {1, 2, 4}, atomic_lanes in [1, 64]");
     g_tuning = *t;
     return GS_OK;
 }
