@@ -123,6 +123,51 @@ __device__ __forceinline__ float alpha_raw(const RasterRec &r, double dx, double
     return __builtin_amdgcn_exp2f((float)e);
 }
 
+// Records of a staged batch that cannot reach alpha_min at any pixel of the wave are skipped
+// by both walks: for them every pixel's alpha is below alpha_min, so their step is a no-op
+// (T, the colour, the last index and every gradient sum stay unchanged). The test is made once
+// per record and batch, by the lane that gathered it, against the rectangle of the wave's
+// pixel centres.
+struct WaveRect {
+    double x_lo, x_hi, y_lo, y_hi;   // pixel centres of the wave: [x_lo, x_hi] x [y_lo, y_hi]
+    double thr;                       // log2(alpha_min) less a margin
+};
+
+template <int PX>
+__device__ inline WaveRect wave_rect(const ItemPixels &t, const gs_params &prm)
+{
+    // lane 0 holds the first row and column, lane 63 the last row and the last lane's columns
+    WaveRect w;
+    w.x_lo = (double)__builtin_amdgcn_readlane(t.col0, 0) + 0.5;
+    w.x_hi = (double)__builtin_amdgcn_readlane(t.col0, kWave - 1) + (double)(PX - 1) + 0.5;
+    w.y_lo = (double)__builtin_amdgcn_readlane(t.row, 0) + 0.5;
+    w.y_hi = (double)__builtin_amdgcn_readlane(t.row, kWave - 1) + 0.5;
+    // the margin (2^-10) is far above the rounding of the per-pixel exponent, its float32
+    // conversion and exp2; with alpha_min <= 0 the threshold is -inf or NaN and nothing is skipped
+    w.thr = log2((double)prm.alpha_min) - 0x1p-10;
+    return w;
+}
+
+// True when the gathered record cannot reach alpha_min inside the rectangle. The exponent
+// lo + A dx^2 + B dx dy + C dy^2 (a concave quadratic) is at least thr only inside an ellipse
+// around mu' whose bounding box has half-widths sqrt(k (-4C) / D) and sqrt(k (-4A) / D), with
+// k = lo - thr and D = 4AC - B^2; the record is skipped when k < 0 or that box, widened by a
+// relative 2^-20 and an absolute 2^-20, misses the rectangle. Records whose D carries more
+// than 2^-20 relative cancellation, and any NaN, are kept.
+__device__ inline bool record_misses(const Gathered &g, const WaveRect &w)
+{
+    RasterRec r;
+    __builtin_memcpy(&r, &g, sizeof(RasterRec));
+    const double k = r.lo - w.thr;
+    if (k < 0.0) return true;
+    const double ac4 = 4.0 * r.A * r.C, bb = r.B * r.B, D = ac4 - bb;
+    if (!(D * 0x1p20 > ac4 + bb)) return false;
+    const double sx = sqrt(k * (-4.0 * r.C) / D) * (1.0 + 0x1p-20) + 0x1p-20;
+    const double sy = sqrt(k * (-4.0 * r.A) / D) * (1.0 + 0x1p-20) + 0x1p-20;
+    const double mx = r.mx, my = r.my;
+    return mx + sx < w.x_lo || mx - sx > w.x_hi || my + sy < w.y_lo || my - sy > w.y_hi;
+}
+
 // Work-list cursor of a wave: positions [pos, end) taken from the counter and not yet used.
 struct ItemCursor {
     int pos, end;
@@ -230,6 +275,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
 {
     bool snapped = snap_pos < 0;
     int walked = t.end - t.start;
+    const WaveRect wr = wave_rect<PX>(t, prm);
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
     // batch k covers entries [t.start + 64 k, ...): its slots are loaded two batches ahead,
@@ -242,6 +288,8 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             snapped = true;
         }
         const int nb = min(kBatch, t.end - b);
+        // the counting pass (kVisited) counts every pair it reaches
+        const uint64_t skip = kVisited ? 0ull : __ballot(lane < nb && record_misses(next, wr));
         stage(slice, next, lane);
         if (b + kBatch < t.end) next = gather(rr, nid);
         if (b + 2 * kBatch < t.end) nid = load_ids(ids, b + 2 * kBatch, t.end - b - 2 * kBatch, lane);
@@ -268,6 +316,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             // the next record is read while this one is composited (index kept inside the slice)
             const RasterRec r = rn;
             rn = slice[min(j + 1, kBatch - 1)];
+            if ((skip >> j) & 1) continue;
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
@@ -409,6 +458,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     maxlast = __builtin_amdgcn_readfirstlane(wave_max(maxlast));
     const int kend = min(hi, t.start + maxlast);
     if (kend <= lo) return;
+    const WaveRect wr = wave_rect<PX>(t, prm);
     RasterRec *slice = wave_slice();
     WaveAcc *acc = wave_acc();
     acc_clear(acc, lane);
@@ -425,6 +475,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     for (int bend = kend; bend > lo; bend -= kBatch) {
         const int bstart = max(lo, bend - kBatch);
         const int nb = bend - bstart;
+        const uint64_t skip = __ballot(lane < nb && record_misses(next, wr));
         stage(slice, next, lane);
         if (bstart > lo) next = gather(rr, nid);
         const int e2 = bstart - kBatch;   // end of the batch after next
@@ -438,6 +489,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             // the next record (j - 1) is read while this one is processed
             const RasterRec r = rn;
             rn = slice[max(j - 1, 0)];
+            if ((skip >> j) & 1) continue;
             const double dy = (double)r.my - ps.pyd;
             const double dx0 = (double)r.mx - ps.px0;
             const double bdy = r.B * dy;
