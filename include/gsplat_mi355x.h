@@ -103,10 +103,12 @@ typedef struct gs_gaussians {
  *   rec[p*12 + 9]     depth t_z
  *   rec[p*12 + 10]    scene Gaussian index (int32 bits)
  *   rec[p*12 + 11]    camera index (int32 bits)
- * mu', Y and depth are computed in float64 and rounded once to float32.
+ * mu', Y and depth are computed in float64 and rounded once to float32. rec is an optional
+ * output (NULL: not written): no later step reads it; it states the projection's result in
+ * the paper's terms, for inspection and tests.
  */
 typedef struct gs_splats {
-    float *rec;              /* [P][12], 16-byte aligned */
+    float *rec;              /* [P][12], 16-byte aligned, or NULL */
     float *raster;           /* [P][16], 64-byte aligned: compositing record written by gs_project and
                                 read by the rasterizer; its layout is private to the library */
     float *depth;            /* [P] t_z (not written for a culled slot) */
@@ -222,8 +224,8 @@ int gs_l2_grad(const float *image, const float *target, int64_t n, float *dL_dim
  * tile [0, n_splats). out: splat buffers of capacity >= n_splats; tiles_touched is written
  * for every slot, the other fields only for slots with tiles_touched > 0 (a culled slot's
  * record, depth and box are left as they were).
- * Errors: GS_ERR_INVALID for null pointers, n_cams < 1, n_splats < 0 or
- * n_splats > out->capacity.
+ * Errors: GS_ERR_INVALID for null pointers (other than out->rec), n_cams < 1,
+ * n_splats < 0 or n_splats > out->capacity.
  */
 int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
                gs_splats *out, void *stream);

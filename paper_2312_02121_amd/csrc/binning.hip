@@ -1159,15 +1159,19 @@ __device__ inline int sched_len(const int32_t *__restrict__ ranges, const int32_
     return walk >= 1 && walk < len ? walk : len;
 }
 
-// Per-block bucket histogram in LDS, then one global atomic per non-empty bucket.
-__global__ __launch_bounds__(256) void sched_count_kernel(const int32_t *__restrict__ ranges, int n_tiles,
-                                                          int split_len, int split_items, int32_t *__restrict__ sched)
+// Per-block bucket histogram in LDS, then one global atomic per non-empty bucket. When the
+// sort's error word is set (a wait gave up, or the counts disagree) the ranges are emptied
+// first, whatever wrote them: nothing reads the list.
+__global__ __launch_bounds__(256) void sched_count_kernel(int32_t *__restrict__ ranges, int n_tiles, int split_len,
+                                                          int split_items, int32_t *__restrict__ sched,
+                                                          const int64_t *__restrict__ err)
 {
     __shared__ int cnt[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_tiles) {
+        if (err && *err) ranges[2 * t] = ranges[2 * t + 1] = 0;
         const int len = sched_len(ranges, sched, n_tiles, t);
         atomicAdd(&cnt[length_bucket(len)], len >= split_len ? split_items : 1);
     }
@@ -1330,7 +1334,7 @@ static int build_schedule(gs_bins *bins, const int64_t *err, hipStream_t st)
     hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule, bins->counters, err);
     const gs_tuning &tu = current_tuning();
     hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
-                       tu.split_parts * tu.bwd_segs, bins->schedule);
+                       tu.split_parts * tu.bwd_segs, bins->schedule, err);
     hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
                        tu.split_parts, tu.bwd_segs, bins->schedule);
     return check_launch("gs_bin_and_sort");

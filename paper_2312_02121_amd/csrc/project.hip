@@ -127,9 +127,11 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     // a culled slot (tiles_touched = 0) is never listed, so only its count is written
     tiles_out[p] = tiles;
     if (tiles > 0) {
-        rec[3 * p + 0] = r0;
-        rec[3 * p + 1] = r1;
-        rec[3 * p + 2] = r2;
+        if (rec) {   // optional output, uniform
+            rec[3 * p + 0] = r0;
+            rec[3 * p + 1] = r1;
+            rec[3 * p + 2] = r2;
+        }
         rrec[p] = rr;
         depth_out[p] = dep;
         rect_out[p] = box;
@@ -149,8 +151,8 @@ extern "C" int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t 
     if (n_splats > out->capacity)
         return set_error(GS_ERR_INVALID, "gs_project: n_splats exceeds splat capacity");
     if (n_splats == 0) return GS_OK;
-    if (!g->means || !g->quats || !g->scales || !g->colors || !g->opacities || g->n < 1 || !out->rec ||
-        !out->raster || !out->depth || !out->rect || !out->tiles_touched)
+    if (!g->means || !g->quats || !g->scales || !g->colors || !g->opacities || g->n < 1 || !out->raster ||
+        !out->depth || !out->rect || !out->tiles_touched)
         return set_error(GS_ERR_INVALID, "gs_project: null plane");
     if ((((uintptr_t)out->rec) & 15) || (((uintptr_t)out->rect) & 15) || (((uintptr_t)out->raster) & 63))
         return set_error(GS_ERR_INVALID, "gs_project: rec/rect must be 16-byte and raster 64-byte aligned");

@@ -223,7 +223,7 @@ extern "C" int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int3
 {
     clear_error();
     if (!g || !cams || !s || n_cams < 1 || n_splats < 0 || n_splats > s->capacity || !dL_dmean2d || !dL_dconic ||
-        !dL_dmeans || !dL_dscales || !dL_dquats || !s->rec || !s->tiles_touched)
+        !dL_dmeans || !dL_dscales || !dL_dquats || !s->tiles_touched)
         return set_error(GS_ERR_INVALID, "gs_project_bwd: null argument or bad size");
     if (!g->means || !g->quats || !g->scales || g->n < 1)
         return set_error(GS_ERR_INVALID, "gs_project_bwd: null Gaussian plane");

@@ -141,16 +141,18 @@ class GaussianSet:
 
 @dataclass
 class Splats:
-    rec: torch.Tensor
+    rec: torch.Tensor | None
     raster: torch.Tensor
     depth: torch.Tensor
     rect: torch.Tensor
     tiles: torch.Tensor
 
     @staticmethod
-    def alloc(P: int, device) -> "Splats":
+    def alloc(P: int, device, records: bool = False) -> "Splats":
+        """records: also keep gs_project's 12-float records (an optional output that no later
+        step reads; tests compare it with the oracle's projection)."""
         P1 = max(P, 1)
-        return Splats(torch.empty(P1 * abi.REC_FLOATS, dtype=torch.float32, device=device),
+        return Splats(torch.empty(P1 * abi.REC_FLOATS, dtype=torch.float32, device=device) if records else None,
                       torch.empty(P1 * abi.RASTER_FLOATS, dtype=torch.float32, device=device),
                       torch.empty(P1, dtype=torch.float32, device=device),
                       torch.empty(P1 * 4, dtype=torch.int32, device=device),
@@ -207,12 +209,12 @@ class Rasterizer:
     """Reusable buffers for one (GaussianSet layout, CameraSet) pair."""
 
     def __init__(self, cams: CameraSet, params: abi.GsParams | None = None, capacity: int | None = None,
-                 keep_visited: bool = False):
+                 keep_visited: bool = False, keep_records: bool = False):
         self.cams = cams
         self.params = params or make_params()
         self.device = cams.device
         P = cams.n_splats
-        self.splats = Splats.alloc(P, self.device)
+        self.splats = Splats.alloc(P, self.device, keep_records)
         self.capacity = int(capacity) if capacity else max(4 * P, 1024)
         self.bins = Bins.alloc(P, self.capacity, cams.n_tiles, self.device)
         npx = cams.n_pixels
@@ -309,10 +311,10 @@ class TrainStep:
 
     def __init__(self, g: GaussianSet, cams: CameraSet, targets: torch.Tensor, params: abi.GsParams | None = None,
                  capacity: int | None = None, capacity_margin: float = 1.25, mode: str = "separate",
-                 keep_image: bool = True, scene_grads: "TrainStep | None" = None):
+                 keep_image: bool = True, scene_grads: "TrainStep | None" = None, keep_records: bool = False):
         self.g, self.cams, self.mode = g, cams, mode
         self.STAGES = self.STAGE_SETS[mode]
-        self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True)
+        self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True, keep_records=keep_records)
         self.targets = targets.contiguous().view(3, -1).to(torch.float32)
         assert self.targets.shape[1] == cams.n_pixels
         st = self.r.forward(g)                      # sizes the list capacity

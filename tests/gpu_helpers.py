@@ -31,7 +31,7 @@ def gpu_forward(wl, keep_visited=True, capacity=None):
     from paper_2312_02121_amd import pipeline
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
-    r = pipeline.Rasterizer(cams, capacity=capacity, keep_visited=keep_visited)
+    r = pipeline.Rasterizer(cams, capacity=capacity, keep_visited=keep_visited, keep_records=True)
     st = r.forward(g)
     torch.cuda.synchronize()
     return r, st

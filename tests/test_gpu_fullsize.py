@@ -41,7 +41,7 @@ def graph_step(wl):
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
-    step = pipeline.TrainStep(g, cams, tgt, mode="fused")
+    step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_records=True)
     tuned = autotune.tune(step, steps=2, warmup=1, cache_path=autotune.DEFAULT_CACHE)
     print(f"autotuned: {tuned['tuning']}")
     graph = pipeline.GraphStep(step)
