@@ -217,6 +217,21 @@ def test_deterministic_lists_and_image():
     assert torch.equal(keys, r2.bins.keys[: st2.K]) and torch.equal(img, st2.image)
 
 
+def test_projection_record_is_optional():
+    # without gs_project's 12-float record (rec = NULL) the list and the image are the same
+    _print_case("optional record", wl="c2_20k")
+    from paper_2312_02121_amd import pipeline
+    wl = wl_cache()["c2_20k"]
+    r, st = gpu_forward(wl)
+    g = pipeline.GaussianSet(wl.scenes)
+    r2 = pipeline.Rasterizer(pipeline.CameraSet(wl.cameras, g.sizes), keep_records=False)
+    assert r2.splats.rec is None
+    st2 = r2.forward(g)
+    torch.cuda.synchronize()
+    assert st2.K == st.K
+    assert torch.equal(r.bins.keys[: st.K], r2.bins.keys[: st2.K]) and torch.equal(st.image, st2.image)
+
+
 def test_edge_cases():
     _print_case("edges", wl="edge")
     # everything behind the camera or outside the image: K = 0, empty image
