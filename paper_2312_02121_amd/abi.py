@@ -83,7 +83,8 @@ def expected_layout() -> list[int]:
             f["tile_offset"][1], f["tiles_y"][1],
             ctypes.sizeof(GsGaussians), GsGaussians.n.offset,
             ctypes.sizeof(GsSplats), GsSplats.capacity.offset,
-            ctypes.sizeof(GsParams), ctypes.sizeof(GsBins), GsBins.capacity.offset, GsBins.n_tiles.offset]
+            ctypes.sizeof(GsParams), ctypes.sizeof(GsBins), GsBins.capacity.offset, GsBins.n_tiles.offset,
+            ctypes.sizeof(GsTuning), GsTuning.bwd_segs.offset, GsTuning.atomic_lanes.offset]
 
 
 # --------------------------------------------------------------------------- loading

@@ -123,7 +123,8 @@ extern "C" int gs_abi_layout(int64_t *out, int n)
         (int64_t)sizeof(gs_gaussians), (int64_t)offsetof(gs_gaussians, n),
         (int64_t)sizeof(gs_splats), (int64_t)offsetof(gs_splats, capacity),
         (int64_t)sizeof(gs_params), (int64_t)sizeof(gs_bins), (int64_t)offsetof(gs_bins, capacity),
-        (int64_t)offsetof(gs_bins, n_tiles)};
+        (int64_t)offsetof(gs_bins, n_tiles), (int64_t)sizeof(gs_tuning), (int64_t)offsetof(gs_tuning, bwd_segs),
+        (int64_t)offsetof(gs_tuning, atomic_lanes)};
     const int m = (int)(sizeof(v) / sizeof(v[0]));
     for (int k = 0; k < n && k < m; ++k) out[k] = v[k];
     return m;
