@@ -37,12 +37,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# What the fused kernel's code and launch depend on: its source, the shared device header, the
+# C-ABI header and the recorded launch tuning. A change to any of them makes the committed
+# traffic summary stale.
+FUSED_KERNEL_INPUTS = ("paper_2312_02121_amd/csrc/raster.hip", "paper_2312_02121_amd/csrc/common.h",
+                       "include/gsplat_mi355x.h", "paper_2312_02121_amd/tuned.json")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2312_02121_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode() + fh.read())
+    for rel in FUSED_KERNEL_INPUTS:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
