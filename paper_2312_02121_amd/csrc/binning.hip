@@ -24,17 +24,19 @@
 // views with near-plane splats (hundreds of millions of entries) the sort is HBM-bound and
 // the difference is the whole cost.
 //
-// The compaction, the offset scan and every sort pass are single-pass launches with
-// decoupled look-back: each block publishes its chunk's count(s), sums its predecessors'
-// published counts for its global offsets (waiting, with a spin limit, on any predecessor
-// that has not published yet) and writes its part. A sort pass ranks its chunk, stages it
-// in LDS in digit order and writes it out in runs; the digit counts of all its passes come
-// from one earlier read of the keys.
-// Block ranking uses wave ballots to group equal digits and LDS counters per (wave,
-// digit), so no LDS atomics contend on popular digits. Every kernel is sized from
-// host-known capacities and reads its element count from device memory, and the
-// look-back state is cleared by a kernel at the start of each call, so the whole sequence
-// replays unchanged inside a captured HIP graph.
+// Every sort pass and the range scan are single-pass launches with decoupled look-back:
+// each block publishes its chunk's count(s), sums its predecessors' published counts for
+// its global offsets (waiting, with a spin limit, on any predecessor that has not published
+// yet) and writes its part. A sort pass ranks its chunk, stages it in LDS in digit order and
+// writes it out in runs; the digit counts of all its passes come from one earlier read of
+// the keys. The compaction and the emit-offset scan are three launches each in which no
+// block waits on another (counts, a one-block scan, writes).
+// Block ranking groups equal digits of a row of 64 keys with wave ballots; one leader lane
+// per group adds the group's size to an LDS counter per (wave, digit), so atomics on a
+// popular digit do not contend across lanes. Every kernel is sized from host-known
+// capacities and reads its element count from device memory, and the look-back state is
+// cleared by a kernel at the start of each call, so the whole sequence replays unchanged
+// inside a captured HIP graph.
 #include <mutex>
 
 #include "common.h"
@@ -162,7 +164,9 @@ constexpr int kSpinLimit = 1 << 20;   // bounded wait: a predecessor that never 
 // once: block g takes chunks g, g + G, g + 2G, ... (G = gridDim.x) in turn. A chunk only
 // waits on lower chunks, which are held by running blocks, so every wait ends without a
 // global ticket counter (one atomic per chunk on a single address, which serialises the
-// launch on this device). Called at the top of each turn: returns true when an earlier
+// launch on this device). The grid fills the GPU when the chunks outnumber it, so nothing
+// may run beside such a launch: a concurrent kernel would hold back some of its blocks while
+// the others wait on their chunks. Called at the top of each turn: returns true when an earlier
 // step of the sequence gave up (the error word is set); the block then stops.
 __device__ inline bool chunk_stop(const int64_t *err_flag, int *sh_flag)
 {
