@@ -1101,12 +1101,14 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
 }
 
 // Zeroes a[0, na) and b[0, nb) in one launch (grid-stride; consecutive threads take
-// consecutive words).
+// consecutive words), and the work-list header except its walk stamp.
 __global__ __launch_bounds__(256) void zero_pair_kernel(int32_t *__restrict__ a, int64_t na, int32_t *__restrict__ b,
-                                                        int64_t nb)
+                                                        int64_t nb, int32_t *__restrict__ sched)
 {
     const int64_t n = na + nb, step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (first < kSchedHeader && first != kSchedWalkStamp) sched[first] = 0;
+    for (int64_t i = first; i < n; i += step) {
         if (i < na) a[i] = 0;
         else b[i - na] = 0;
     }
@@ -1142,16 +1144,6 @@ __device__ inline int length_bucket(int len)
 }
 
 // Clears the header, except the walk-length stamp.
-// Clears the work-list header (keeping the walk stamp) and folds the sort's error word, when
-// there is one, into the flags (2: a look-back wait gave up or the counts disagree; 4: a
-// camera wider than the count array).
-__global__ __launch_bounds__(64) void sched_clear_kernel(int32_t *__restrict__ sched, int64_t *__restrict__ counters,
-                                                         const int64_t *__restrict__ err)
-{
-    if (threadIdx.x != kSchedWalkStamp) sched[threadIdx.x] = 0;
-    if (threadIdx.x == 0 && err && *err) counters[1] |= *err;
-}
-
 // The length a tile is scheduled by: its list length, or the walk length of the last
 // rasterization when recorded for this tile count (and not longer than the list).
 __device__ inline int sched_len(const int32_t *__restrict__ ranges, const int32_t *__restrict__ sched, int n_tiles,
@@ -1163,17 +1155,21 @@ __device__ inline int sched_len(const int32_t *__restrict__ ranges, const int32_
     return walk >= 1 && walk < len ? walk : len;
 }
 
-// Per-block bucket histogram in LDS, then one global atomic per non-empty bucket. When the
-// sort's error word is set (a wait gave up, or the counts disagree) the ranges are emptied
-// first, whatever wrote them: nothing reads the list.
+// Per-block bucket histogram in LDS, then one global atomic per non-empty bucket (the header
+// was zeroed at the start of the call). When the sort's error word is set (a wait gave up, or
+// the counts disagree) the ranges are emptied first, whatever wrote them, so nothing reads
+// the list, and the word joins the flags (2: the list is invalid; 4: a camera wider than the
+// count array).
 __global__ __launch_bounds__(256) void sched_count_kernel(int32_t *__restrict__ ranges, int n_tiles, int split_len,
                                                           int split_items, int32_t *__restrict__ sched,
-                                                          const int64_t *__restrict__ err)
+                                                          const int64_t *__restrict__ err,
+                                                          int64_t *__restrict__ counters)
 {
     __shared__ int cnt[kSchedNumBuckets];
     if (threadIdx.x < kSchedNumBuckets) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && err && *err) counters[1] |= *err;
     if (t < n_tiles) {
         if (err && *err) ranges[2 * t] = ranges[2 * t + 1] = 0;
         const int len = sched_len(ranges, sched, n_tiles, t);
@@ -1332,13 +1328,14 @@ static unsigned resident_grid(const void *kernel, int block, int64_t chunks)
 
 using namespace gsx;
 
+// The work list (its header was zeroed at the start of the call); the sort's error word
+// joins the flags.
 static int build_schedule(gs_bins *bins, const int64_t *err, hipStream_t st)
 {
     const unsigned g = grid_for(bins->n_tiles, 256);
-    hipLaunchKernelGGL(sched_clear_kernel, dim3(1), dim3(kSchedHeader), 0, st, bins->schedule, bins->counters, err);
     const gs_tuning &tu = current_tuning();
     hipLaunchKernelGGL(sched_count_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
-                       tu.split_parts * tu.bwd_segs, bins->schedule, err);
+                       tu.split_parts * tu.bwd_segs, bins->schedule, err, bins->counters);
     hipLaunchKernelGGL(sched_fill_kernel, dim3(g), dim3(256), 0, st, bins->ranges, bins->n_tiles, tu.split_len,
                        tu.split_parts, tu.bwd_segs, bins->schedule);
     return check_launch("gs_bin_and_sort");
@@ -1390,16 +1387,16 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
 
-    // ranges start empty, (0, 0); the look-back state, counts and histograms start at zero
+    // ranges start empty, (0, 0); the look-back state, counts, histograms and the work-list header start at zero
     if (n_splats == 0) {
         hipLaunchKernelGGL(zero_pair_kernel, dim3(grid_for(2ll * bins->n_tiles, 256)), dim3(256), 0, st,
-                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)bins->counters, (int64_t)4);
+                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)bins->counters, (int64_t)4, bins->schedule);
         return build_schedule(bins, (const int64_t *)nullptr, st);
     }
     {
         const int64_t nz = (int64_t)((L.total - L.zero_begin) / 4), n = 2ll * bins->n_tiles + nz;
         hipLaunchKernelGGL(zero_pair_kernel, dim3((unsigned)min(grid_for(n, 256), 4096u)), dim3(256), 0, st,
-                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)(ws + L.zero_begin), nz);
+                           bins->ranges, 2ll * bins->n_tiles, (int32_t *)(ws + L.zero_begin), nz, bins->schedule);
     }
     int rc = GS_OK;
 
@@ -1509,6 +1506,6 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
                        dim3(kSortBlock), 0, st, (const int32_t *)tile_cnt, bins->n_tiles, K, cap, stat_ranges,
                        bins->ranges, err);
 
-    // 6. the work list; the sort's error word joins the overflow flag
+    // 6. the work list
     return build_schedule(bins, (const int64_t *)err, st);
 }
