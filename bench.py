@@ -123,8 +123,10 @@ def e_dense(step) -> int:
 
 def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
     """One fused persistent launch sequence over every camera, captured in a HIP graph, against
-    the same kernels run one view per launch sequence with no graph. Each form gets its own
-    autotuned launch tuning (the search runs before the timed region)."""
+    the same kernels run one view per launch sequence with no graph (speedup), and against the
+    conventional per-view pipeline with separate forward, loss-gradient and backward launches
+    (speedup_vs_separate). Each form gets its own autotuned launch tuning (the search runs
+    before the timed region)."""
     import numpy as np
     import torch
     from paper_2312_02121_amd import autotune, pipeline, synth
@@ -142,19 +144,25 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
     del graph, step
     torch.cuda.empty_cache()
     targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
-    per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
-    tv = (autotune.tune_callable("per_view:" + autotune.signature_of(g, cams, K), per_view,
-                                 cache_path=autotune.DEFAULT_CACHE) if tune else None)
-    ms_v = time_steps(per_view, steps, warmup)
-    del per_view
-    torch.cuda.empty_cache()
+    per_view_ms, per_view_tuning = {}, {}
+    for mode in ("fused", "separate"):
+        per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode=mode)
+        tv = (autotune.tune_callable(autotune.per_view_key(mode, g, cams, K), per_view,
+                                     cache_path=autotune.DEFAULT_CACHE) if tune else None)
+        per_view_ms[mode] = time_steps(per_view, steps, warmup)
+        per_view_tuning[mode] = tv["tuning"] if tv else None
+        del per_view
+        torch.cuda.empty_cache()
     autotune.apply(autotune.default_tuning())
-    log(f"config {cfg}: batched {ms_b:.3f} ms, per-view {ms_v:.3f} ms")
+    ms_v, ms_s = per_view_ms["fused"], per_view_ms["separate"]
+    log(f"config {cfg}: batched {ms_b:.3f} ms, per-view {ms_v:.3f} ms (separate launches {ms_s:.3f} ms)")
     return {"workload": wl.name, "views": cams.n_cams, "n_gaussians": g.n, "E_fwd": E,
             "batched_ms_per_step": ms_b, "per_view_ms_per_step": ms_v,
             "batched_evals_per_s": E / (ms_b * 1e-3), "per_view_evals_per_s": E / (ms_v * 1e-3),
             "speedup": ms_v / ms_b, "batched_ms_per_view": ms_b / cams.n_cams,
-            "batched_tuning": tb["tuning"] if tb else None, "per_view_tuning": tv["tuning"] if tv else None}
+            "per_view_separate_ms_per_step": ms_s, "speedup_vs_separate": ms_s / ms_b,
+            "batched_tuning": tb["tuning"] if tb else None, "per_view_tuning": per_view_tuning["fused"],
+            "per_view_separate_tuning": per_view_tuning["separate"]}
 
 
 def autograd_ms(wl, steps: int, warmup: int) -> float:

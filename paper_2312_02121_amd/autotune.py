@@ -83,6 +83,12 @@ def signature(step) -> str:
     return signature_of(step.g, step.cams, step.K)
 
 
+def per_view_key(mode: str, g, cams, K: int) -> str:
+    """Cache key of the one-view-per-launch form (PerViewSteps) of a batched workload: the
+    fused kernels per view, or the conventional separate forward and backward launches."""
+    return ("per_view:" if mode == "separate" else f"per_view_{mode}:") + signature_of(g, cams, K)
+
+
 def _time_graph(step, steps: int, warmup: int, repeats: int = 3) -> float:
     """Mean ms per replay of the step captured as a graph: the best of `repeats` runs of
     `steps` replays (run-to-run noise on a shared GPU is one-sided)."""
@@ -236,17 +242,20 @@ def main():
         res = tune(step, cache_path=args.out, update_cache=True, log=print)
         print(f"c{cfg}: {res['tuning']} {res['default_ms']:.4f} -> {res['ms']:.4f} ms", flush=True)
         if args.per_view:
+            K = step.K
             del step
             torch.cuda.empty_cache()
             targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
-            per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode="separate")
-            pkey = "per_view:" + key
-            cache = _load(args.out)
-            cache.pop(pkey, None)
-            _store(args.out, cache)
-            res = tune_callable(pkey, per_view, cache_path=args.out, update_cache=True, log=print)
-            print(f"c{cfg} per view: {res['tuning']} {res['default_ms']:.4f} -> {res['ms']:.4f} ms", flush=True)
-            del per_view
+            for mode in ("fused", "separate"):
+                per_view = pipeline.PerViewSteps(g, wl.cameras, targets, mode=mode)
+                pkey = per_view_key(mode, g, cams, K)
+                cache = _load(args.out)
+                cache.pop(pkey, None)
+                _store(args.out, cache)
+                res = tune_callable(pkey, per_view, cache_path=args.out, update_cache=True, log=print)
+                print(f"c{cfg} per view ({mode}): {res['tuning']} {res['default_ms']:.4f} -> {res['ms']:.4f} ms",
+                      flush=True)
+                del per_view
         torch.cuda.empty_cache()
     apply(default_tuning())
 
