@@ -76,13 +76,57 @@ __device__ inline Gathered gather(const RasterRec *__restrict__ rr, int id)
     return g;
 }
 
-__device__ inline void stage(RasterRec *slice, const Gathered &g, int lane)
+// Entries a walk goes through per group: the walks run over whole groups, the all-finished
+// test of the forward is made between groups, and the staged batch is padded to a multiple.
+constexpr int kGroup = 8;
+
+// Backward: lane j's record goes to slot j.
+__device__ inline void stage_all(RasterRec *slice, const Gathered &g, int lane)
 {
     float4 *d = (float4 *)(slice + lane);
     d[0] = g.q0;
     d[1] = g.q1;
     d[2] = g.q2;
     d[3] = g.q3;
+}
+
+// Forward: stages the lanes' gathered records selected by `keep` (a lane mask) into the slice,
+// packed in lane order: the record of the k-th selected lane goes to slot k. The staged copy
+// carries, in place of o (which compositing does not use), the record's list position plus
+// one (p1 of the lane, an int). Slots from the number kept up to the next multiple of kGroup
+// receive a null record (alpha 0 at every pixel, colour 0, position 0): a walk step over it
+// changes nothing. Returns the number of slots to walk (kept records plus padding).
+__device__ inline int stage_packed(RasterRec *slice, const Gathered &g, uint64_t keep, int lane, int p1)
+{
+    const int nk = __popcll(keep);
+    const int np = (nk + kGroup - 1) & ~(kGroup - 1);
+    if ((keep >> lane) & 1) {
+        const int k = __builtin_amdgcn_mbcnt_hi((unsigned)(keep >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)keep, 0u));
+        float4 *d = (float4 *)(slice + k);
+        d[0] = g.q0;
+        d[1] = g.q1;
+        d[2] = g.q2;
+        d[3] = make_float4(g.q3.x, __int_as_float(p1), g.q3.z, g.q3.w);
+    }
+    if (lane >= nk && lane < np) {
+        // lo = -1e30 with A = B = C = 0 gives an exponent of -1e30 (finite) and alpha = exp2 = 0
+        RasterRec z;
+        z.mx = z.my = 0.f;
+        z.lo = -1e30;
+        z.A = z.B = z.C = 0.0;
+        z.c0 = z.c1 = z.c2 = 0.f;
+        z.o = __int_as_float(0);
+        z.src = z.slot = 0;
+        slice[lane] = z;
+    }
+    return np;
+}
+
+// List position plus one of a staged record (stored in place of o); wave-uniform, since every
+// lane reads the same slot.
+__device__ __forceinline__ int staged_p1(const RasterRec &r)
+{
+    return __builtin_amdgcn_readfirstlane(__float_as_int(r.o));
 }
 
 struct ItemPixels {
@@ -154,17 +198,25 @@ __device__ inline WaveRect wave_rect(const ItemPixels &t, const gs_params &prm)
 // k = lo - thr and D = 4AC - B^2; the record is skipped when k < 0 or that box, widened by a
 // relative 2^-20 and an absolute 2^-20, misses the rectangle. Records whose D carries more
 // than 2^-20 relative cancellation, and any NaN, are kept.
+// A float64 field of the gathered record from its two 32-bit halves (low word first).
+__device__ __forceinline__ double rec_f64(float lo_word, float hi_word)
+{
+    return __hiloint2double(__float_as_int(hi_word), __float_as_int(lo_word));
+}
+
 __device__ inline bool record_misses(const Gathered &g, const WaveRect &w)
 {
-    RasterRec r;
-    __builtin_memcpy(&r, &g, sizeof(RasterRec));
-    const double k = r.lo - w.thr;
+    // the fields are taken from the registers directly (RasterRec layout: mx, my, lo in q0;
+    // A, B in q1; C in q2), so no copy of the record is made in memory
+    const double lo = rec_f64(g.q0.z, g.q0.w), A = rec_f64(g.q1.x, g.q1.y), B = rec_f64(g.q1.z, g.q1.w),
+                 C = rec_f64(g.q2.x, g.q2.y);
+    const double k = lo - w.thr;
     if (k < 0.0) return true;
-    const double ac4 = 4.0 * r.A * r.C, bb = r.B * r.B, D = ac4 - bb;
+    const double ac4 = 4.0 * A * C, bb = B * B, D = ac4 - bb;
     if (!(D * 0x1p20 > ac4 + bb)) return false;
-    const double sx = sqrt(k * (-4.0 * r.C) / D) * (1.0 + 0x1p-20) + 0x1p-20;
-    const double sy = sqrt(k * (-4.0 * r.A) / D) * (1.0 + 0x1p-20) + 0x1p-20;
-    const double mx = r.mx, my = r.my;
+    const double sx = sqrt(k * (-4.0 * C) / D) * (1.0 + 0x1p-20) + 0x1p-20;
+    const double sy = sqrt(k * (-4.0 * A) / D) * (1.0 + 0x1p-20) + 0x1p-20;
+    const double mx = g.q0.x, my = g.q0.y;
     return mx + sx < w.x_lo || mx - sx > w.x_hi || my + sy < w.y_lo || my - sy > w.y_hi;
 }
 
@@ -298,9 +350,10 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             snapped = true;
         }
         const int nb = min(kBatch, t.end - b);
-        // the counting pass (kVisited) counts every pair it reaches
-        const uint64_t skip = kVisited ? 0ull : __ballot(lane < nb && record_misses(next, wr));
-        stage(slice, next, lane);
+        // records that miss the wave are left out of the staged batch; the counting pass
+        // (kVisited) counts every pair it reaches and keeps them all
+        const uint64_t keep = __ballot(lane < nb && (kVisited || !record_misses(next, wr)));
+        const int np = stage_packed(slice, next, keep, lane, b - t.start + lane + 1);
         if (b + kBatch < t.end) next = gather(rr, nid);
         if (b + 2 * kBatch < t.end) nid = load_ids(ids, b + 2 * kBatch, t.end - b - 2 * kBatch, lane);
         float tmax = ps.T[0];
@@ -310,34 +363,35 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             walked = b - t.start;
             break;
         }
-        // groups of 8 entries, with the all-finished test between groups, so that the inner
-        // loop has a single exit
-        for (int j0 = 0; j0 < nb; j0 += 8) {
+        // whole groups of staged slots, straight-line code inside a group (constant LDS
+        // offsets, no per-entry branch), with the all-finished test between groups
+        RasterRec rn = slice[0];
+        for (int j0 = 0; j0 < np; j0 += kGroup) {
             if (j0 > 0) {
                 float m = ps.T[0];
 #pragma unroll
                 for (int q = 1; q < PX; ++q) m = fmaxf(m, ps.T[q]);
                 if (__ballot(m >= 0.f) == 0) break;
             }
-            const int j1 = min(j0 + 8, nb);
-            RasterRec rn = slice[j0];
-#pragma unroll 2
-            for (int j = j0; j < j1; ++j) {
-            // the next record is read while this one is composited (index kept inside the slice)
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+            // the next record is read while this one is composited, and no further: the
+            // barrier lets only VALU and SALU work move across it, so later LDS reads are not
+            // hoisted (two records in registers at most)
             const RasterRec r = rn;
-            rn = slice[min(j + 1, kBatch - 1)];
-            if ((skip >> j) & 1) continue;
+            rn = slice[j < kGroup - 1 ? j0 + j + 1 : min(j0 + kGroup, kBatch - 1)];
+            __builtin_amdgcn_sched_barrier(0x0006);
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
             const double cdl = __builtin_fma(r.C * dy, dy, r.lo);
             const double dx0 = (double)r.mx - ps.px0;
-            const int pos1 = b + j - t.start + 1;
+            const int pos1 = staged_p1(r);
 #pragma unroll
             for (int q = 0; q < PX; ++q) {
                 const double dx = dx0 - (double)q;   // exact: both sides are small binary fractions
                 float a = __builtin_amdgcn_fmed3f(alpha_raw(r, dx, bdy, cdl), 0.f, prm.alpha_max);
                 a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
-                if (kVisited) ps.vis[q] += ps.T[q] >= 0.f ? 1 : 0;
+                if (kVisited) ps.vis[q] += (ps.T[q] >= 0.f && pos1 > 0) ? 1 : 0;   // padding not counted
                 const float Tn = ps.T[q] * (1.f - a);
                 const bool stop = Tn < prm.T_min;                // also true once finished (T < 0)
                 const float w = stop ? 0.f : a * ps.T[q];
@@ -486,7 +540,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         const int bstart = max(lo, bend - kBatch);
         const int nb = bend - bstart;
         const uint64_t skip = __ballot(lane < nb && record_misses(next, wr));
-        stage(slice, next, lane);
+        stage_all(slice, next, lane);
         if (bstart > lo) next = gather(rr, nid);
         const int e2 = bstart - kBatch;   // end of the batch after next
         if (e2 > lo) {
