@@ -80,19 +80,9 @@ __device__ inline Gathered gather(const RasterRec *__restrict__ rr, int id)
 // test of the forward is made between groups, and the staged batch is padded to a multiple.
 constexpr int kGroup = 8;
 
-// Backward: lane j's record goes to slot j.
-__device__ inline void stage_all(RasterRec *slice, const Gathered &g, int lane)
-{
-    float4 *d = (float4 *)(slice + lane);
-    d[0] = g.q0;
-    d[1] = g.q1;
-    d[2] = g.q2;
-    d[3] = g.q3;
-}
-
-// Forward: stages the lanes' gathered records selected by `keep` (a lane mask) into the slice,
+// Stages the lanes' gathered records selected by `keep` (a lane mask) into the slice,
 // packed in lane order: the record of the k-th selected lane goes to slot k. The staged copy
-// carries, in place of o (which compositing does not use), the record's list position plus
+// carries, in place of o (which the walks do not read), the record's list position plus
 // one (p1 of the lane, an int). Slots from the number kept up to the next multiple of kGroup
 // receive a null record (alpha 0 at every pixel, colour 0, position 0): a walk step over it
 // changes nothing. Returns the number of slots to walk (kept records plus padding).
@@ -473,15 +463,18 @@ __device__ inline void lds_add(float *p, float v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Lane j < nb moves slot j (the splat of staged record j) to the global gradients and
-// clears it:
+// Lane j < nk (the staged records) moves slot j (the splat of staged record j) to the global
+// gradients and clears it:
 //   dL/dmu' = -Y sum v Delta, with Y = -(2A, B; B, 2C) / log2(e)
 //   dL/dY = -1/2 sum v Delta Delta^T,  dL/dc(k) = sum alpha T dL/dC(k),  dL/do = sum v / o
-__device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nb, int lane, const BwdOut &out)
+// The staged copy carries the list position in place of o, so 1/o is recovered as
+// exp2(-lo) in float32 (lo = log2(o)): a splat reaches this point only with o >= alpha_min,
+// so |lo| <= 8 for alpha_min = 1/255 and the relative error of 1/o is below 1e-6.
+__device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nk, int lane, const BwdOut &out)
 {
     // LDS operations of one wave complete in order, so the slot reads below see every add
     __builtin_amdgcn_wave_barrier();
-    if (lane < nb) {
+    if (lane < nk) {
         const double s_v = acc->d[0][lane], s_x = acc->d[1][lane], s_y = acc->d[2][lane];
         const double s_xx = acc->d[3][lane], s_xy = acc->d[4][lane], s_yy = acc->d[5][lane];
         const float s_c0 = acc->f[0][lane], s_c1 = acc->f[1][lane], s_c2 = acc->f[2][lane];
@@ -497,7 +490,7 @@ __device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nb, i
             atomic_add_f32(&out.d_colors[r.src], s_c0);
             atomic_add_f32(&out.d_colors[out.n_gauss + r.src], s_c1);
             atomic_add_f32(&out.d_colors[2 * out.n_gauss + r.src], s_c2);
-            atomic_add_f32(&out.d_opac[r.src], (float)(s_v / (double)r.o));
+            atomic_add_f32(&out.d_opac[r.src], (float)(s_v * (double)__builtin_amdgcn_exp2f(-(float)r.lo)));
         }
     }
     acc_clear(acc, lane);
@@ -539,21 +532,22 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     for (int bend = kend; bend > lo; bend -= kBatch) {
         const int bstart = max(lo, bend - kBatch);
         const int nb = bend - bstart;
-        const uint64_t skip = __ballot(lane < nb && record_misses(next, wr));
-        stage_all(slice, next, lane);
+        // records that miss the wave are left out of the staged batch
+        const uint64_t keep = __ballot(lane < nb && !record_misses(next, wr));
+        const int nk = __popcll(keep);
+        stage_packed(slice, next, keep, lane, bstart - t.start + lane + 1);
         if (bstart > lo) next = gather(rr, nid);
         const int e2 = bstart - kBatch;   // end of the batch after next
         if (e2 > lo) {
             const int s2 = max(lo, e2 - kBatch);
             nid = load_ids(ids, s2, e2 - s2, lane);
         }
-        RasterRec rn = slice[nb - 1];
-        for (int j = nb - 1; j >= 0; --j) {
-            const int pos = bstart + j - t.start;
+        RasterRec rn = slice[max(nk - 1, 0)];
+        for (int j = nk - 1; j >= 0; --j) {
             // the next record (j - 1) is read while this one is processed
             const RasterRec r = rn;
             rn = slice[max(j - 1, 0)];
-            if ((skip >> j) & 1) continue;
+            const int pos1 = staged_p1(r);
             const double dy = (double)r.my - ps.pyd;
             const double dx0 = (double)r.mx - ps.px0;
             const double bdy = r.B * dy;
@@ -572,7 +566,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 const double dx = dx0 - (double)q;
                 const float a_raw = alpha_raw(r, dx, bdy, cdl);
                 float a = __builtin_amdgcn_fmed3f(a_raw, 0.f, prm.alpha_max);
-                a = pos < ps.last[q] ? a : 0.f;
+                a = pos1 <= ps.last[q] ? a : 0.f;
                 a = a < prm.alpha_min ? 0.f : a;
                 live_sum += a;
                 const float rinv = __builtin_amdgcn_rcpf(1.f - a);
@@ -640,7 +634,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
                 }
             }
         }
-        acc_flush(slice, acc, nb, lane, out);
+        acc_flush(slice, acc, nk, lane, out);
     }
 }
 
