@@ -76,8 +76,9 @@ def tile_box_covers(rect: np.ndarray, tiles: np.ndarray, n: int, tx: np.ndarray,
 
 
 def render(mean2d, conic, depth, rect, tiles, colors, opac, width: int, height: int,
-           alpha_min: float, alpha_max: float, T_min: float) -> dict:
-    """Global-depth-order compositing; conic is [3, N] = (Y00, Y01, Y11)."""
+           alpha_min: float, alpha_max: float, T_min: float, background=(0.0, 0.0, 0.0)) -> dict:
+    """Global-depth-order compositing; conic is [3, N] = (Y00, Y01, Y11). The background
+    colour is seen through what is left of each pixel (T_final)."""
     jj, ii = np.meshgrid(np.arange(width), np.arange(height))
     px, py = jj + 0.5, ii + 0.5
     tx, ty = jj // 16, ii // 16
@@ -107,4 +108,6 @@ def render(mean2d, conic, depth, rect, tiles, colors, opac, width: int, height: 
             C[ch] = np.where(keep, C[ch] + colors[ch, n] * a * T, C[ch])
         T = np.where(keep, Tn, T)
         last = np.where(keep, count, last)
+    for ch in range(3):
+        C[ch] = C[ch] + T * background[ch]
     return {"C": C, "T_final": T, "last": last}

@@ -34,6 +34,11 @@
  *     stored 2x2 conic gradient is the (0,1) entry, not doubled.
  *   - camera-pose gradient: eq. (28) accounts for T_cw through t only; R_cw also
  *     enters Sigma' through T = J R_cw, and that term is added.
+ *   - background: the image formation of Sec. 2.2 has none (a background of zero).
+ *     As an option, a colour bg is seen through what is left of the pixel:
+ *     C = sum_n c_n alpha_n T_n + T_final bg. In the backward bg acts as one more
+ *     colour behind the last composited entry, with weight T_final, so it enters
+ *     S(n) of eq. (18) for every entry.
  *
  * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
  */
@@ -76,6 +81,7 @@ typedef struct {
     int32_t errata;
     int32_t n_threads;     /* <= 0: OpenMP default */
     int32_t pad;
+    double background[3];  /* bg, zero for the paper's image formation */
 } orc_params;
 
 /* ------------------------------------------------------------------ small linear algebra */
@@ -419,7 +425,9 @@ void orc_rasterize_fwd(int64_t N, const double *mean2d, const double *conic, con
                 T = Tn;
                 nlast = (int32_t)(k - start + 1);
             }
-            C[pix] = c0; C[HW + pix] = c1; C[2 * HW + pix] = c2;
+            C[pix] = c0 + T * prm->background[0];
+            C[HW + pix] = c1 + T * prm->background[1];
+            C[2 * HW + pix] = c2 + T * prm->background[2];
             T_final[pix] = T;
             last[pix] = nlast;
             if (visited) visited[pix] = nvis;
@@ -443,8 +451,10 @@ static void pixel_backward(int64_t N, const double *mean2d, const double *conic,
                            int form, double *g9)
 {
     const int delta_flip = (prm->errata & ORC_ERRATA_DELTA) != 0;
+    const double *bg = prm->background;
     if (form == 0) {
-        double T = T_fin, gS = 0.0;
+        /* the background is the colour behind the last entry, seen with weight T_final */
+        double T = T_fin, gS = (g[0] * bg[0] + g[1] * bg[1] + g[2] * bg[2]) * T_fin;
         for (int64_t k = start + nlast - 1; k >= start; --k) {
             const int32_t n = ids[k];
             const double Y3[3] = {conic[n], conic[N + n], conic[2 * N + n]};
@@ -506,7 +516,7 @@ static void pixel_backward(int64_t N, const double *mean2d, const double *conic,
         double *o = g9 + 9 * (k - start);
         double dalpha = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
-            double S = 0.0;
+            double S = bg[ch] * T;   /* T = prod over all composited entries: T_final */
             for (int64_t b = a + 1; b < m; ++b)
                 S += colors[ch * N + ids[pos[b]]] * al[6 * b] * al[6 * b + 1];
             o[5 + ch] += alpha * Tn * g[ch];

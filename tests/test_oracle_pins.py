@@ -299,6 +299,44 @@ def test_coverage_identity_and_monotone_T():
         prev = T
 
 
+
+# ------------------------------------------------- background variant (C + T_final bg)
+
+BG = (0.3, -0.2, 0.8)
+
+
+def test_background_closed_form_single_gaussian():
+    """One Gaussian over a background: C = c alpha + (1 - alpha) bg where its box covers the
+    pixel, bg elsewhere (T = 1 there)."""
+    cam = _cam(64.0, 64.0, 32.0, 32.0, 64, 64)
+    s, z, o = 0.08, 3.0, 0.7
+    scene = {"means": np.array([[0.1], [-0.05], [z]], np.float32), "quats": np.array([[1], [0], [0], [0]], np.float32),
+             "scales": np.full((3, 1), s, np.float32), "colors": np.array([[0.2], [0.5], [0.9]], np.float32),
+             "opacities": np.array([o], np.float32)}
+    out = oracle.render(scene, cam, oracle.Params.literal(round_interface=False, background=BG))
+    plain = oracle.render(scene, cam, oracle.Params.literal(round_interface=False))
+    a = 1.0 - plain["T_final"]                    # alpha of the one Gaussian (0 where not covered)
+    for ch in range(3):
+        want = np.float64(scene["colors"][ch, 0]) * a + (1.0 - a) * BG[ch]
+        assert np.abs(out["C"][ch] - want).max() < 1e-13
+    assert np.array_equal(out["T_final"], plain["T_final"])
+    far = np.all(plain["C"] == 0.0, axis=0)      # nothing composited: the background alone
+    assert far.any() and np.all(out["C"][:, far] == np.array(BG)[:, None])
+
+
+@pytest.mark.parametrize("mode", ["literal", "standard"])
+def test_background_tile_pipeline_equals_global_sort(mode):
+    wl = synth.tilted_camera_scene(27, n=40)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    prm = (oracle.Params.literal if mode == "literal" else oracle.Params.standard)(background=BG)
+    out = oracle.render(scene, cam, prm)
+    pr = out["proj"]
+    ref = brute.render(pr["mean2d"], pr["conic"], pr["depth"], pr["rect"], pr["tiles"],
+                       scene["colors"].astype(np.float64), scene["opacities"].astype(np.float64),
+                       cam.width, cam.height, prm.alpha_min, prm.alpha_max, prm.T_min, background=BG)
+    assert np.abs(out["C"] - ref["C"]).max() < 1e-12
+    assert np.array_equal(out["last"], ref["last"])
+
 # ------------------------------------------------------------------ gradients (Sec. 3)
 
 PARAM_KEYS = ("means", "quats", "scales", "colors", "opacities")
@@ -394,6 +432,39 @@ def test_division_form_equals_direct_form():
             scale = np.abs(b[k]).max()
             assert np.abs(a[k] - b[k]).max() <= 1e-11 * scale, k
 
+
+
+def test_background_gradients_match_finite_differences():
+    """The background enters the gradients of every entry through S(n): with it left out of
+    the backward (or with its sign flipped) the opacity and mean gradients miss a term
+    proportional to bg, which this check exposes."""
+    prm = oracle.Params.standard(round_interface=False, background=BG)
+    wl = synth.tiny_scene(36, n=16, log_scale=(-1.0, 0.3), opac_sd=2.0, spread=0.3)
+    worst, discont, checked = _fd_check(wl, prm)
+    assert checked > 150 and discont <= 2
+    assert worst < 2e-6, worst
+    # the same scene without the background term in the backward fails the check
+    scene = {k: v.astype(np.float64) for k, v in wl.scenes[0].items()}
+    cam = wl.cameras[0]
+    g = np.random.default_rng(0).standard_normal((3, cam.height, cam.width))
+    with_bg = oracle.render_backward(scene, cam, prm, g)
+    state = oracle.render(scene, cam, prm)
+    no_bg = oracle.render_backward(scene, cam, oracle.Params.standard(round_interface=False), g, state=state)
+    rel = np.linalg.norm(with_bg["opacities"] - no_bg["opacities"]) / np.linalg.norm(with_bg["opacities"])
+    assert rel > 1e-2
+
+
+def test_background_division_form_equals_direct_form():
+    prm = oracle.Params.standard(background=BG)
+    wl = synth.tiny_scene(37, n=48, log_scale=(-1.2, 0.3), opac_sd=2.5)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    g = np.random.default_rng(2).standard_normal((3, cam.height, cam.width))
+    state = oracle.render(scene, cam, prm)
+    a = oracle.render_backward(scene, cam, prm, g, state=state, form=0)
+    b = oracle.render_backward(scene, cam, prm, g, state=state, form=1)
+    for k in ("mean2d", "conic", "colors", "opacities"):
+        scale = np.abs(b[k]).max()
+        assert np.abs(a[k] - b[k]).max() <= 1e-11 * scale, k
 
 def test_conic_to_cov2d_gradient_by_fd():
     rng = np.random.default_rng(35)
