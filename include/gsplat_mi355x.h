@@ -36,6 +36,10 @@
  * - alpha = min(alpha_max, o exp(-sigma)); entries with alpha < alpha_min are
  *   skipped; compositing stops before the first entry whose T (1 - alpha) would drop
  *   below T_min (that entry is not composited).
+ * - the image formation of Sec. 2.2 has no background (gs_params.background = 0). A
+ *   nonzero background bg is an option: C = sum c alpha T + T_final bg, and the
+ *   backward counts bg, with weight T_final, in the colour behind every entry (S of
+ *   eq. 18).
  */
 #ifndef GSPLAT_MI355X_H
 #define GSPLAT_MI355X_H
@@ -117,11 +121,13 @@ typedef struct gs_splats {
     int64_t capacity;        /* P */
 } gs_splats;
 
-/* Compositing thresholds (see the readings above). Defaults: 1/255, 0.99, 1e-4. */
+/* Compositing thresholds (see the readings above). Defaults: 1/255, 0.99, 1e-4.
+ * background: colour seen through T_final (RGB); zero for the paper's image formation. */
 typedef struct gs_params {
     float alpha_min;
     float alpha_max;
     float T_min;
+    float background[3];
     int32_t reserved;
 } gs_params;
 
@@ -266,7 +272,7 @@ int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams,
  * transmittance. A persistent launch takes work items (whole 16x16 tiles, or 16x4 quarters
  * of long-list tiles) from the work list gs_bin_and_sort wrote, longest first.
  * Outputs over the packed pixels of all cameras (n_pixels = sum of width * height):
- *   image   [3][n_pixels]  C
+ *   image   [3][n_pixels]  C (plus T_final times prm->background)
  *   T_final [n_pixels]     T after the last composited entry
  *   last    [n_pixels]     1 + list position (within the tile's run) of the last
  *                          composited entry, 0 if none: where the backward starts
@@ -289,7 +295,8 @@ int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const gs_camera *c
  *   dL_dcolors [3][n_gaussians] dL/dc per scene Gaussian
  *   dL_dopac   [n_gaussians]    dL/do per scene Gaussian
  * dL_dimage [3][n_pixels]; T_final and last from gs_rasterize_fwd with the same
- * inputs. Gradients of clamped alphas (o exp(-sigma) > alpha_max) reach only c.
+ * inputs (and the same prm, whose background enters through T_final). Gradients of
+ * clamped alphas (o exp(-sigma) > alpha_max) reach only c.
  * Outputs are accumulated; zero them first. dL/dmu' and dL/dY are float64 because
  * gs_project_bwd multiplies them by Y on both sides (dL/dSigma' = -Y dL/dY Y): for a
  * needle-like splat float32 rounding of dL/dY, scaled by the square of Y's largest
@@ -307,7 +314,8 @@ int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, 
  * of a long-list tile, of any camera) the forward of eq. (7), the gradient of the L2
  * image loss L = sum (C - target)^2, dL/dC = 2 (C - target), and the backward of
  * Sec. 3.1 run back to back inside one persistent launch, so the image, T and `last`
- * stay in registers. target [3][n_pixels]. image: optional (NULL) output of C. loss:
+ * stay in registers. C includes the background term of prm. target [3][n_pixels].
+ * image: optional (NULL) output of C. loss:
  * optional (NULL) device float to which L is added. Gradient outputs and errors as for
  * gs_rasterize_bwd (accumulated; zero them first).
  */

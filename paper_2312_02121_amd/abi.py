@@ -57,7 +57,7 @@ class GsSplats(ctypes.Structure):
 
 class GsParams(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("background", ctypes.c_float * 3), ("reserved", ctypes.c_int32)]
 
 
 class GsTuning(ctypes.Structure):

@@ -658,9 +658,10 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
     for (int q = 0; q < PX; ++q) {
         if (pixel_inside<PX>(t, q)) {
             const int64_t pix = t.pix0 + q;
-            o.image[pix] = ps.c0[q];
-            o.image[o.n_pixels + pix] = ps.c1[q];
-            o.image[2 * o.n_pixels + pix] = ps.c2[q];
+            // the background is seen through T_final (exactly C when it is zero)
+            o.image[pix] = __builtin_fmaf(ps.T[q], prm.background[0], ps.c0[q]);
+            o.image[o.n_pixels + pix] = __builtin_fmaf(ps.T[q], prm.background[1], ps.c1[q]);
+            o.image[2 * o.n_pixels + pix] = __builtin_fmaf(ps.T[q], prm.background[2], ps.c2[q]);
             o.T_out[pix] = ps.T[q];
             o.last_out[pix] = ps.last[q];
             if (kVisited) o.visited_out[pix] = ps.vis[q];
@@ -726,9 +727,11 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
             g2[q] = in.dL_dimage[2 * in.n_pixels + pix];
         }
     }
+    // the background is the colour behind the last entry, seen with weight T_final
     float gS[PX];
 #pragma unroll
-    for (int q = 0; q < PX; ++q) gS[q] = 0.f;
+    for (int q = 0; q < PX; ++q)
+        gS[q] = (g0[q] * prm.background[0] + g1[q] * prm.background[1] + g2[q] * prm.background[2]) * T[q];
     bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, t.start, t.end);
 }
 
@@ -791,17 +794,20 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
         g0[q] = g1[q] = g2[q] = 0.f;
         if (pixel_inside<PX>(t, q)) {
             const int64_t pix = t.pix0 + q;
-            const float d0 = ps.c0[q] - io.target[pix];
-            const float d1 = ps.c1[q] - io.target[io.n_pixels + pix];
-            const float d2 = ps.c2[q] - io.target[2 * io.n_pixels + pix];
+            const float C0 = __builtin_fmaf(ps.T[q], prm.background[0], ps.c0[q]);
+            const float C1 = __builtin_fmaf(ps.T[q], prm.background[1], ps.c1[q]);
+            const float C2 = __builtin_fmaf(ps.T[q], prm.background[2], ps.c2[q]);
+            const float d0 = C0 - io.target[pix];
+            const float d1 = C1 - io.target[io.n_pixels + pix];
+            const float d2 = C2 - io.target[2 * io.n_pixels + pix];
             g0[q] = 2.f * d0;
             g1[q] = 2.f * d1;
             g2[q] = 2.f * d2;
             l2 += d0 * d0 + d1 * d1 + d2 * d2;
             if (io.image && seg == 0) {
-                io.image[pix] = ps.c0[q];
-                io.image[io.n_pixels + pix] = ps.c1[q];
-                io.image[2 * io.n_pixels + pix] = ps.c2[q];
+                io.image[pix] = C0;
+                io.image[io.n_pixels + pix] = C1;
+                io.image[2 * io.n_pixels + pix] = C2;
             }
         }
     }
@@ -810,17 +816,19 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
         if ((threadIdx.x & (kWave - 1)) == kWave - 1) atomic_add_f32(io.loss, l2);
     }
     // the walk back over [lo, hi) starts from the state after entry hi - 1: for the last
-    // segment T_final and nothing behind; otherwise the snapshot, with the colour added
-    // from hi on carried by gS = dL/dC . (C_final - C(hi))
+    // segment T_final and only the background behind (weight T_final); otherwise the
+    // snapshot, with the colour added from hi on carried by gS = dL/dC . (C_final - C(hi))
     float T[PX], gS[PX];
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
+        const float gbg = (g0[q] * prm.background[0] + g1[q] * prm.background[1] + g2[q] * prm.background[2]) * ps.T[q];
         if (hi < t.end) {
             T[q] = sn.T[q];
-            gS[q] = g0[q] * (ps.c0[q] - sn.c0[q]) + g1[q] * (ps.c1[q] - sn.c1[q]) + g2[q] * (ps.c2[q] - sn.c2[q]);
+            gS[q] = g0[q] * (ps.c0[q] - sn.c0[q]) + g1[q] * (ps.c1[q] - sn.c1[q]) + g2[q] * (ps.c2[q] - sn.c2[q]) +
+                    gbg;
         } else {
             T[q] = ps.T[q];
-            gS[q] = 0.f;
+            gS[q] = gbg;
         }
     }
     bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, lo, hi);

@@ -26,12 +26,12 @@ def oracle_params(**kw):
     return oracle.Params.standard(margin_alpha=MARGIN_ALPHA, margin_T=MARGIN_T, margin_clamp=MARGIN_CLAMP, **kw)
 
 
-def gpu_forward(wl, keep_visited=True, capacity=None):
+def gpu_forward(wl, keep_visited=True, capacity=None, params=None):
     import torch
     from paper_2312_02121_amd import pipeline
     g = pipeline.GaussianSet(wl.scenes)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
-    r = pipeline.Rasterizer(cams, capacity=capacity, keep_visited=keep_visited, keep_records=True)
+    r = pipeline.Rasterizer(cams, params, capacity=capacity, keep_visited=keep_visited, keep_records=True)
     st = r.forward(g)
     torch.cuda.synchronize()
     return r, st

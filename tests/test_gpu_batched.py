@@ -161,3 +161,36 @@ def test_results_do_not_depend_on_launch_tuning(name):
                 assert_grads_close(g, ref, tol=1e-5)
     finally:
         autotune.apply(autotune.default_tuning())
+
+
+
+def test_background_fused_equals_separate():
+    """With a background, the fused kernel (including list segments of split tiles, which
+    carry the background in the colour behind their segment) reproduces the separate
+    kernels, and the background changes the image by T_final bg."""
+    _print_case("background_fused_vs_separate", wl="c2_20k")
+    from paper_2312_02121_amd import autotune, pipeline
+    bg = (0.3, -0.2, 0.8)
+    wl = synth.make_config(2, n_override=20_000)
+    prm = pipeline.make_params(background=bg)
+    try:
+        for t in ({}, {"split_len": 64, "split_parts": 4, "bwd_segs": 4, "prio_len": 64},
+                  {"split_len": 128, "split_parts": 2, "bwd_segs": 2}):
+            autotune.apply(t)
+            _, _, _, sep = build(wl, "separate", params=prm)
+            _, _, _, fus = build(wl, "fused", params=prm)
+            sep()
+            fus()
+            torch.cuda.synchronize()
+            assert torch.equal(sep.r.image, fus.r.image), t
+            loss_ref = float(((sep.r.image.double() - sep.targets.double()) ** 2).sum())
+            assert abs(float(fus.loss) - loss_ref) <= 1e-5 * loss_ref, t
+            assert_grads_close(grads_np(fus), grads_np(sep))
+        _, _, _, plain = build(wl, "separate")
+        plain()
+        torch.cuda.synchronize()
+        T = sep.r.T_final.double()
+        want = plain.r.image.double() + T.view(1, -1) * torch.tensor(bg, dtype=torch.float64, device="cuda").view(3, 1)
+        assert float((sep.r.image.double() - want).abs().max()) <= 1e-6
+    finally:
+        autotune.apply(autotune.default_tuning())

@@ -83,10 +83,10 @@ def test_bins_bit_exact(name, generate):
     assert np.array_equal(g["ranges"], np.concatenate(oranges).astype(np.int32))
 
 
-def _forward_compare(wl, r, st):
+def _forward_compare(wl, r, st, prm=None):
     flagged_total, pixels = 0, 0
     for k in range(len(wl.cameras)):
-        orc, scene, cam, prm = oracle_camera(wl, k)
+        orc, scene, cam, prm = oracle_camera(wl, k, prm)
         g = camera_images(r, st, k)
         ok = orc["flags"] == 0
         flagged_total += int((~ok).sum())
@@ -109,15 +109,16 @@ def test_forward_image(name):
     assert flagged <= max(3, 0.02 * pixels)
 
 
-def _backward_compare(wl, r, st, seed=0, with_pose=False):
+def _backward_compare(wl, r, st, seed=0, with_pose=False, prm=None):
     rng = np.random.default_rng(seed)
     cams = r.cams
     g_img = np.zeros((3, cams.n_pixels), dtype=np.float32)
     og = {k: np.zeros_like(v, dtype=np.float64) for k, v in wl.scenes[0].items()}
     ograds = [{key: np.zeros(np.asarray(s[key]).shape) for key in ("means", "quats", "scales", "colors", "opacities")}
               for s in wl.scenes]
+    oprm = prm
     for k, cam in enumerate(wl.cameras):
-        orc, scene, _, prm = oracle_camera(wl, k)
+        orc, scene, _, prm = oracle_camera(wl, k, oprm)
         g = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
         g[:, orc["flags"] != 0] = 0.0
         off = int(cams.host[k]["pixel_offset"])
@@ -151,6 +152,27 @@ def test_backward_gradients(name):
         assert rel <= GRAD_REL, (key, rel)
         assert elem, key
 
+
+
+BG = (0.3, -0.2, 0.8)
+
+
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k"])
+def test_background_forward_and_backward(name):
+    """The background variant (C + T_final bg; bg in the colour behind every entry) against
+    the oracle with the same background, forward and backward."""
+    _print_case("background", wl=name)
+    from paper_2312_02121_amd import pipeline
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl, params=pipeline.make_params(background=BG))
+    prm = oracle_params(background=BG)
+    flagged, pixels = _forward_compare(wl, r, st, prm=prm)
+    assert flagged <= max(3, 0.02 * pixels)
+    res = _backward_compare(wl, r, st, prm=prm)
+    print(res)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
 
 def test_multi_scene_multi_camera():
     _print_case("multi", wl="c5_small")
