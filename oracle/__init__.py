@@ -62,7 +62,7 @@ class _Params(ctypes.Structure):
                 ("T_min", ctypes.c_double), ("margin_alpha", ctypes.c_double),
                 ("margin_T", ctypes.c_double), ("margin_clamp", ctypes.c_double),
                 ("round_interface", ctypes.c_int32), ("errata", ctypes.c_int32),
-                ("n_threads", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n_threads", ctypes.c_int32), ("normalize_quats", ctypes.c_int32),
                 ("background", ctypes.c_double * 3)]
 
 
@@ -126,6 +126,7 @@ class Params:
     errata: int = 0
     n_threads: int = 0
     background: tuple = (0.0, 0.0, 0.0)   # colour seen through T_final; zero in the paper
+    normalize_quats: bool = False         # R(q / |q|); the paper takes q as given
 
     @staticmethod
     def standard(**kw) -> "Params":
@@ -142,7 +143,8 @@ class Params:
     def c(self) -> _Params:
         return _Params(self.alpha_min, self.alpha_max, self.T_min, self.margin_alpha, self.margin_T,
                        self.margin_clamp, int(bool(self.round_interface)), int(self.errata),
-                       int(self.n_threads), 0, (ctypes.c_double * 3)(*[float(x) for x in self.background]))
+                       int(self.n_threads), int(bool(self.normalize_quats)),
+                       (ctypes.c_double * 3)(*[float(x) for x in self.background]))
 
 
 def camera_struct(cam) -> _Camera:

@@ -20,7 +20,9 @@
  *   - eq. (5): the printed R11 = 1 - 2(x^2 - z^2) is not a rotation; we use
  *     1 - 2(x^2 + z^2), the only form consistent with dR/dz in Sec. 3.2.1.
  *   - quaternions are stored (w, x, y, z), the order of Sec. 3.2.1, and are not
- *     renormalised.
+ *     renormalised (the paper's R(q) assumes a unit q). As an option
+ *     (normalize_quats), q is replaced by q / |q| before R(q), and dL/dq becomes
+ *     (dL/dq^ - q^ (q^ . dL/dq^)) / |q| with q^ = q / |q|.
  *   - Delta = mu' - p (pixel centre p), the sign for which dsigma/dmu' = Y Delta.
  *   - eq. (23): the second row uses h, and t means t' there.
  *   - near/far cull: keep only near < t_z < far.
@@ -80,7 +82,7 @@ typedef struct {
     int32_t round_interface; /* round mu', Y, depth to float32 where the HIP path stores them */
     int32_t errata;
     int32_t n_threads;     /* <= 0: OpenMP default */
-    int32_t pad;
+    int32_t normalize_quats; /* 1: R(q / |q|) (an option; the paper uses q as given) */
     double background[3];  /* bg, zero for the paper's image formation */
 } orc_params;
 
@@ -166,6 +168,7 @@ static void proj_matrix(const orc_camera *c, double *P)
 
 typedef struct {
     double mu[3], q[4], s[3];
+    double qn;                  /* |q| when q was normalised, else 1 */
     double R[9], M[9], Sigma[9];
     double t[4], tp[4];         /* t = T_cw [mu; 1], t' = P t (eq. 2) */
     double J[6], T[6];          /* eq. (3) and T = J R_cw */
@@ -182,6 +185,13 @@ static int project_one(const orc_camera *cam, const orc_params *prm, orc_proj *g
 {
     g->tiles = 0;
     g->rect[0] = g->rect[1] = g->rect[2] = g->rect[3] = 0;
+    g->qn = 1.0;
+    if (prm->normalize_quats) {
+        /* a zero or non-finite q gives a non-finite q^, which is culled below */
+        const double qn = sqrt(g->q[0] * g->q[0] + g->q[1] * g->q[1] + g->q[2] * g->q[2] + g->q[3] * g->q[3]);
+        for (int a = 0; a < 4; ++a) g->q[a] = g->q[a] / qn;
+        g->qn = qn;
+    }
     if (!all_finite(g->mu, 3) || !all_finite(g->q, 4) || !all_finite(g->s, 3))
         return 0;
     orc_cov3d(g->q, g->s, prm->errata, g->R, g->M, g->Sigma);
@@ -713,9 +723,15 @@ void orc_project_bwd(int64_t N, const double *means, const double *quats, const 
         mm(Rt, dM, dS, 3, 3, 3);
 
         /* dR/dq (Sec. 3.2.1) and eq. (31) */
-        double dRq[4][9];
+        double dRq[4][9], dq[4];
         rot_jacobians(g.q, dRq);
-        for (int a = 0; a < 4; ++a) dquats[a * N + i] += frob(dR, dRq[a], 9);
+        for (int a = 0; a < 4; ++a) dq[a] = frob(dR, dRq[a], 9);
+        if (prm->normalize_quats) {
+            /* through q^ = q / |q|: d q^ / d q = (I - q^ q^T) / |q| */
+            const double dot = g.q[0] * dq[0] + g.q[1] * dq[1] + g.q[2] * dq[2] + g.q[3] * dq[3];
+            for (int a = 0; a < 4; ++a) dq[a] = (dq[a] - g.q[a] * dot) / g.qn;
+        }
+        for (int a = 0; a < 4; ++a) dquats[a * N + i] += dq[a];
         for (int a = 0; a < 3; ++a) dscales[a * N + i] += dS[4 * a];
     }
 }

@@ -466,6 +466,49 @@ def test_background_division_form_equals_direct_form():
         scale = np.abs(b[k]).max()
         assert np.abs(a[k] - b[k]).max() <= 1e-11 * scale, k
 
+
+# ------------------------------------- quaternion normalisation variant (R(q / |q|))
+
+def _scaled_quats(scene, seed):
+    out = {k: v.astype(np.float64).copy() for k, v in scene.items()}
+    k = np.random.default_rng(seed).uniform(0.5, 2.0, out["quats"].shape[1])
+    out["quats"] = out["quats"] * k
+    return out
+
+
+def test_normalised_quats_are_scale_invariant():
+    """With normalisation the render depends on q only through q / |q|: scaling q changes
+    nothing, and unit inputs render as without the option."""
+    wl = synth.tilted_camera_scene(41, n=40)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    prm = oracle.Params.standard(normalize_quats=True)
+    unit = {k: v.astype(np.float64) for k, v in scene.items()}
+    unit["quats"] = unit["quats"] / np.sqrt((unit["quats"] ** 2).sum(axis=0))
+    a = oracle.render(_scaled_quats(scene, 0), cam, prm)
+    b = oracle.render(unit, cam, oracle.Params.standard())
+    assert np.abs(a["C"] - b["C"]).max() < 1e-12
+    assert np.array_equal(a["proj"]["rect"], b["proj"]["rect"])
+    # a zero quaternion has no direction: it is culled
+    z = _scaled_quats(scene, 0)
+    z["quats"][:, 3] = 0.0
+    assert oracle.render(z, cam, prm)["proj"]["tiles"][3] == 0
+
+
+def test_normalised_quats_gradient_by_fd_and_orthogonal_to_q():
+    """dL/dq through q / |q|: finite differences on non-unit quaternions, and the gradient is
+    orthogonal to q (the render is invariant to |q|); without the projection term it is not."""
+    wl = synth.tilted_camera_scene(42, n=12)
+    wl.scenes[0] = _scaled_quats(wl.scenes[0], 1)
+    prm = oracle.Params.standard(round_interface=False, normalize_quats=True)
+    worst, discont, checked = _fd_check(wl, prm)
+    assert checked > 150 and discont <= 2
+    assert worst < 2e-6, worst
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    g = np.random.default_rng(3).standard_normal((3, cam.height, cam.width))
+    gr = oracle.render_backward(scene, cam, prm, g)
+    dots = (gr["quats"] * scene["quats"]).sum(axis=0)
+    assert np.abs(dots).max() <= 1e-12 * np.abs(gr["quats"]).max() * np.abs(scene["quats"]).max()
+
 def test_conic_to_cov2d_gradient_by_fd():
     rng = np.random.default_rng(35)
     for _ in range(20):
