@@ -25,7 +25,9 @@
  * Readings of the paper that fix the conventions (each is pinned by a CPU test of the
  * FP64 oracle):
  * - quaternions are (w, x, y, z) (Sec. 3.2.1); R(q) is the polynomial of eq. (5) with
- *   R11 = 1 - 2(x^2 + z^2); q is not renormalised.
+ *   R11 = 1 - 2(x^2 + z^2); q is not renormalised unless gs_gaussians.flags has
+ *   GS_NORMALIZE_QUATS (an option: R(q / |q|), and gs_project_bwd returns dL/dq through
+ *   the normalisation, (dL/dq^ - q^ (q^ . dL/dq^)) / |q|).
  * - mu' follows eq. (2) literally, so a point on the optical axis lands at
  *   (c_x + 1/2, c_y + 1/2); pixel (row i, col j) has centre (j + 1/2, i + 1/2) and
  *   Delta = mu' - pixel centre.
@@ -95,7 +97,12 @@ typedef struct gs_gaussians {
     const float *colors;     /* [3][n] */
     const float *opacities;  /* [n] */
     int64_t n;
+    int32_t flags;           /* GS_NORMALIZE_QUATS or 0 */
+    int32_t reserved;
 } gs_gaussians;
+
+/* gs_gaussians.flags: use q / |q| (in float64) for R(q); a zero quaternion is culled. */
+#define GS_NORMALIZE_QUATS 1
 
 /*
  * Projected 2D Gaussians ("splats"), one slot per (camera, Gaussian of its scene):

@@ -47,7 +47,11 @@ assert CAMERA_DTYPE.itemsize == 128
 
 class GsGaussians(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("quats", ctypes.c_void_p), ("scales", ctypes.c_void_p),
-                ("colors", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("n", ctypes.c_int64)]
+                ("colors", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+GS_NORMALIZE_QUATS = 1
 
 
 class GsSplats(ctypes.Structure):

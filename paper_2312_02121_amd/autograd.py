@@ -26,10 +26,10 @@ class RasterizeGaussians(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, means, quats, scales, colors, opacities, cams: pipeline.CameraSet,
-                params: abi.GsParams, sizes: tuple):
+                params: abi.GsParams, sizes: tuple, normalize_quats: bool = False):
         g = pipeline.GaussianSet.from_tensors(means.detach().contiguous(), quats.detach().contiguous(),
                                               scales.detach().contiguous(), colors.detach().contiguous(),
-                                              opacities.detach().contiguous(), sizes)
+                                              opacities.detach().contiguous(), sizes, normalize_quats)
         key = (cams.n_splats, cams.n_tiles)
         r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key))
         st = r.forward(g)
@@ -45,13 +45,14 @@ class RasterizeGaussians(torch.autograd.Function):
         grads = r.backward(st, dL_dimage.contiguous())
         ctx.state = ctx.rasterizer = ctx.gaussians = None
         return (grads["means"], grads["quats"], grads["scales"], grads["colors"], grads["opacities"],
-                None, None, None)
+                None, None, None, None)
 
 
 def render(means: torch.Tensor, quats: torch.Tensor, scales: torch.Tensor, colors: torch.Tensor,
            opacities: torch.Tensor, cameras: Sequence, scene_sizes: Sequence[int] | None = None,
-           params: abi.GsParams | None = None) -> list[torch.Tensor]:
+           params: abi.GsParams | None = None, normalize_quats: bool = False) -> list[torch.Tensor]:
     """Renders every camera; returns [3, H, W] images that are differentiable in all five inputs.
+    params: thresholds and background (pipeline.make_params); normalize_quats: use q / |q|.
 
     means [3, N], quats [4, N] (w, x, y, z), scales [3, N], colors [3, N], opacities [N], float32 on
     the GPU. Several scenes may be concatenated along N (scene_sizes); each camera's ``scene``
@@ -60,5 +61,5 @@ def render(means: torch.Tensor, quats: torch.Tensor, scales: torch.Tensor, color
     sizes = tuple(scene_sizes) if scene_sizes is not None else (int(opacities.shape[-1]),)
     cams = pipeline.CameraSet(cameras, sizes, device=means.device)
     params = params or pipeline.make_params()
-    packed = RasterizeGaussians.apply(means, quats, scales, colors, opacities, cams, params, sizes)
+    packed = RasterizeGaussians.apply(means, quats, scales, colors, opacities, cams, params, sizes, normalize_quats)
     return [cams.unpack(packed, k) for k in range(cams.n_cams)]

@@ -25,7 +25,15 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
 
     const double mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
-    const double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    if (g.flags & GS_NORMALIZE_QUATS) {
+        // q / |q|; a zero or non-finite q gives a non-finite result, which is culled below
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw = qw / qn;
+        qx = qx / qn;
+        qy = qy / qn;
+        qz = qz / qn;
+    }
     const double s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
 
     int visible = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(qw) && isfinite(qx) &&

@@ -37,7 +37,15 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
         const int64_t n = g.n;
         const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
         const double mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
-        const double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+        double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+        double qn = 1.0;   // |q| when normalised (same arithmetic as the projection)
+        if (g.flags & GS_NORMALIZE_QUATS) {
+            qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            qw = qw / qn;
+            qx = qx / qn;
+            qy = qy / qn;
+            qz = qz / qn;
+        }
         const double s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
         const double R[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4], cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
         const double fx = cam.fx, fy = cam.fy;
@@ -147,13 +155,21 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(gs_gaussians g, const 
 #pragma unroll
         for (int b = 0; b < 3; ++b) ds[b] = Q[b] * dM[b] + Q[3 + b] * dM[3 + b] + Q[6 + b] * dM[6 + b];
         // dR/dq (Sec. 3.2.1), q = (w, x, y, z)
-        const double dqw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-        const double dqx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
-                                 qw * dR[7] - 2.0 * qx * dR[8]);
-        const double dqy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
-                                 qz * dR[7] - 2.0 * qy * dR[8]);
-        const double dqz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
-                                 qy * dR[5] + qx * dR[6] + qy * dR[7]);
+        double dqw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+        double dqx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                            qw * dR[7] - 2.0 * qx * dR[8]);
+        double dqy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                            qz * dR[7] - 2.0 * qy * dR[8]);
+        double dqz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
+                            qy * dR[5] + qx * dR[6] + qy * dR[7]);
+        if (g.flags & GS_NORMALIZE_QUATS) {
+            // through q^ = q / |q|: d q^ / d q = (I - q^ q^T) / |q|
+            const double dot = qw * dqw + qx * dqx + qy * dqy + qz * dqz;
+            dqw = (dqw - qw * dot) / qn;
+            dqx = (dqx - qx * dot) / qn;
+            dqy = (dqy - qy * dot) / qn;
+            dqz = (dqz - qz * dot) / qn;
+        }
 
         if (use_atomics) {
             atomic_add_f32(&d_means[i], (float)dmu0);

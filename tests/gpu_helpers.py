@@ -26,10 +26,10 @@ def oracle_params(**kw):
     return oracle.Params.standard(margin_alpha=MARGIN_ALPHA, margin_T=MARGIN_T, margin_clamp=MARGIN_CLAMP, **kw)
 
 
-def gpu_forward(wl, keep_visited=True, capacity=None, params=None):
+def gpu_forward(wl, keep_visited=True, capacity=None, params=None, normalize_quats=False):
     import torch
     from paper_2312_02121_amd import pipeline
-    g = pipeline.GaussianSet(wl.scenes)
+    g = pipeline.GaussianSet(wl.scenes, normalize_quats=normalize_quats)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     r = pipeline.Rasterizer(cams, params, capacity=capacity, keep_visited=keep_visited, keep_records=True)
     st = r.forward(g)
@@ -98,14 +98,14 @@ def tile_offsets(wl):
     return offs
 
 
-def check_projection(wl, r, views=None):
+def check_projection(wl, r, views=None, prm=None):
     """Splat fields of every camera (or of `views`) bit-exact against the oracle's projection."""
     s = splat_arrays(r)
     for k in (range(len(wl.cameras)) if views is None else views):
         cam = wl.cameras[k]
         off = int(r.cams.host[k]["proj_offset"])
         n = int(r.cams.host[k]["gauss_count"])
-        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
+        o = oracle.project(wl.scenes[cam.scene], cam, prm or oracle_params())
         sl = slice(off, off + n)
         assert np.array_equal(s["tiles"][sl], o["tiles"]), "tiles_touched"
         vis = o["tiles"] > 0

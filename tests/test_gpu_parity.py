@@ -174,6 +174,30 @@ def test_background_forward_and_backward(name):
         assert rel <= GRAD_REL, (key, rel)
         assert elem, key
 
+
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k"])
+def test_normalized_quats_projection_image_and_gradients(name):
+    """Quaternion normalisation (R(q / |q|)) on non-unit quaternions: the projection stays
+    bit-exact against the oracle with the same option, the image and every gradient (dL/dq
+    through the normalisation) within the bars."""
+    import copy
+    _print_case("normalize_quats", wl=name)
+    base = wl_cache()[name]
+    wl = copy.copy(base)
+    rng = np.random.default_rng(5)
+    wl.scenes = [dict(sc, quats=(sc["quats"] * rng.uniform(0.5, 2.0, sc["quats"].shape[1])).astype(np.float32))
+                 for sc in base.scenes]
+    r, st = gpu_forward(wl, normalize_quats=True)
+    prm = oracle_params(normalize_quats=True)
+    check_projection(wl, r, prm=prm)
+    flagged, pixels = _forward_compare(wl, r, st, prm=prm)
+    assert flagged <= max(3, 0.02 * pixels)
+    res = _backward_compare(wl, r, st, prm=prm)
+    print(res)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
+
 def test_multi_scene_multi_camera():
     _print_case("multi", wl="c5_small")
     wl = synth.make_config(5, n_override=3000)
