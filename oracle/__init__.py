@@ -63,7 +63,7 @@ class _Params(ctypes.Structure):
                 ("margin_T", ctypes.c_double), ("margin_clamp", ctypes.c_double),
                 ("round_interface", ctypes.c_int32), ("errata", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("normalize_quats", ctypes.c_int32),
-                ("background", ctypes.c_double * 3)]
+                ("background", ctypes.c_double * 3), ("box_lambda_max", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -127,6 +127,7 @@ class Params:
     n_threads: int = 0
     background: tuple = (0.0, 0.0, 0.0)   # colour seen through T_final; zero in the paper
     normalize_quats: bool = False         # R(q / |q|); the paper takes q as given
+    box_lambda_max: bool = False          # square 3-sigma box from lambda_max (tight box otherwise)
 
     @staticmethod
     def standard(**kw) -> "Params":
@@ -144,7 +145,8 @@ class Params:
         return _Params(self.alpha_min, self.alpha_max, self.T_min, self.margin_alpha, self.margin_T,
                        self.margin_clamp, int(bool(self.round_interface)), int(self.errata),
                        int(self.n_threads), int(bool(self.normalize_quats)),
-                       (ctypes.c_double * 3)(*[float(x) for x in self.background]))
+                       (ctypes.c_double * 3)(*[float(x) for x in self.background]),
+                       int(bool(self.box_lambda_max)), 0)
 
 
 def camera_struct(cam) -> _Camera:

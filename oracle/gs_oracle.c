@@ -27,6 +27,9 @@
  *   - eq. (23): the second row uses h, and t means t' there.
  *   - near/far cull: keep only near < t_z < far.
  *   - 3-sigma box: tight axis-aligned half extents 3 sqrt(Sigma'_00), 3 sqrt(Sigma'_11).
+ *     As an option (box_lambda_max), a square of half extent 3 sqrt(lambda_max) with
+ *     lambda_max = (a + c) / 2 + sqrt(((a - c) / 2)^2 + b^2), Sigma' = (a, b; b, c):
+ *     the largest eigenvalue, so the square contains the tight box.
  *   - tile k spans pixel coordinates [16k, 16k+16); pixel (row i, col j) has centre
  *     (j + 1/2, i + 1/2).
  *   - alpha = min(alpha_max, o exp(-sigma)); entries with alpha < alpha_min are
@@ -84,6 +87,8 @@ typedef struct {
     int32_t n_threads;     /* <= 0: OpenMP default */
     int32_t normalize_quats; /* 1: R(q / |q|) (an option; the paper uses q as given) */
     double background[3];  /* bg, zero for the paper's image formation */
+    int32_t box_lambda_max;  /* 1: square 3-sigma box from the largest eigenvalue of Sigma' */
+    int32_t pad2;
 } orc_params;
 
 /* ------------------------------------------------------------------ small linear algebra */
@@ -241,8 +246,14 @@ static int project_one(const orc_camera *cam, const orc_params *prm, orc_proj *g
         return 0;
 
     /* Sec. 2.2: axis-aligned box of the 3-sigma ellipse, intersected with the tile grid */
-    const double ex = 3.0 * sqrt(g->cov2d[0]);
-    const double ey = 3.0 * sqrt(g->cov2d[3]);
+    double ex = 3.0 * sqrt(g->cov2d[0]);
+    double ey = 3.0 * sqrt(g->cov2d[3]);
+    if (prm->box_lambda_max) {
+        const double a = g->cov2d[0], b = g->cov2d[1], c = g->cov2d[3];
+        const double h = (a - c) / 2.0;
+        const double lmax = (a + c) / 2.0 + sqrt(h * h + b * b);
+        ex = ey = 3.0 * sqrt(lmax);
+    }
     const double TX = (double)((cam->W + ORC_TILE - 1) / ORC_TILE);
     const double TY = (double)((cam->H + ORC_TILE - 1) / ORC_TILE);
     double x0 = floor((g->mean2d[0] - ex) / ORC_TILE);

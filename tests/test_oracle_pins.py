@@ -509,6 +509,49 @@ def test_normalised_quats_gradient_by_fd_and_orthogonal_to_q():
     dots = (gr["quats"] * scene["quats"]).sum(axis=0)
     assert np.abs(dots).max() <= 1e-12 * np.abs(gr["quats"]).max() * np.abs(scene["quats"]).max()
 
+
+# ------------------------------------------- square 3-sigma box from lambda_max (option)
+
+def test_lambda_max_box_contains_tight_box_and_matches_eigvalsh():
+    """The square box has half extent 3 sqrt(lambda_max(Sigma')): it contains the tight box,
+    and its tile rect is the one numpy's eigvalsh of Sigma' = Y^-1 gives."""
+    wl = synth.tilted_camera_scene(43, n=200)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    tight = oracle.project(scene, cam, oracle.Params.standard(round_interface=False))
+    sq = oracle.project(scene, cam, oracle.Params.standard(round_interface=False, box_lambda_max=True))
+    vis = tight["tiles"] > 0
+    assert np.all(sq["tiles"][vis] > 0)            # a larger box only adds visible splats
+    r0, r1 = tight["rect"][:, vis], sq["rect"][:, vis]
+    assert np.all(r1[0] <= r0[0]) and np.all(r1[1] <= r0[1]) and np.all(r1[2] >= r0[2]) and np.all(r1[3] >= r0[3])
+    assert (sq["tiles"][vis] > tight["tiles"][vis]).any()
+    TX, TY = (cam.width + 15) // 16, (cam.height + 15) // 16
+    checked = 0
+    for n in np.nonzero(sq["tiles"] > 0)[0]:
+        Y = np.array([[sq["conic"][0, n], sq["conic"][1, n]], [sq["conic"][1, n], sq["conic"][2, n]]])
+        e = 3.0 * np.sqrt(np.linalg.eigvalsh(np.linalg.inv(Y)).max())
+        edges = np.array([sq["mean2d"][0, n] - e, sq["mean2d"][1, n] - e, sq["mean2d"][0, n] + e,
+                          sq["mean2d"][1, n] + e]) / 16.0
+        if np.any(np.abs(edges - np.round(edges)) < 1e-9):
+            continue                               # a floor on the edge: rounding may decide
+        want = np.floor(edges)
+        want = np.array([max(want[0], 0), max(want[1], 0), min(want[2], TX - 1), min(want[3], TY - 1)])
+        assert np.array_equal(sq["rect"][:, n], want.astype(np.int32)), n
+        checked += 1
+    assert checked > 150
+
+
+def test_lambda_max_box_tile_pipeline_equals_global_sort():
+    wl = synth.tiny_scene(44, n=40)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    prm = oracle.Params.standard(box_lambda_max=True)
+    out = oracle.render(scene, cam, prm)
+    pr = out["proj"]
+    ref = brute.render(pr["mean2d"], pr["conic"], pr["depth"], pr["rect"], pr["tiles"],
+                       scene["colors"].astype(np.float64), scene["opacities"].astype(np.float64),
+                       cam.width, cam.height, prm.alpha_min, prm.alpha_max, prm.T_min)
+    assert np.abs(out["C"] - ref["C"]).max() < 1e-12
+    assert np.array_equal(out["last"], ref["last"])
+
 def test_conic_to_cov2d_gradient_by_fd():
     rng = np.random.default_rng(35)
     for _ in range(20):
