@@ -33,8 +33,9 @@
  *   Delta = mu' - pixel centre.
  * - a Gaussian is culled unless near < t_z < far, Sigma' has positive determinant
  *   and its 3-sigma tile box meets the image.
- * - the 3-sigma box has half extents 3 sqrt(Sigma'_00), 3 sqrt(Sigma'_11); tile k
- *   covers pixel coordinates [16k, 16k + 16).
+ * - the 3-sigma box has half extents 3 sqrt(Sigma'_00), 3 sqrt(Sigma'_11) (the tight box
+ *   of the ellipse), or, with GS_BOX_LAMBDA_MAX, 3 sqrt(lambda_max) on both axes, lambda_max
+ *   the largest eigenvalue of Sigma'; tile k covers pixel coordinates [16k, 16k + 16).
  * - alpha = min(alpha_max, o exp(-sigma)); entries with alpha < alpha_min are
  *   skipped; compositing stops before the first entry whose T (1 - alpha) would drop
  *   below T_min (that entry is not composited).
@@ -97,12 +98,14 @@ typedef struct gs_gaussians {
     const float *colors;     /* [3][n] */
     const float *opacities;  /* [n] */
     int64_t n;
-    int32_t flags;           /* GS_NORMALIZE_QUATS or 0 */
+    int32_t flags;           /* projection options: GS_NORMALIZE_QUATS | GS_BOX_LAMBDA_MAX, or 0 */
     int32_t reserved;
 } gs_gaussians;
 
 /* gs_gaussians.flags: use q / |q| (in float64) for R(q); a zero quaternion is culled. */
 #define GS_NORMALIZE_QUATS 1
+/* gs_gaussians.flags: square 3-sigma box of half extent 3 sqrt(lambda_max(Sigma')). */
+#define GS_BOX_LAMBDA_MAX 2
 
 /*
  * Projected 2D Gaussians ("splats"), one slot per (camera, Gaussian of its scene):

@@ -52,6 +52,7 @@ class GsGaussians(ctypes.Structure):
 
 
 GS_NORMALIZE_QUATS = 1
+GS_BOX_LAMBDA_MAX = 2
 
 
 class GsSplats(ctypes.Structure):

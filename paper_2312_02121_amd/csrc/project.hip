@@ -101,7 +101,13 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
 
         if (visible) {
             // axis-aligned box of the 3-sigma ellipse on the 16x16 tile grid
-            const double ex = 3.0 * sqrt(C00), ey = 3.0 * sqrt(C11);
+            double ex = 3.0 * sqrt(C00), ey = 3.0 * sqrt(C11);
+            if (g.flags & GS_BOX_LAMBDA_MAX) {
+                // square from the largest eigenvalue of Sigma' (contains the tight box)
+                const double h = (C00 - C11) / 2.0;
+                const double lmax = (C00 + C11) / 2.0 + sqrt(h * h + C01 * C01);
+                ex = ey = 3.0 * sqrt(lmax);
+            }
             const double TX = (double)cam.tiles_x, TY = (double)cam.tiles_y;
             double x0 = floor((mu0 - ex) / 16.0), x1 = floor((mu0 + ex) / 16.0);
             double y0 = floor((mu1 - ey) / 16.0), y1 = floor((mu1 + ey) / 16.0);

@@ -119,11 +119,13 @@ class GaussianSet:
     KEYS = ("means", "quats", "scales", "colors", "opacities")
 
     def __init__(self, scenes: Sequence[dict] | dict, device="cuda", requires_grad: bool = False,
-                 normalize_quats: bool = False):
+                 normalize_quats: bool = False, box_lambda_max: bool = False):
         if isinstance(scenes, dict):
             scenes = [scenes]
-        # normalize_quats: the projection uses q / |q| and its backward differentiates through it
+        # normalize_quats: the projection uses q / |q| and its backward differentiates through it;
+        # box_lambda_max: square 3-sigma boxes from the largest eigenvalue of Sigma'
         self.normalize_quats = bool(normalize_quats)
+        self.box_lambda_max = bool(box_lambda_max)
         self.sizes = [int(s["opacities"].shape[-1]) for s in scenes]
         self.n = sum(self.sizes)
         self.t = {}
@@ -135,6 +137,7 @@ class GaussianSet:
     def from_tensors(means, quats, scales, colors, opacities, sizes=None, normalize_quats: bool = False) -> "GaussianSet":
         obj = GaussianSet.__new__(GaussianSet)
         obj.normalize_quats = bool(normalize_quats)
+        obj.box_lambda_max = False
         obj.t = {"means": means, "quats": quats, "scales": scales, "colors": colors, "opacities": opacities}
         obj.n = int(opacities.shape[-1])
         obj.sizes = list(sizes) if sizes is not None else [obj.n]
@@ -146,7 +149,9 @@ class GaussianSet:
             if not (t[k].is_contiguous() and t[k].dtype == torch.float32 and t[k].is_cuda):
                 raise ValueError(f"{k} must be a contiguous float32 device tensor")
         return abi.GsGaussians(_ptr(t["means"]), _ptr(t["quats"]), _ptr(t["scales"]), _ptr(t["colors"]),
-                               _ptr(t["opacities"]), self.n, abi.GS_NORMALIZE_QUATS if self.normalize_quats else 0)
+                               _ptr(t["opacities"]), self.n,
+                               (abi.GS_NORMALIZE_QUATS if self.normalize_quats else 0) |
+                               (abi.GS_BOX_LAMBDA_MAX if getattr(self, "box_lambda_max", False) else 0))
 
 
 @dataclass

@@ -26,10 +26,10 @@ def oracle_params(**kw):
     return oracle.Params.standard(margin_alpha=MARGIN_ALPHA, margin_T=MARGIN_T, margin_clamp=MARGIN_CLAMP, **kw)
 
 
-def gpu_forward(wl, keep_visited=True, capacity=None, params=None, normalize_quats=False):
+def gpu_forward(wl, keep_visited=True, capacity=None, params=None, normalize_quats=False, box_lambda_max=False):
     import torch
     from paper_2312_02121_amd import pipeline
-    g = pipeline.GaussianSet(wl.scenes, normalize_quats=normalize_quats)
+    g = pipeline.GaussianSet(wl.scenes, normalize_quats=normalize_quats, box_lambda_max=box_lambda_max)
     cams = pipeline.CameraSet(wl.cameras, g.sizes)
     r = pipeline.Rasterizer(cams, params, capacity=capacity, keep_visited=keep_visited, keep_records=True)
     st = r.forward(g)

@@ -198,6 +198,29 @@ def test_normalized_quats_projection_image_and_gradients(name):
         assert rel <= GRAD_REL, (key, rel)
         assert elem, key
 
+
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k"])
+def test_lambda_max_box_projection_lists_image_and_gradients(name):
+    """Square 3-sigma boxes from lambda_max: projection (rect, tile counts) and tile lists
+    bit-exact against the oracle with the same option, image and gradients within the bars."""
+    _print_case("box_lambda_max", wl=name)
+    wl = wl_cache()[name]
+    r, st = gpu_forward(wl, box_lambda_max=True)
+    prm = oracle_params(box_lambda_max=True)
+    check_projection(wl, r, prm=prm)
+    toffs = tile_offsets(wl)
+    K = 0
+    for k, cam in enumerate(wl.cameras):
+        K += oracle.bin_and_sort(oracle.project(wl.scenes[cam.scene], cam, prm), cam, tile_offset=toffs[k])["K"]
+    assert st.K == K
+    flagged, pixels = _forward_compare(wl, r, st, prm=prm)
+    assert flagged <= max(3, 0.02 * pixels)
+    res = _backward_compare(wl, r, st, prm=prm)
+    print(res)
+    for key, (rel, elem) in res.items():
+        assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
+
 def test_multi_scene_multi_camera():
     _print_case("multi", wl="c5_small")
     wl = synth.make_config(5, n_override=3000)
