@@ -236,6 +236,42 @@ def bin_and_sort(proj: dict, cam, tile_offset: int = 0) -> dict:
     return {"K": K, "keys": keys, "ids": ids, "ranges": ranges}
 
 
+def splats_from_2d(mean2d, conic, depth, valid, cam, params: Params) -> dict:
+    """The per-stage rasterizer input (Sec. 2.2 without the projection): the 3-sigma tile box
+    of each slot from given mu' [2, N], Y [3, N] = (Y00, Y01, Y11) and depth [N], with
+    Sigma' = Y^-1 formed in float64 from the given values (the box rule of the projection,
+    including its lambda_max option). Slots with valid 0, a Y that is not positive definite
+    or a box off the image are culled (tiles 0). Returns a projection-like dict."""
+    m = _f64(mean2d)
+    Y = _f64(conic)
+    d = _f64(depth)
+    N = m.shape[1]
+    TX, TY = tiles_of(cam)
+    rect = np.zeros((4, N), dtype=np.int32)
+    tiles = np.zeros(N, dtype=np.int32)
+    for n in range(N):
+        y00, y01, y11 = Y[0, n], Y[1, n], Y[2, n]
+        det = y00 * y11 - y01 * y01
+        if not valid[n] or not np.isfinite(det) or not det > 0.0 or not y00 > 0.0 or not y11 > 0.0:
+            continue
+        c00, c01, c11 = y11 / det, -y01 / det, y00 / det
+        if not (np.isfinite(c00) and np.isfinite(c01) and np.isfinite(c11) and np.isfinite(m[0, n])
+                and np.isfinite(m[1, n])):
+            continue
+        ex, ey = 3.0 * np.sqrt(c00), 3.0 * np.sqrt(c11)
+        if params.box_lambda_max:
+            h = (c00 - c11) / 2.0
+            ex = ey = 3.0 * np.sqrt((c00 + c11) / 2.0 + np.sqrt(h * h + c01 * c01))
+        x0, x1 = np.floor((m[0, n] - ex) / 16.0), np.floor((m[0, n] + ex) / 16.0)
+        y0, y1 = np.floor((m[1, n] - ey) / 16.0), np.floor((m[1, n] + ey) / 16.0)
+        if not (x1 >= 0 and y1 >= 0 and x0 <= TX - 1 and y0 <= TY - 1):
+            continue
+        r = (max(x0, 0), max(y0, 0), min(x1, TX - 1), min(y1, TY - 1))
+        rect[:, n] = r
+        tiles[n] = int((r[2] - r[0] + 1) * (r[3] - r[1] + 1))
+    return {"mean2d": m, "conic": Y, "depth": d, "rect": rect, "tiles": tiles}
+
+
 def rasterize_fwd(proj: dict, colors, opac, bins: dict, cam, params: Params) -> dict:
     colors, opac = _f64(colors), _f64(opac)
     N = opac.shape[0]

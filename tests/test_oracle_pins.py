@@ -552,6 +552,32 @@ def test_lambda_max_box_tile_pipeline_equals_global_sort():
     assert np.abs(out["C"] - ref["C"]).max() < 1e-12
     assert np.array_equal(out["last"], ref["last"])
 
+
+# ------------------------------------------------- per-stage form: splats from mu' and Y
+
+@pytest.mark.parametrize("box_lambda_max", [False, True])
+def test_splats_from_2d_reproduce_the_projection_box(box_lambda_max):
+    """Given the projection's own float64 mu' and Y, the box from Sigma' = Y^-1 is the
+    projection's box (which it decides on Sigma' itself), up to floors that land within
+    rounding of a tile edge; a wrong inversion (a transposed or swapped entry) moves boxes."""
+    wl = synth.tilted_camera_scene(45, n=300)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    prm = oracle.Params.standard(round_interface=False, box_lambda_max=box_lambda_max)
+    pr = oracle.project(scene, cam, prm)
+    valid = (pr["tiles"] > 0).astype(np.int32)
+    two = oracle.splats_from_2d(pr["mean2d"], pr["conic"], pr["depth"], valid, cam, prm)
+    same = np.all(two["rect"] == pr["rect"], axis=0) & (two["tiles"] == pr["tiles"])
+    assert valid.sum() > 150 and (~same).sum() <= 2
+    if not box_lambda_max:                         # the square is symmetric in the two axes
+        swapped = oracle.splats_from_2d(pr["mean2d"], pr["conic"][[2, 1, 0]], pr["depth"], valid, cam, prm)
+        assert (np.any(swapped["rect"] != pr["rect"], axis=0)).sum() > 20
+    # a culled slot stays culled, and the 2D splats render like the projected ones
+    assert np.all(two["tiles"][valid == 0] == 0)
+    b1, b2 = oracle.bin_and_sort(pr, cam), oracle.bin_and_sort(two, cam)
+    f1 = oracle.rasterize_fwd(pr, scene["colors"], scene["opacities"], b1, cam, prm)
+    f2 = oracle.rasterize_fwd(two, scene["colors"], scene["opacities"], b2, cam, prm)
+    assert np.abs(f1["C"] - f2["C"]).max() < 1e-6
+
 def test_conic_to_cov2d_gradient_by_fd():
     rng = np.random.default_rng(35)
     for _ in range(20):
