@@ -246,6 +246,23 @@ int gs_l2_grad(const float *image, const float *target, int64_t n, float *dL_dim
 int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
                gs_splats *out, void *stream);
 
+/*
+ * Per-stage form (the projection of Sec. 2.1 and the rasterizer of Sec. 2.2 as separate
+ * differentiable steps): writes the splats gs_bin_and_sort and the rasterizer read from
+ * given 2D quantities instead of projecting. Per slot p (slots as in gs_project):
+ *   mean2d [2][n_splats] mu', conic [3][n_splats] Y = (Y00, Y01, Y11), depth [n_splats],
+ *   valid [n_splats] int32 (0: the slot stays culled, e.g. where gs_project culled it).
+ * Colours and opacities come from the slot's scene Gaussian in g (means, quats, scales are
+ * not read). The 3-sigma box is decided on Sigma' = Y^-1, formed in float64 from the given
+ * float32 Y, with the box option of g->flags; a slot is culled where Y is not positive
+ * definite or its box misses the image. The rasterizer's gradients dL/dmu' and dL/dY then
+ * refer to these inputs. out->rec is not written. Errors: GS_ERR_INVALID for null pointers,
+ * bad sizes or misaligned planes.
+ */
+int gs_splats_from_2d(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
+                      const float *mean2d, const float *conic, const float *depth, const int32_t *valid,
+                      gs_splats *out, void *stream);
+
 /* Number of int32 entries of gs_bins.schedule for n_tiles tiles. */
 int64_t gs_schedule_size(int32_t n_tiles);
 

@@ -24,7 +24,7 @@ EXPORTED = (
     "gs_device_check", "gs_last_hip_error", "gs_last_error_message", "gs_version", "gs_zero", "gs_abi_layout",
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
     "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
-    "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning",
+    "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning", "gs_splats_from_2d",
 )
 
 
@@ -117,6 +117,7 @@ def lib():
         "gs_zero": (ctypes.c_int, [_P, ctypes.c_size_t, _P]),
         "gs_abi_layout": (ctypes.c_int, [_P, ctypes.c_int]),
         "gs_project": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P]),
+        "gs_splats_from_2d": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P, _P, _P, _P, _P]),
         "gs_bin_and_sort_workspace_size": (ctypes.c_size_t, [_I64, _I64, _I32]),
         "gs_schedule_size": (ctypes.c_int64, [_I32]),
         "gs_bin_and_sort": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P, ctypes.c_size_t, _P]),
@@ -169,6 +170,12 @@ def gs_zero(ptr: int, nbytes: int, stream: int):
 
 def gs_project(g: GsGaussians, cams_ptr: int, n_cams: int, n_splats: int, splats: GsSplats, stream: int):
     _check("gs_project", lib().gs_project(_ref(g), cams_ptr, n_cams, n_splats, _ref(splats), stream))
+
+
+def gs_splats_from_2d(g: GsGaussians, cams_ptr: int, n_cams: int, n_splats: int, mean2d: int, conic: int,
+                      depth: int, valid: int, splats: GsSplats, stream: int):
+    _check("gs_splats_from_2d", lib().gs_splats_from_2d(_ref(g), cams_ptr, n_cams, n_splats, mean2d, conic, depth,
+                                                        valid, _ref(splats), stream))
 
 
 def gs_schedule_size(n_tiles: int) -> int:

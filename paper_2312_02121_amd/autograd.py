@@ -9,6 +9,13 @@ state is stored.
 
 ``render`` is the user-facing wrapper: it takes parameter tensors and a list of cameras
 and returns one [3, H, W] image per camera.
+
+The per-stage form splits the same map at the 2D splats: ``ProjectGaussians`` (Sec. 2.1:
+means, quats, scales -> mu', Y, with gs_project and gs_project_bwd) and ``RasterizeSplats``
+(Sec. 2.2: mu', Y, colours, opacities -> image, with gs_splats_from_2d, the sort and the
+rasterizer; its backward gives dL/dmu' and dL/dY, Sec. 3.1). The 2D splats are ordinary
+tensors between the two, so they can be inspected, hooked or modified. ``render_stages``
+chains them.
 """
 from __future__ import annotations
 
@@ -62,4 +69,89 @@ def render(means: torch.Tensor, quats: torch.Tensor, scales: torch.Tensor, color
     cams = pipeline.CameraSet(cameras, sizes, device=means.device)
     params = params or pipeline.make_params()
     packed = RasterizeGaussians.apply(means, quats, scales, colors, opacities, cams, params, sizes, normalize_quats)
+    return [cams.unpack(packed, k) for k in range(cams.n_cams)]
+
+
+class ProjectGaussians(torch.autograd.Function):
+    """(means, quats, scales) -> mu' [2, P], Y [3, P], plus depth [P] and valid [P] (not
+    differentiable). P = sum over cameras of the scene size; a culled slot has valid 0. mu' and
+    Y hold the projection's float32 values in float64 tensors, so that their gradients reach
+    gs_project_bwd in float64 (dL/dSigma' = -Y dL/dY Y amplifies any rounding of dL/dY)."""
+
+    @staticmethod
+    def forward(ctx, means, quats, scales, colors, opacities, cams: pipeline.CameraSet, sizes: tuple,
+                normalize_quats: bool = False):
+        g = pipeline.GaussianSet.from_tensors(means.detach().contiguous(), quats.detach().contiguous(),
+                                              scales.detach().contiguous(), colors.detach().contiguous(),
+                                              opacities.detach().contiguous(), sizes, normalize_quats)
+        r = pipeline.Rasterizer(cams, capacity=1024, keep_records=True)
+        r.project(g)
+        P = cams.n_splats
+        rec = r.splats.rec[: P * 12].view(P, 12)
+        mean2d = rec[:, 0:2].t().to(torch.float64).contiguous()
+        conic = rec[:, 2:5].t().to(torch.float64).contiguous()
+        depth = r.splats.depth[:P].clone()
+        valid = (r.splats.tiles[:P] > 0).to(torch.int32)
+        ctx.rasterizer, ctx.gaussians = r, g
+        ctx.mark_non_differentiable(depth, valid)
+        return mean2d, conic, depth, valid
+
+    @staticmethod
+    def backward(ctx, d_mean2d, d_conic, _d_depth, _d_valid):
+        r, g = ctx.rasterizer, ctx.gaussians
+        cams, P = r.cams, r.cams.n_splats
+        dev = r.device
+        dm = (d_mean2d if d_mean2d is not None else torch.zeros(2, P, device=dev)).to(torch.float64).contiguous()
+        dc = (d_conic if d_conic is not None else torch.zeros(3, P, device=dev)).to(torch.float64).contiguous()
+        out = {k: torch.zeros(rows, g.n, device=dev) for k, rows in (("means", 3), ("scales", 3), ("quats", 4))}
+        stream = pipeline.current_stream()
+        abi.gs_project_bwd(g.struct(), cams.ptr, cams.n_cams, r.splats.struct(P), P, dm.data_ptr(), dc.data_ptr(),
+                           out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(), None, stream)
+        ctx.rasterizer = ctx.gaussians = None
+        return out["means"], out["quats"], out["scales"], None, None, None, None, None
+
+
+class RasterizeSplats(torch.autograd.Function):
+    """(mu' [2, P], Y [3, P], colours [3, N], opacities [N]; depth and valid per slot) ->
+    packed image [3, n_pixels]. mu' and Y are rounded to float32 for the kernels; the backward
+    returns dL/dmu' and dL/dY (computed in float64) in their dtype, and dL/dc, dL/do."""
+
+    @staticmethod
+    def forward(ctx, mean2d, conic, colors, opacities, depth, valid, cams: pipeline.CameraSet,
+                params: abi.GsParams, sizes: tuple, box_lambda_max: bool = False):
+        n = int(opacities.shape[-1])
+        dummy = torch.zeros(4, n, device=colors.device)
+        g = pipeline.GaussianSet.from_tensors(dummy[:3], dummy, dummy[:3], colors.detach().contiguous(),
+                                              opacities.detach().contiguous(), sizes)
+        g.box_lambda_max = bool(box_lambda_max)
+        key = (cams.n_splats, cams.n_tiles, "2d")
+        r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key))
+        st = r.forward_2d(g, mean2d.detach().to(torch.float32).contiguous(),
+                          conic.detach().to(torch.float32).contiguous(), depth.contiguous(), valid.contiguous())
+        _capacity_hint[key] = max(r.capacity, int(st.K * 1.1) + 1024)
+        ctx.state, ctx.rasterizer = st, r
+        ctx.dtypes = (mean2d.dtype, conic.dtype)
+        return st.image.clone()
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        gr = ctx.rasterizer.backward_2d(ctx.state, dL_dimage)
+        P = ctx.rasterizer.cams.n_splats
+        ctx.state = ctx.rasterizer = None
+        return (gr["mean2d"][:, :P].to(ctx.dtypes[0]), gr["conic"][:, :P].to(ctx.dtypes[1]), gr["colors"],
+                gr["opacities"], None, None, None, None, None, None)
+
+
+def render_stages(means, quats, scales, colors, opacities, cameras: Sequence, scene_sizes=None,
+                  params: abi.GsParams | None = None, normalize_quats: bool = False, splat_hook=None):
+    """``render`` through the two stages; ``splat_hook(mean2d, conic)`` may return modified
+    (mean2d, conic) tensors (differentiable) that the rasterizer then uses."""
+    sizes = tuple(scene_sizes) if scene_sizes is not None else (int(opacities.shape[-1]),)
+    cams = pipeline.CameraSet(cameras, sizes, device=means.device)
+    params = params or pipeline.make_params()
+    mean2d, conic, depth, valid = ProjectGaussians.apply(means, quats, scales, colors, opacities, cams, sizes,
+                                                         normalize_quats)
+    if splat_hook is not None:
+        mean2d, conic = splat_hook(mean2d, conic)
+    packed = RasterizeSplats.apply(mean2d, conic, colors, opacities, depth, valid, cams, params, sizes)
     return [cams.unpack(packed, k) for k in range(cams.n_cams)]

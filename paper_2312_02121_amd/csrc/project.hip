@@ -11,6 +11,52 @@
 
 namespace gsx {
 
+// Tile box of the 3-sigma ellipse of Sigma' = (C00, C01; C01, C11) around mu' on the 16x16
+// grid of the camera (Sec. 2.2): tight axis-aligned half extents 3 sqrt(C00), 3 sqrt(C11),
+// or with GS_BOX_LAMBDA_MAX a square from the largest eigenvalue. False when it misses the
+// image; otherwise box (clamped to the image) and its tile count.
+__device__ inline bool splat_box(double mu0, double mu1, double C00, double C01, double C11, const gs_camera &cam,
+                                 int flags, int4 &box, int32_t &tiles)
+{
+#pragma clang fp contract(off)
+    double ex = 3.0 * sqrt(C00), ey = 3.0 * sqrt(C11);
+    if (flags & GS_BOX_LAMBDA_MAX) {
+        // square from the largest eigenvalue of Sigma' (contains the tight box)
+        const double h = (C00 - C11) / 2.0;
+        const double lmax = (C00 + C11) / 2.0 + sqrt(h * h + C01 * C01);
+        ex = ey = 3.0 * sqrt(lmax);
+    }
+    const double TX = (double)cam.tiles_x, TY = (double)cam.tiles_y;
+    double x0 = floor((mu0 - ex) / 16.0), x1 = floor((mu0 + ex) / 16.0);
+    double y0 = floor((mu1 - ey) / 16.0), y1 = floor((mu1 + ey) / 16.0);
+    if (!(x1 >= 0.0 && y1 >= 0.0 && x0 <= TX - 1.0 && y0 <= TY - 1.0)) return false;
+    x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+    x1 = fmin(x1, TX - 1.0); y1 = fmin(y1, TY - 1.0);
+    box = make_int4((int)x0, (int)y0, (int)x1, (int)y1);
+    tiles = (box.z - box.x + 1) * (box.w - box.y + 1);
+    return true;
+}
+
+// Compositing record of a splat from its float32 mu', conic Y, opacity and colour.
+__device__ inline RasterRec make_record(float mx, float my, float y00, float y01, float y11, float o, float c0,
+                                        float c1, float c2, int src, int slot)
+{
+    RasterRec rr;
+    rr.mx = mx;
+    rr.my = my;
+    rr.lo = o > 0.f ? log2((double)o) : -INFINITY;
+    rr.A = -0.5 * kLog2eD * (double)y00;
+    rr.B = -kLog2eD * (double)y01;
+    rr.C = -0.5 * kLog2eD * (double)y11;
+    rr.c0 = c0;
+    rr.c1 = c1;
+    rr.c2 = c2;
+    rr.o = o;
+    rr.src = src;
+    rr.slot = slot;
+    return rr;
+}
+
 __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
                                                       int n_cams, int64_t n_splats, float4 *__restrict__ rec,
                                                       RasterRec *__restrict__ rrec, float *__restrict__ depth_out,
@@ -101,40 +147,15 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
 
         if (visible) {
             // axis-aligned box of the 3-sigma ellipse on the 16x16 tile grid
-            double ex = 3.0 * sqrt(C00), ey = 3.0 * sqrt(C11);
-            if (g.flags & GS_BOX_LAMBDA_MAX) {
-                // square from the largest eigenvalue of Sigma' (contains the tight box)
-                const double h = (C00 - C11) / 2.0;
-                const double lmax = (C00 + C11) / 2.0 + sqrt(h * h + C01 * C01);
-                ex = ey = 3.0 * sqrt(lmax);
-            }
-            const double TX = (double)cam.tiles_x, TY = (double)cam.tiles_y;
-            double x0 = floor((mu0 - ex) / 16.0), x1 = floor((mu0 + ex) / 16.0);
-            double y0 = floor((mu1 - ey) / 16.0), y1 = floor((mu1 + ey) / 16.0);
-            visible = x1 >= 0.0 && y1 >= 0.0 && x0 <= TX - 1.0 && y0 <= TY - 1.0;
+            visible = splat_box(mu0, mu1, C00, C01, C11, cam, g.flags, box, tiles);
             if (visible) {
-                x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
-                x1 = fmin(x1, TX - 1.0); y1 = fmin(y1, TY - 1.0);
-                box = make_int4((int)x0, (int)y0, (int)x1, (int)y1);
-                tiles = (box.z - box.x + 1) * (box.w - box.y + 1);
                 dep = (float)tz;
                 const float y00 = (float)Y00, y01 = (float)Y01, y11 = (float)Y11;
                 const float o = g.opacities[i];
                 r0 = make_float4((float)mu0, (float)mu1, y00, y01);
                 r1 = make_float4(y11, o, g.colors[i], g.colors[n + i]);
                 r2 = make_float4(g.colors[2 * n + i], dep, __int_as_float((int)i), __int_as_float(c));
-                rr.mx = r0.x;
-                rr.my = r0.y;
-                rr.lo = o > 0.f ? log2((double)o) : -INFINITY;
-                rr.A = -0.5 * kLog2eD * (double)y00;
-                rr.B = -kLog2eD * (double)y01;
-                rr.C = -0.5 * kLog2eD * (double)y11;
-                rr.c0 = r1.z;
-                rr.c1 = r1.w;
-                rr.c2 = r2.x;
-                rr.o = o;
-                rr.src = (int)i;
-                rr.slot = (int)p;
+                rr = make_record(r0.x, r0.y, y00, y01, y11, o, r1.z, r1.w, r2.x, (int)i, (int)p);
             }
         }
     }
@@ -152,9 +173,70 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     }
 }
 
+// Splats from given 2D quantities (the per-stage form): mu' [2][n_splats], Y [3][n_splats]
+// and depth [n_splats] per slot, colours and opacities from the slot's scene Gaussian. The
+// slot keeps its projection only where valid[p] != 0; Sigma' = Y^-1 in float64 from the
+// float32 conic decides the box, as the projection decides it from its own Sigma'.
+__global__ __launch_bounds__(256) void splats_from_2d_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
+                                                             int n_cams, int64_t n_splats,
+                                                             const float *__restrict__ mean2d,
+                                                             const float *__restrict__ conic,
+                                                             const float *__restrict__ depth_in,
+                                                             const int32_t *__restrict__ valid,
+                                                             RasterRec *__restrict__ rrec, float *__restrict__ depth_out,
+                                                             int4 *__restrict__ rect_out, int32_t *__restrict__ tiles_out)
+{
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_splats) return;
+    const int c = camera_of_splat(cams, n_cams, p);
+    const gs_camera &cam = cams[c];
+    const int64_t n = g.n;
+    const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
+    const float m0 = mean2d[p], m1 = mean2d[n_splats + p];
+    const float y00 = conic[p], y01 = conic[n_splats + p], y11 = conic[2 * n_splats + p];
+    const double Y00 = y00, Y01 = y01, Y11 = y11;
+    const double det = Y00 * Y11 - Y01 * Y01;
+    const double C00 = Y11 / det, C01 = -Y01 / det, C11 = Y00 / det;
+    int4 box = make_int4(0, 0, 0, 0);
+    int32_t tiles = 0;
+    bool visible = valid[p] != 0 && isfinite((double)m0) && isfinite((double)m1) && isfinite(det) && det > 0.0 &&
+                   Y00 > 0.0 && Y11 > 0.0 && isfinite(C00) && isfinite(C01) && isfinite(C11);
+    if (visible) visible = splat_box(m0, m1, C00, C01, C11, cam, g.flags, box, tiles);
+    tiles_out[p] = visible ? tiles : 0;
+    if (visible) {
+        const float o = g.opacities[i];
+        rrec[p] = make_record(m0, m1, y00, y01, y11, o, g.colors[i], g.colors[n + i], g.colors[2 * n + i], (int)i,
+                              (int)p);
+        depth_out[p] = depth_in[p];
+        rect_out[p] = box;
+    }
+}
+
 }  // namespace gsx
 
 using namespace gsx;
+
+extern "C" int gs_splats_from_2d(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
+                                 const float *mean2d, const float *conic, const float *depth, const int32_t *valid,
+                                 gs_splats *out, void *stream)
+{
+    clear_error();
+    if (!g || !cams || !out || n_cams < 1 || n_splats < 0)
+        return set_error(GS_ERR_INVALID, "gs_splats_from_2d: null argument or bad size");
+    if (n_splats > out->capacity)
+        return set_error(GS_ERR_INVALID, "gs_splats_from_2d: n_splats exceeds splat capacity");
+    if (n_splats == 0) return GS_OK;
+    if (!mean2d || !conic || !depth || !valid || !g->colors || !g->opacities || g->n < 1 || !out->raster ||
+        !out->depth || !out->rect || !out->tiles_touched)
+        return set_error(GS_ERR_INVALID, "gs_splats_from_2d: null plane");
+    if ((((uintptr_t)out->rect) & 15) || (((uintptr_t)out->raster) & 63))
+        return set_error(GS_ERR_INVALID, "gs_splats_from_2d: rect must be 16-byte and raster 64-byte aligned");
+    hipLaunchKernelGGL(splats_from_2d_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream, *g,
+                       cams, (int)n_cams, n_splats, mean2d, conic, depth, valid, (RasterRec *)out->raster, out->depth,
+                       (int4 *)out->rect, out->tiles_touched);
+    return check_launch("gs_splats_from_2d");
+}
 
 extern "C" int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_cams, int64_t n_splats,
                           gs_splats *out, void *stream)

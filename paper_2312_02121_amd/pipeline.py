@@ -280,6 +280,45 @@ class Rasterizer:
         return ForwardState(g, self.cams, self.params, self.splats, self.bins, self.image, self.T_final,
                             self.last, self.visited, K)
 
+    def forward_2d(self, g: GaussianSet, mean2d: torch.Tensor, conic: torch.Tensor, depth: torch.Tensor,
+                   valid: torch.Tensor) -> ForwardState:
+        """Per-stage forward: splats from given mu' [2, P], Y [3, P], depth [P] and valid [P]
+        (gs_splats_from_2d) instead of the projection, then bin, sort and rasterize."""
+        P = self.cams.n_splats
+        for name, t, shape, dt in (("mean2d", mean2d, (2, P), torch.float32), ("conic", conic, (3, P), torch.float32),
+                                   ("depth", depth, (P,), torch.float32), ("valid", valid, (P,), torch.int32)):
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor of shape {shape}")
+        abi.gs_splats_from_2d(g.struct(), self.cams.ptr, self.cams.n_cams, P, _ptr(mean2d), _ptr(conic), _ptr(depth),
+                              _ptr(valid), self.splats.struct(P), current_stream())
+        self.bin_and_sort()
+        K, over = self.read_count()
+        if over:
+            self.capacity = int(K * 1.25) + 1024
+            self.bins = Bins.alloc(P, self.capacity, self.cams.n_tiles, self.device)
+            self.bin_and_sort()
+            K, over = self.read_count()
+            assert not over
+        self.rasterize_fwd()
+        return ForwardState(g, self.cams, self.params, self.splats, self.bins, self.image, self.T_final,
+                            self.last, self.visited, K)
+
+    def backward_2d(self, state: ForwardState, dL_dimage: torch.Tensor, stream: int | None = None) -> dict:
+        """Rasterizer backward only: dL/dmu' [2, P] and dL/dY [3, P] (float64) per slot,
+        dL/dc and dL/do per scene Gaussian."""
+        stream = current_stream() if stream is None else stream
+        g, cams, P = state.gaussians, self.cams, self.cams.n_splats
+        dev = self.device
+        dL_dimage = dL_dimage.contiguous().to(torch.float32)
+        grads = {"mean2d": torch.zeros(2, max(P, 1), dtype=torch.float64, device=dev),
+                 "conic": torch.zeros(3, max(P, 1), dtype=torch.float64, device=dev),
+                 "colors": torch.zeros(3, g.n, device=dev), "opacities": torch.zeros(g.n, device=dev)}
+        abi.gs_rasterize_bwd(state.splats.struct(P), P, state.bins.struct(), cams.ptr, cams.n_cams, state.params,
+                             cams.n_pixels, _ptr(dL_dimage), _ptr(state.T_final), _ptr(state.last),
+                             _ptr(grads["mean2d"]), _ptr(grads["conic"]), g.n, _ptr(grads["colors"]),
+                             _ptr(grads["opacities"]), stream)
+        return grads
+
     # ---------------------------------------------------------------------- backward
     def backward(self, state: ForwardState, dL_dimage: torch.Tensor, with_pose: bool = False,
                  stream: int | None = None) -> dict:
