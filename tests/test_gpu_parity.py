@@ -187,6 +187,7 @@ def test_normalized_quats_projection_image_and_gradients(name):
     rng = np.random.default_rng(5)
     wl.scenes = [dict(sc, quats=(sc["quats"] * rng.uniform(0.5, 2.0, sc["quats"].shape[1])).astype(np.float32))
                  for sc in base.scenes]
+    wl.scenes[0]["quats"][:, 0] = 0.0            # no direction: culled on both sides
     r, st = gpu_forward(wl, normalize_quats=True)
     prm = oracle_params(normalize_quats=True)
     check_projection(wl, r, prm=prm)
