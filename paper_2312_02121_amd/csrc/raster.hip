@@ -16,10 +16,13 @@
 //
 // Records. A wave walks its list in batches of 64 entries. For each batch every lane
 // gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
-// into the wave's own LDS slice; the next batch is gathered into registers while the
-// current one is composited, so the random record reads stay off the critical path. The
-// walk then reads each record back with broadcast LDS loads. No workgroup barrier is ever
-// needed: a wave only reads the LDS slice it wrote. Per lane and splat the row terms
+// into registers, one batch ahead, so the random record reads stay off the critical path.
+// Each lane then tests its record against the rectangle of the wave's pixel centres;
+// records that cannot reach alpha_min there are dropped, and the rest are staged packed,
+// in list order, into the wave's own LDS slice (the forward pads them to a multiple of 8
+// with null records and composites groups of 8 as straight-line code). The walk reads each
+// record back with broadcast LDS loads. No workgroup barrier is ever needed: a wave only
+// reads the LDS slice it wrote. Per lane and splat the row terms
 // lo + C dy^2 and B dy are formed once and shared by the lane's pixels; per pixel the
 // exponent costs one subtraction and two FMAs in float64 (exact Delta, no cancellation
 // loss), one conversion and a float32 exp2. Compositing is branch-free: a pixel that
