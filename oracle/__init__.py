@@ -63,7 +63,8 @@ class _Params(ctypes.Structure):
                 ("margin_T", ctypes.c_double), ("margin_clamp", ctypes.c_double),
                 ("round_interface", ctypes.c_int32), ("errata", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("normalize_quats", ctypes.c_int32),
-                ("background", ctypes.c_double * 3), ("box_lambda_max", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("background", ctypes.c_double * 3), ("box_lambda_max", ctypes.c_int32), ("pad2", ctypes.c_int32),
+                ("round_T", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -128,6 +129,7 @@ class Params:
     background: tuple = (0.0, 0.0, 0.0)   # colour seen through T_final; zero in the paper
     normalize_quats: bool = False         # R(q / |q|); the paper takes q as given
     box_lambda_max: bool = False          # square 3-sigma box from lambda_max (tight box otherwise)
+    round_T: float = 0.0                  # rounding bound of one float32 update of T (near-tie flags)
 
     @staticmethod
     def standard(**kw) -> "Params":
@@ -146,7 +148,7 @@ class Params:
                        self.margin_clamp, int(bool(self.round_interface)), int(self.errata),
                        int(self.n_threads), int(bool(self.normalize_quats)),
                        (ctypes.c_double * 3)(*[float(x) for x in self.background]),
-                       int(bool(self.box_lambda_max)), 0)
+                       int(bool(self.box_lambda_max)), 0, float(self.round_T))
 
 
 def camera_struct(cam) -> _Camera:

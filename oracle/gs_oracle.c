@@ -74,13 +74,19 @@ typedef struct {
 
 typedef struct {
     double alpha_min, alpha_max, T_min;
-    double margin_alpha;   /* flag a pixel if |alpha - alpha_min| <= margin_alpha * alpha_min */
-    double margin_T;       /* ... or |T (1 - alpha) - T_min| <= (margin_T + e_T) * T_min, where
-                              e_T = sum over the factors of T (1 - alpha) of
-                                    margin_alpha * alpha / (1 - alpha) + 2^-22:
-                              a bound on the relative error of a float32 product of those
-                              factors whose alphas carry relative errors up to margin_alpha
-                              (e_T is taken as 0 when margin_T is 0) */
+    /* Near-tie flags. A float32 implementation takes the skip, termination and clamp
+     * decisions on rounded values; a pixel whose exact decision quantity lies within the
+     * implementation's error bound of a threshold may go either way there, and is flagged.
+     * The bounds describe that implementation and are passed in by the caller: */
+    double margin_alpha;   /* relative error bound of its alpha: flag a pixel if
+                              |alpha - alpha_min| <= margin_alpha * alpha_min */
+    double margin_T;       /* ... or |T (1 - alpha) - T_min| <= e_T * max(T (1 - alpha), T_min), with
+                              e_T = margin_T + sum over the factors of T (1 - alpha) so far of
+                                    round_T + (alpha clamped ? 0 : margin_alpha * alpha / (1 - alpha)):
+                              a first-order bound on the relative error of its product T,
+                              each factor carrying one rounding of the update (round_T) and the
+                              error of its alpha, which a clamped alpha (exactly alpha_max)
+                              does not have (e_T is taken as 0 when margin_T is 0) */
     double margin_clamp;   /* ... or |o exp(-sigma) - alpha_max| <= margin_clamp */
     int32_t round_interface; /* round mu', Y, depth to float32 where the HIP path stores them */
     int32_t errata;
@@ -89,6 +95,7 @@ typedef struct {
     double background[3];  /* bg, zero for the paper's image formation */
     int32_t box_lambda_max;  /* 1: square 3-sigma box from the largest eigenvalue of Sigma' */
     int32_t pad2;
+    double round_T;        /* relative rounding bound of one float32 update of T (see margin_T) */
 } orc_params;
 
 /* ------------------------------------------------------------------ small linear algebra */
@@ -422,7 +429,7 @@ void orc_rasterize_fwd(int64_t N, const double *mean2d, const double *conic, con
             const int64_t pix = i * W + j;
             const int64_t tile = (i / ORC_TILE) * TX + (j / ORC_TILE);
             const double px = (double)j + 0.5, py = (double)i + 0.5;
-            double T = 1.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, eT = 0.0;
+            double T = 1.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, eT = prm->margin_T;
             int32_t nlast = 0, nvis = 0, fl = 0;
             const int64_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
             for (int64_t k = start; k < end; ++k) {
@@ -436,8 +443,10 @@ void orc_rasterize_fwd(int64_t N, const double *mean2d, const double *conic, con
                 if (fabs(alpha - prm->alpha_min) <= prm->margin_alpha * prm->alpha_min) fl |= 1;
                 if (alpha < prm->alpha_min) continue;
                 const double Tn = T * (1.0 - alpha);
-                const double eTn = prm->margin_T > 0.0 ? eT + prm->margin_alpha * alpha / (1.0 - alpha) + 0x1p-22 : 0.0;
-                if (fabs(Tn - prm->T_min) <= (prm->margin_T + eTn) * prm->T_min) fl |= 2;
+                const double eTn = prm->margin_T > 0.0
+                    ? eT + prm->round_T + (a_raw >= prm->alpha_max ? 0.0 : prm->margin_alpha * alpha / (1.0 - alpha))
+                    : 0.0;
+                if (fabs(Tn - prm->T_min) <= eTn * (Tn > prm->T_min ? Tn : prm->T_min)) fl |= 2;
                 if (Tn < prm->T_min) break;
                 eT = eTn;
                 c0 += colors[g] * alpha * T;

@@ -657,3 +657,198 @@ def test_golden_closed_form_fixture():
             i, j = case["pixel"]
             assert np.allclose(out["C"][:, i, j], case["expected_rgb"], rtol=0, atol=1e-14)
             assert abs(out["T_final"][i, j] - case["expected_T"]) < 1e-15
+
+
+# ------------------------------------------------- several cameras in one key space
+
+@pytest.mark.parametrize("offset", [1, 4096, 57600 - 12])
+def test_tile_offset_shifts_keys_and_keeps_ranges(offset):
+    """A camera placed at tile offset k in a shared key space sorts exactly as on its own:
+    keys are the plain keys plus k << 32, ids and per-camera ranges are unchanged, and so
+    is the image (Sec. 2.2 sorts per tile; the offset only renames the tiles)."""
+    for wl in (synth.tiny_scene(41, n=60), synth.tilted_camera_scene(42, n=60)):
+        scene, cam = wl.scenes[0], wl.cameras[0]
+        prm = oracle.Params.standard()
+        plain = oracle.render(scene, cam, prm)
+        shifted = oracle.render(scene, cam, prm, tile_offset=offset)
+        K = plain["bins"]["K"]
+        assert K > 0 and shifted["bins"]["K"] == K
+        assert np.array_equal(shifted["bins"]["keys"], plain["bins"]["keys"] + (np.uint64(offset) << np.uint64(32)))
+        assert np.array_equal(shifted["bins"]["ids"], plain["bins"]["ids"])
+        assert np.array_equal(shifted["bins"]["ranges"], plain["bins"]["ranges"])
+        for name in ("C", "T_final", "last", "visited"):
+            assert np.array_equal(shifted[name], plain[name])
+
+
+def test_tile_ranges_ignore_other_cameras_keys():
+    """Two cameras' keys in one sorted list: each camera's ranges, taken with its own offset,
+    index exactly its own runs (and keys of the other camera are skipped)."""
+    wa, wb = synth.tiny_scene(43, n=50), synth.tilted_camera_scene(44, n=50)
+    prm = oracle.Params.standard()
+    ra = oracle.render(wa.scenes[0], wa.cameras[0], prm)
+    nta = wa.cameras[0].tiles_x * wa.cameras[0].tiles_y
+    rb = oracle.render(wb.scenes[0], wb.cameras[0], prm, tile_offset=nta)
+    keys = np.concatenate([ra["bins"]["keys"], rb["bins"]["keys"]])
+    lib = oracle.lib()
+    for r, cam, off in ((ra, wa.cameras[0], 0), (rb, wb.cameras[0], nta)):
+        nt = cam.tiles_x * cam.tiles_y
+        got = np.zeros((nt, 2), dtype=np.int64)
+        lib.orc_tile_ranges(keys.size, oracle._ptr(keys), nt, off, oracle._ptr(got))
+        base = 0 if off == 0 else ra["bins"]["K"]
+        want = r["bins"]["ranges"].copy()
+        nonempty = want[:, 1] > want[:, 0]
+        want[nonempty] += base
+        assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------ near-tie decision flags
+
+def _stack_at_pixel_centre(opacities, depth0=4.0, scale=0.05):
+    """Gaussians on the optical axis of the 64x64 test camera, one behind the other:
+    mu' = (32.5, 32.5), the centre of pixel (row 32, col 32), so alpha there is o exactly
+    (sigma = 0)."""
+    n = len(opacities)
+    return {"means": np.array([[0.0] * n, [0.0] * n, [depth0 + k for k in range(n)]], np.float32),
+            "quats": np.array([[1.0] * n, [0.0] * n, [0.0] * n, [0.0] * n], np.float32),
+            "scales": np.full((3, n), scale, np.float32),
+            "colors": np.full((3, n), 0.5, np.float32),
+            "opacities": np.array(opacities, np.float32)}
+
+
+FLAG_PRM = dict(margin_alpha=3e-7, margin_T=1e-7, margin_clamp=3e-7, round_T=2.0 ** -24)
+
+
+def _flag_at_centre(opacities, **kw):
+    prm = oracle.Params.standard(**{**FLAG_PRM, **kw})
+    out = oracle.render(_stack_at_pixel_centre(opacities), _cam(), prm)
+    return int(out["flags"][32, 32]), out
+
+
+def test_flags_catch_alpha_min_tie_and_spare_clear_pixel():
+    a_min = np.float32(1.0 / 255.0)
+    tie = np.nextafter(a_min, np.float32(1))           # alpha = o = alpha_min (1 + 2.3e-7)
+    fl, out = _flag_at_centre([tie])
+    assert fl & 1 and out["last"][32, 32] == 1
+    fl, out = _flag_at_centre([np.nextafter(a_min, np.float32(0))])   # just below: skipped
+    assert fl & 1 and out["last"][32, 32] == 0 and out["visited"][32, 32] == 1
+    fl, _ = _flag_at_centre([a_min * np.float32(1.01)])
+    assert fl == 0
+    fl, _ = _flag_at_centre([tie], margin_alpha=0.0)    # no margin: exact decisions, no flag
+    assert fl == 0
+
+
+def test_flags_catch_alpha_max_tie_and_spare_clear_pixel():
+    a_max = np.float32(0.99)
+    for o in (np.nextafter(a_max, np.float32(1)), np.nextafter(a_max, np.float32(0))):
+        fl, _ = _flag_at_centre([o])
+        assert fl & 4
+    fl, _ = _flag_at_centre([np.float32(0.995)])
+    assert fl == 0
+    fl, _ = _flag_at_centre([np.float32(0.95)])
+    assert fl == 0
+
+
+def _opacity_for_T(T_before, target):
+    """The float32 opacity o with T_before (1 - o) closest to target (searched over
+    neighbouring float32 values)."""
+    o = np.float32(1.0 - target / T_before)
+    best = o
+    for _ in range(64):
+        cands = [np.nextafter(best, np.float32(0)), best, np.nextafter(best, np.float32(1))]
+        errs = [abs(T_before * (1.0 - np.float64(c)) - target) for c in cands]
+        nxt = cands[int(np.argmin(errs))]
+        if nxt == best:
+            break
+        best = nxt
+    return best
+
+
+def test_flags_catch_T_min_tie_and_spare_clear_pixel():
+    """Four Gaussians on one pixel: the fourth brings T within a float32 rounding of T_min
+    (flagged, whether it terminates or not), or clearly above or below it (not flagged, and
+    the termination rule decides: stop before the entry that would take T below T_min)."""
+    T_min = np.float64(np.float32(1e-4))
+    front = [np.float32(0.9)] * 3
+    T3 = np.prod(1.0 - np.array(front, np.float64))
+    for rel, tie in ((1e-6, True), (-1e-6, True), (2e-3, False), (-2e-3, False)):
+        o4 = _opacity_for_T(T3, T_min * (1.0 + rel))
+        Tn = T3 * (1.0 - np.float64(o4))
+        assert abs(Tn / T_min - 1.0 - rel) < 1e-6           # the float32 o4 lands where asked
+        fl, out = _flag_at_centre(front + [o4])
+        assert bool(fl & 2) == tie, (rel, fl)
+        assert out["last"][32, 32] == (4 if Tn >= T_min else 3)
+    # the band grows with the factors before the decision: the same relative distance is a
+    # tie behind many translucent factors and clear behind few
+    many = [np.float32(0.5)] * 12
+    T12 = np.prod(1.0 - np.array(many, np.float64))
+    o_last = _opacity_for_T(T12, T_min * (1.0 + 1.2e-6))
+    fl, _ = _flag_at_centre(many + [o_last])
+    assert fl & 2
+    fl, _ = _flag_at_centre(many + [o_last], round_T=0.0, margin_alpha=0.0)
+    assert not fl & 2
+
+
+def _float32_walk(pr, scene, cam, prm, rel_alpha_err, rng):
+    """A float32 implementation of the compositing decisions (Sec. 2.2): alpha rounded to
+    float32 after a relative error drawn from [-rel_alpha_err, rel_alpha_err] (unclamped
+    alphas only; a clamped alpha is alpha_max exactly), T updated as one rounding of
+    T (1 - alpha), the skip, clamp and stop rules of the standard mode. Global depth order
+    over the tile-box predicate, vectorised over pixels. Returns `last` per pixel."""
+    W, H = cam.width, cam.height
+    jj, ii = np.meshgrid(np.arange(W), np.arange(H))
+    px, py = jj + 0.5, ii + 0.5
+    tx, ty = jj // 16, ii // 16
+    N = pr["depth"].shape[0]
+    order = np.lexsort((np.arange(N), pr["depth"].astype(np.float32)))
+    a_max, a_min, T_min = np.float32(prm.alpha_max), np.float32(prm.alpha_min), np.float32(prm.T_min)
+    T = np.ones((H, W), np.float32)
+    done = np.zeros((H, W), bool)
+    count = np.zeros((H, W), np.int64)
+    last = np.zeros((H, W), np.int64)
+    op = scene["opacities"].astype(np.float64)
+    for n in order:
+        inc = brute.tile_box_covers(pr["rect"], pr["tiles"], n, tx, ty)
+        if not inc.any():
+            continue
+        dx, dy = pr["mean2d"][0, n] - px, pr["mean2d"][1, n] - py
+        c = pr["conic"][:, n]
+        raw = op[n] * np.exp(-0.5 * (c[0] * dx * dx + 2.0 * c[1] * dx * dy + c[2] * dy * dy))
+        raw32 = np.float32(raw * (1.0 + rng.uniform(-rel_alpha_err, rel_alpha_err, raw.shape)))
+        a = np.minimum(raw32, a_max)
+        count = count + inc
+        keep = inc & ~done & ~(a < a_min)
+        Tn = np.float32(T.astype(np.float64) * (1.0 - a.astype(np.float64)))
+        stop = keep & (Tn < T_min)
+        done |= stop
+        keep &= ~stop
+        T = np.where(keep, Tn, T)
+        last = np.where(keep, count, last)
+    return last
+
+
+@pytest.mark.parametrize("seed", [51, 52])
+def test_flags_bound_every_float32_decision_flip(seed):
+    """Soundness of the flags: a float32 walk whose alphas carry relative errors up to the
+    margin decides every unflagged pixel exactly as the FP64 oracle. The alpha error is taken
+    large here (1e-3, far above float32 rounding) so that near-ties are frequent (hundreds of
+    decisions flip between the walks); with a margin 30 times smaller than the error, flips
+    land on unflagged pixels (the test has teeth)."""
+    wl = synth.tiny_scene(seed, n=2000, width=128, height=96, f=102.4, log_scale=(-2.0, 0.3), opac_sd=3.0)
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    err = 1e-3
+    prm = oracle.Params.standard(margin_alpha=err, margin_T=1e-7, margin_clamp=err, round_T=2.0 ** -24)
+    out = oracle.render(scene, cam, prm)
+    flagged = out["flags"] != 0
+    weak = oracle.render(scene, cam, oracle.Params.standard(margin_alpha=err / 30, margin_T=1e-7,
+                                                             margin_clamp=err / 30, round_T=2.0 ** -24))
+    weak_flagged = weak["flags"] != 0
+    rng = np.random.default_rng(seed)
+    flips_weak = 0
+    flips = 0
+    for _ in range(4):
+        last = _float32_walk(out["proj"], scene, cam, prm, err, rng)
+        diff = last != out["last"]
+        assert not (diff & ~flagged).any(), int((diff & ~flagged).sum())
+        flips += int(diff.sum())
+        flips_weak += int((diff & ~weak_flagged).sum())
+    assert flips > 100 and flips_weak > 100
