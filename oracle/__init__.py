@@ -98,6 +98,8 @@ def lib():
         L.orc_conic_grad_to_cov2d.argtypes = [_P, _P, _P]
         L.orc_project_state.restype = ctypes.c_int
         L.orc_project_state.argtypes = [_P, _P, _P, _P, _P, _P]
+        L.orc_rasterize_tiles.restype = ctypes.c_double
+        L.orc_rasterize_tiles.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P]
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -290,6 +292,29 @@ def rasterize_fwd(proj: dict, colors, opac, bins: dict, cam, params: Params) -> 
     return out
 
 
+def rasterize_tiles(mean2d, conic, colors, opac, ids, ranges, cam, params: Params, tiles, target=None) -> dict:
+    """eq. (7) on the tiles ``tiles`` (tile indices of ``cam``) only, each with its list
+    ids[ranges[t, 0]:ranges[t, 1]] into the given per-splat arrays. Returns C [3, n, 16, 16],
+    T_final, last, flags [n, 16, 16] (pixels past the image edge hold zeros) and, with a
+    target [3, H*W] (or [3, H, W]), loss = sum over the tiles' pixels of (C - target)^2."""
+    mean2d, conic, colors, opac = _f64(mean2d), _f64(conic), _f64(colors), _f64(opac)
+    ids = np.ascontiguousarray(ids, dtype=np.int32) if len(ids) else np.zeros(1, np.int32)
+    ranges = np.ascontiguousarray(ranges, dtype=np.int64)
+    sel = np.ascontiguousarray(tiles, dtype=np.int64)
+    n = sel.size
+    W, H = int(cam.width), int(cam.height)
+    out = {"C": np.zeros((3, n, 16, 16)), "T_final": np.zeros((n, 16, 16)),
+           "last": np.zeros((n, 16, 16), np.int32), "flags": np.zeros((n, 16, 16), np.int32)}
+    tgt = None if target is None else _f64(np.asarray(target).reshape(3, -1))
+    ps = params.c()
+    out["loss"] = lib().orc_rasterize_tiles(opac.shape[0], _ptr(mean2d), _ptr(conic), _ptr(colors), _ptr(opac),
+                                            _ptr(ids), _ptr(ranges), W, H, ctypes.byref(ps), n,
+                                            _ptr(sel) if n else None, _ptr(tgt) if tgt is not None else None,
+                                            _ptr(out["C"]), _ptr(out["T_final"]), _ptr(out["last"]),
+                                            _ptr(out["flags"]))
+    return out
+
+
 def rasterize_bwd(proj: dict, colors, opac, bins: dict, cam, params: Params, dL_dC, fwd: dict,
                   form: int = 0) -> dict:
     colors, opac = _f64(colors), _f64(opac)
@@ -300,7 +325,7 @@ def rasterize_bwd(proj: dict, colors, opac, bins: dict, cam, params: Params, dL_
          "opacities": np.zeros(N)}
     ids = bins["ids"] if bins["K"] else np.zeros(1, dtype=np.int32)
     ps = params.c()
-    lib().orc_rasterize_bwd(N, _ptr(proj["mean2d"]), _ptr(proj["conic"]), _ptr(colors), _ptr(opac),
+    lib().orc_rasterize_bwd(N, _ptr(_f64(proj["mean2d"])), _ptr(_f64(proj["conic"])), _ptr(colors), _ptr(opac),
                             bins["K"], _ptr(ids), _ptr(bins["ranges"]), W, H, ctypes.byref(ps),
                             _ptr(dL_dC), _ptr(_f64(fwd["T_final"])),
                             _ptr(np.ascontiguousarray(fwd["last"], dtype=np.int32)), form,

@@ -408,12 +408,54 @@ static double sigma_of(const double *Y3, double dx, double dy)
     return 0.5 * (dx * (Y3[0] * dx + Y3[1] * dy) + dy * (Y3[1] * dx + Y3[2] * dy));
 }
 
+/* eq. (7) for one pixel with centre (px, py) over the list entries [start, end): outputs
+ * the colour (background seen through T_final), T_final, last (one past the list position
+ * of the last composited entry), visited (entries whose alpha was evaluated, including a
+ * terminating one) and flags (near-tie decisions: 1 skip threshold, 2 termination,
+ * 4 clamp). */
+static void composite_pixel(int64_t N, const double *mean2d, const double *conic, const double *colors,
+                            const double *opac, const int32_t *ids, int64_t start, int64_t end,
+                            double px, double py, const orc_params *prm,
+                            double *rgb, double *T_out, int32_t *last, int32_t *visited, int32_t *flags)
+{
+    double T = 1.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, eT = prm->margin_T;
+    int32_t nlast = 0, nvis = 0, fl = 0;
+    for (int64_t k = start; k < end; ++k) {
+        const int32_t g = ids[k];
+        const double Y3[3] = {conic[g], conic[N + g], conic[2 * N + g]};
+        const double dx = mean2d[g] - px, dy = mean2d[N + g] - py;
+        const double a_raw = opac[g] * exp(-sigma_of(Y3, dx, dy));
+        ++nvis;
+        if (fabs(a_raw - prm->alpha_max) <= prm->margin_clamp) fl |= 4;
+        const double alpha = a_raw < prm->alpha_max ? a_raw : prm->alpha_max;
+        if (fabs(alpha - prm->alpha_min) <= prm->margin_alpha * prm->alpha_min) fl |= 1;
+        if (alpha < prm->alpha_min) continue;
+        const double Tn = T * (1.0 - alpha);
+        const double eTn = prm->margin_T > 0.0
+            ? eT + prm->round_T + (a_raw >= prm->alpha_max ? 0.0 : prm->margin_alpha * alpha / (1.0 - alpha))
+            : 0.0;
+        if (fabs(Tn - prm->T_min) <= eTn * (Tn > prm->T_min ? Tn : prm->T_min)) fl |= 2;
+        if (Tn < prm->T_min) break;
+        eT = eTn;
+        c0 += colors[g] * alpha * T;
+        c1 += colors[N + g] * alpha * T;
+        c2 += colors[2 * N + g] * alpha * T;
+        T = Tn;
+        nlast = (int32_t)(k - start + 1);
+    }
+    rgb[0] = c0 + T * prm->background[0];
+    rgb[1] = c1 + T * prm->background[1];
+    rgb[2] = c2 + T * prm->background[2];
+    *T_out = T;
+    *last = nlast;
+    *visited = nvis;
+    *flags = fl;
+}
+
 /*
  * eq. (7) per pixel over its tile's depth-ordered list.
- * colors [3][N], opac [N] are per projected Gaussian. Outputs C [3][W*H], T_final,
- * last (one past the list position of the last composited entry), visited (entries
- * whose alpha was evaluated, including a terminating one) and flags (near-tie
- * decisions: 1 skip threshold, 2 termination, 4 clamp).
+ * colors [3][N], opac [N] are per projected Gaussian. Outputs C [3][W*H], T_final, last,
+ * visited and flags per pixel (see composite_pixel; visited and flags may be NULL).
  */
 void orc_rasterize_fwd(int64_t N, const double *mean2d, const double *conic, const double *colors,
                        const double *opac, const int32_t *ids, const int64_t *ranges,
@@ -428,42 +470,73 @@ void orc_rasterize_fwd(int64_t N, const double *mean2d, const double *conic, con
         for (int64_t j = 0; j < W; ++j) {
             const int64_t pix = i * W + j;
             const int64_t tile = (i / ORC_TILE) * TX + (j / ORC_TILE);
-            const double px = (double)j + 0.5, py = (double)i + 0.5;
-            double T = 1.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, eT = prm->margin_T;
-            int32_t nlast = 0, nvis = 0, fl = 0;
-            const int64_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-            for (int64_t k = start; k < end; ++k) {
-                const int32_t g = ids[k];
-                const double Y3[3] = {conic[g], conic[N + g], conic[2 * N + g]};
-                const double dx = mean2d[g] - px, dy = mean2d[N + g] - py;
-                const double a_raw = opac[g] * exp(-sigma_of(Y3, dx, dy));
-                ++nvis;
-                if (fabs(a_raw - prm->alpha_max) <= prm->margin_clamp) fl |= 4;
-                const double alpha = a_raw < prm->alpha_max ? a_raw : prm->alpha_max;
-                if (fabs(alpha - prm->alpha_min) <= prm->margin_alpha * prm->alpha_min) fl |= 1;
-                if (alpha < prm->alpha_min) continue;
-                const double Tn = T * (1.0 - alpha);
-                const double eTn = prm->margin_T > 0.0
-                    ? eT + prm->round_T + (a_raw >= prm->alpha_max ? 0.0 : prm->margin_alpha * alpha / (1.0 - alpha))
-                    : 0.0;
-                if (fabs(Tn - prm->T_min) <= eTn * (Tn > prm->T_min ? Tn : prm->T_min)) fl |= 2;
-                if (Tn < prm->T_min) break;
-                eT = eTn;
-                c0 += colors[g] * alpha * T;
-                c1 += colors[N + g] * alpha * T;
-                c2 += colors[2 * N + g] * alpha * T;
-                T = Tn;
-                nlast = (int32_t)(k - start + 1);
-            }
-            C[pix] = c0 + T * prm->background[0];
-            C[HW + pix] = c1 + T * prm->background[1];
-            C[2 * HW + pix] = c2 + T * prm->background[2];
-            T_final[pix] = T;
-            last[pix] = nlast;
+            double rgb[3];
+            int32_t nvis, fl;
+            composite_pixel(N, mean2d, conic, colors, opac, ids, ranges[2 * tile], ranges[2 * tile + 1],
+                            (double)j + 0.5, (double)i + 0.5, prm, rgb, &T_final[pix], &last[pix], &nvis, &fl);
+            C[pix] = rgb[0];
+            C[HW + pix] = rgb[1];
+            C[2 * HW + pix] = rgb[2];
             if (visited) visited[pix] = nvis;
             if (flags) flags[pix] = fl;
         }
     }
+}
+
+/*
+ * eq. (7) on a subset of tiles only: the n_sel tiles sel[] (tile indices of a W x H
+ * camera), each with its depth-ordered list ids[ranges[2t] .. ranges[2t+1]). Pixels of
+ * tile sel[s] are written at [s][row][col] of a 16 x 16 block (rows and columns past the
+ * image edge are left untouched): C [3][n_sel][256], T_final, last, flags [n_sel][256]
+ * (each may be NULL).
+ * Returns sum over the written pixels and channels of (C - target)^2, target [3][W*H]
+ * (NULL: no loss). The arithmetic per pixel is composite_pixel, as in orc_rasterize_fwd.
+ */
+double orc_rasterize_tiles(int64_t N, const double *mean2d, const double *conic, const double *colors,
+                           const double *opac, const int32_t *ids, const int64_t *ranges,
+                           int64_t W, int64_t H, const orc_params *prm, int64_t n_sel, const int64_t *sel,
+                           const double *target, double *C, double *T_final, int32_t *last, int32_t *flags)
+{
+    const int64_t TX = (W + ORC_TILE - 1) / ORC_TILE;
+    const int64_t HW = W * H, B = ORC_TILE * ORC_TILE;
+    double loss = 0.0;
+    set_threads(prm);
+    /* per-tile partial sums, added in tile order, so the loss does not depend on threads */
+    double *part = (double *)calloc((size_t)(n_sel > 0 ? n_sel : 1), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sel; ++s) {
+        const int64_t t = sel[s], ty = t / TX, tx = t % TX;
+        double acc = 0.0;
+        for (int64_t r = 0; r < ORC_TILE; ++r)
+            for (int64_t c = 0; c < ORC_TILE; ++c) {
+                const int64_t i = ty * ORC_TILE + r, j = tx * ORC_TILE + c;
+                if (i >= H || j >= W) continue;
+                double rgb[3], T;
+                int32_t nl, nv, fl;
+                composite_pixel(N, mean2d, conic, colors, opac, ids, ranges[2 * t], ranges[2 * t + 1],
+                                (double)j + 0.5, (double)i + 0.5, prm, rgb, &T, &nl, &nv, &fl);
+                const int64_t o = s * B + r * ORC_TILE + c;
+                if (C) {
+                    C[o] = rgb[0];
+                    C[n_sel * B + o] = rgb[1];
+                    C[2 * n_sel * B + o] = rgb[2];
+                }
+                if (T_final) T_final[o] = T;
+                if (last) last[o] = nl;
+                if (flags) flags[o] = fl;
+                if (target) {
+                    const int64_t pix = i * W + j;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const double d = rgb[ch] - target[ch * HW + pix];
+                        acc += d * d;
+                    }
+                }
+            }
+        part[s] = acc;
+    }
+    for (int64_t s = 0; s < n_sel; ++s) loss += part[s];
+    free(part);
+    return loss;
 }
 
 /*
@@ -655,6 +728,10 @@ void orc_project_bwd(int64_t N, const double *means, const double *quats, const 
     proj_matrix(cam, P);
     tr(P, Pt, 4, 4);
     const double w = (double)cam->W, h = (double)cam->H;
+    set_threads(prm);
+    /* each Gaussian writes only its own outputs; the camera-pose sum runs serially, in
+     * Gaussian order */
+#pragma omp parallel for schedule(static) if (dTcw == NULL)
     for (int64_t i = 0; i < N; ++i) {
         orc_proj g;
         load_gaussian(N, i, means, quats, scales, &g);

@@ -852,3 +852,102 @@ def test_flags_bound_every_float32_decision_flip(seed):
         flips += int(diff.sum())
         flips_weak += int((diff & ~weak_flagged).sum())
     assert flips > 100 and flips_weak > 100
+
+
+# ------------------------------------------- local re-render (finite differences at scale)
+
+def _small_c5():
+    wl = synth.make_config(5, n_override=3000)
+    for k, c in enumerate(wl.cameras):
+        s = min(1.0, 160.0 / max(c.width, c.height))
+        w, h = max(1, int(c.width * s)), max(1, int(c.height * s))
+        wl.cameras[k] = synth.Camera(c.R, c.t, c.fx * s, c.fy * s, w / 2, h / 2, w, h, c.near, c.far, c.scene)
+    rng = np.random.default_rng(9)
+    wl.targets = [rng.uniform(0, 1, (3, c.height, c.width)).astype(np.float32) for c in wl.cameras]
+    return wl
+
+
+def _scene_views(wl, s):
+    ks = [k for k, c in enumerate(wl.cameras) if c.scene == s]
+    return [wl.cameras[k] for k in ks], [wl.targets[k] for k in ks]
+
+
+def test_local_render_and_gradient_equal_the_whole_image():
+    """The region render of one Gaussian's neighbourhood equals the whole-image render on those
+    tiles, and its analytic gradient equals that Gaussian's gradient from the whole-image
+    backward of the same loss (every pixel outside its tiles contributes nothing to it)."""
+    from oracle import local
+    wl = _small_c5()
+    prm = oracle.Params.standard()
+    s = 1
+    cams, tg = _scene_views(wl, s)
+    ls = local.LocalScene(wl.scenes[s], cams, tg, prm)
+    full = []
+    for cam, t in zip(cams, tg):
+        st = oracle.render(wl.scenes[s], cam, prm)
+        _, dL = oracle.loss_l2(st["C"], t)
+        full.append((st, oracle.render_backward(wl.scenes[s], cam, prm, dL, state=st)))
+    rng = np.random.default_rng(3)
+    vis = np.nonzero(np.any([p["tiles"] > 0 for p in ls.proj], axis=0))[0]
+    checked = 0
+    for g in rng.choice(vis, 12, replace=False):
+        want = np.zeros(14)
+        for c, (st, gr) in enumerate(full):
+            out = ls.render(int(g), c)
+            if out is None:
+                continue
+            tx = cams[c].tiles_x
+            for j, t in enumerate(out["tiles"]):
+                ty, txx = divmod(int(t), tx)
+                h, w = min(16, cams[c].height - 16 * ty), min(16, cams[c].width - 16 * txx)
+                blk = (slice(16 * ty, 16 * ty + h), slice(16 * txx, 16 * txx + w))
+                assert np.array_equal(out["C"][:, j, :h, :w], st["C"][:, blk[0], blk[1]])
+                assert np.array_equal(out["last"][j, :h, :w], st["last"][blk])
+            want += np.concatenate([gr["means"][:, g], gr["quats"][:, g], gr["scales"][:, g],
+                                    gr["colors"][:, g], [gr["opacities"][g]]])
+        got = ls.grad(int(g))
+        assert np.abs(got - want).max() <= 1e-12 * (np.abs(want).max() + 1e-300), (g, got, want)
+        checked += 1
+    assert checked == 12
+
+
+def test_local_finite_differences_match_gradient():
+    """Central differences of the local loss (steps h and h/10, FP64, no interface rounding)
+    against its analytic gradient, on sampled Gaussians of a multi-scene batch."""
+    from oracle import local
+    wl = _small_c5()
+    prm = oracle.Params.standard(round_interface=False)
+    rng = np.random.default_rng(4)
+    done = disc = 0
+    worst = 0.0
+    for s in (0, 3):
+        cams, tg = _scene_views(wl, s)
+        ls = local.LocalScene(wl.scenes[s], cams, tg, prm)
+        vis = np.nonzero(np.any([p["tiles"] > 0 for p in ls.proj], axis=0))[0]
+        took = 0
+        for g in rng.permutation(vis)[:60]:
+            g = int(g)
+            an = ls.grad(g)
+            th = ls.theta(g)
+            if took == 6:
+                break
+            if not np.abs(an).max() > 0.0:           # no pixel composites it
+                continue
+            took += 1
+            try:
+                hs = local.steps(th)
+                fds = [[ls.fd(g, i, hs[i] / m) for i in range(14)] for m in (1, 10)]
+            except local.Discontinuous:
+                disc += 1
+                continue
+            f1, f2 = np.array(fds[0]), np.array(fds[1])
+            scale = np.abs(an).max()
+            if np.abs(f1 - f2).max() > 0.1 * scale:
+                disc += 1
+                continue
+            err = np.abs(f1 - an).max() / scale
+            worst = max(worst, err)
+            assert err < 2e-5, (g, err)
+            done += 1
+    print(f"FD samples {done}, discontinuous {disc}, worst {worst:.2e}")
+    assert done >= 9, (done, disc)
