@@ -951,3 +951,32 @@ def test_local_finite_differences_match_gradient():
             done += 1
     print(f"FD samples {done}, discontinuous {disc}, worst {worst:.2e}")
     assert done >= 9, (done, disc)
+
+
+@pytest.mark.slow
+def test_c5_full_size_gradients_by_finite_differences():
+    """The uneven 8-scene, 32-camera batch at full size: for 64 sampled Gaussians (8 per scene)
+    every one of the 14 parameters' analytic gradient of the summed L2 loss (Sec. 3, summed
+    over the scene's cameras) against central differences in FP64 over a local re-render of
+    the Gaussian's tiles, at steps h and h/10. A sample whose two differences disagree by
+    more than 10% (a decision flips inside the step) is discontinuous: it is counted and
+    another Gaussian is drawn. Bar: |fd - g| <= 1e-3 (|g| + rms of that parameter type over
+    the sample)."""
+    import multiprocessing as mp
+    import os
+    import sampled
+    wl = synth.make_config(5)
+    # one process per scene (the oracle runs single-threaded inside each)
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        res = pool.starmap(sampled.fd_scene, [(wl, s, 8, 100 + s) for s in range(len(wl.scenes))])
+    for s, (an, fd, _, _) in enumerate(res):
+        assert an.shape == (8, 14), (s, an.shape)
+    an_all = np.concatenate([r[0] for r in res])
+    fd_all = np.concatenate([r[1] for r in res])
+    disc, zero = sum(r[2] for r in res), sum(r[3] for r in res)
+    rms = sampled.per_type_rms(an_all)
+    err = np.abs(fd_all - an_all) / (np.abs(an_all) + rms)
+    i = np.unravel_index(int(np.argmax(err)), err.shape)
+    print(f"64 Gaussians x 14: worst elementwise {err.max():.2e} at {i} (fd {fd_all[i]:.6e}, "
+          f"analytic {an_all[i]:.6e}); median {np.median(err):.1e}; discontinuous {disc}, no gradient {zero}")
+    assert err.max() <= 1e-3
