@@ -385,7 +385,9 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
                 float a = __builtin_amdgcn_fmed3f(alpha_raw(r, dx, bdy, cdl), 0.f, prm.alpha_max);
                 a = a < prm.alpha_min ? 0.f : a;                 // skipped: a no-op update
                 if (kVisited) ps.vis[q] += (ps.T[q] >= 0.f && pos1 > 0) ? 1 : 0;   // padding not counted
-                const float Tn = ps.T[q] * (1.f - a);
+                // T (1 - alpha) as T - T alpha with one rounding: the termination test sees T
+                // with one rounding per factor (besides the error of alpha itself)
+                const float Tn = __builtin_fmaf(-ps.T[q], a, ps.T[q]);
                 const bool stop = Tn < prm.T_min;                // also true once finished (T < 0)
                 const float w = stop ? 0.f : a * ps.T[q];
                 ps.c0[q] = __builtin_fmaf(r.c0, w, ps.c0[q]);

@@ -106,3 +106,36 @@ def test_camera_pose_gradient_matches_oracle():
     grads = r.backward(st, torch.from_numpy(w.reshape(3, -1)).float().cuda(), with_pose=True)
     got = grads["campose"][0].view(3, 4).cpu().numpy().astype(np.float64)
     assert rel_err(got, ref) <= GRAD_REL, (got, ref)
+    assert elementwise_ok(got, ref), (got, ref)
+
+
+def test_camera_pose_gradient_many_cameras():
+    """eq. (28) with the R_cw term, reduced per camera, for a batch of 32 cameras over 8
+    scenes (each camera's pose gradient sums over the Gaussians it sees): every camera's 3x4
+    block against the oracle, norm and elementwise bars over the whole batch."""
+    _print_case("pose", wl="c5_small")
+    from paper_2312_02121_amd import pipeline
+    from test_gpu_batched import small_c5
+    wl = small_c5()
+    prm = oracle_params()
+    g = pipeline.GaussianSet(wl.scenes)
+    cams = pipeline.CameraSet(wl.cameras, g.sizes)
+    rng = np.random.default_rng(4)
+    w_img = np.zeros((3, cams.n_pixels), np.float32)
+    ref = np.zeros((len(wl.cameras), 3, 4))
+    for k, cam in enumerate(wl.cameras):
+        orc = oracle.render(wl.scenes[cam.scene], cam, prm)
+        w = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+        w[:, orc["flags"] != 0] = 0.0
+        off, H, W = cams.image_slice(k)
+        w_img[:, off:off + H * W] = w.reshape(3, -1)
+        ref[k] = oracle.render_backward(wl.scenes[cam.scene], cam, prm, w.astype(np.float64), state=orc,
+                                        with_pose=True)["Tcw"][:3]
+    r = pipeline.Rasterizer(cams)
+    st = r.forward(g)
+    grads = r.backward(st, torch.from_numpy(w_img).cuda(), with_pose=True)
+    got = grads["campose"].view(-1, 3, 4).cpu().numpy().astype(np.float64)
+    e = rel_err(got, ref)
+    print(f"camera-pose gradients of {len(wl.cameras)} cameras: rel err {e:.2e}")
+    assert e <= GRAD_REL, e
+    assert elementwise_ok(got, ref)

@@ -2,18 +2,23 @@
 
 The whole training step (project, bin and sort, fused forward + L2 gradient + backward,
 project_bwd) is autotuned, captured once in a HIP graph and replayed, exactly as bench.py
-runs it, and then compared with the FP64 oracle:
+runs it, and then compared with the FP64 oracle.
+
+The fused kernel forms dL/dC = 2 (C - target) itself. To give a near-tie pixel (one whose
+threshold decision sits within the kernel's float32 error bound, see gpu_helpers) zero
+upstream gradient on the GPU side as well, its target is set to the image the GPU rendered
+there, and the graph is replayed: the forward is deterministic, so dL/dC is exactly zero at
+that pixel and nothing flows from it. The oracle zeroes dL/dC at the same pixels. Views that
+are not compared get their whole target replaced that way, so the scene gradients are the
+sum over the compared views only. Every Gaussian is then compared, none is left out.
 
 * 1M Gaussians at 1920x1080 (one view): every splat field and the whole tile list
-  bit-exact, the whole image within 1e-5, and every scene gradient -- all 14 parameters
-  of all 1M Gaussians -- to the gradient bar. The fused kernel forms dL/dC = 2(C - target)
-  itself, so a near-tie pixel (one whose threshold decision sits within float32 rounding,
-  see gpu_helpers) cannot be masked on the GPU side: Gaussians listed in a tile that holds
-  such a pixel are left out of the elementwise gradient comparison and counted.
-* 3M Gaussians seen by 16 orbit cameras at 1280x720, and the 8-scene, 32-camera batch:
-  the batched graph runs over all views; sampled views (the oracle sorts ~26M entries per
-  orbit view) are compared in full: splat fields and that view's run of the global list
-  bit-exact, and its image within 1e-5.
+  bit-exact, the whole image within 1e-5, the loss, and all 14 parameters of all 1M
+  Gaussians to the gradient bar.
+* 3M Gaussians seen by 16 orbit cameras at 1280x720, and the 8-scene, 32-camera batch: the
+  batched graph runs over all views; for sampled views (the oracle sorts ~13M entries per
+  orbit view) the splat fields and the view's run of the global list bit-exact, its image
+  within 1e-5, and the scene gradients summed over those views to the gradient bar.
 """
 import numpy as np
 import pytest
@@ -21,8 +26,8 @@ import pytest
 import oracle
 from paper_2312_02121_amd import synth
 
-from gpu_helpers import (GRAD_REL, IMAGE_ATOL, bins_arrays, check_projection, elementwise_ok, oracle_params,
-                         rel_err, tile_offsets, worst_element)
+from gpu_helpers import (GRAD_REL, IMAGE_ATOL, bins_arrays, check_projection, elementwise_ok, flag_budget,
+                         oracle_params, rel_err, tile_offsets, worst_element)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
@@ -80,8 +85,46 @@ def compare_view(wl, step, k, toffs):
     err = np.abs(C - orc["C"])[:, ok].max(initial=0.0)
     print(f"view {k}: K={keys.size} image err {err:.2e}, near-tie pixels {int((~ok).sum())} / {ok.size}")
     assert err <= IMAGE_ATOL, (k, err)
-    assert (~ok).sum() <= max(3, 1e-3 * ok.size)
+    assert (~ok).sum() <= flag_budget(ok.size), (k, int((~ok).sum()))
     return orc
+
+
+def neutralise_targets(wl, step, flagged: dict):
+    """Target := the GPU's own image at the flagged pixels of the compared views (flagged:
+    view -> [H, W] bool) and at every pixel of the other views; then one more replay."""
+    mask = np.ones(step.cams.n_pixels, dtype=bool)
+    for k, fl in flagged.items():
+        off, H, W = step.cams.image_slice(k)
+        mask[off:off + H * W] = fl.reshape(-1)
+    m = torch.from_numpy(mask).cuda()
+    step.targets[:, m] = step.r.image[:, m]
+    torch.cuda.synchronize()
+
+
+def oracle_grads_over_views(wl, views, orcs, prm):
+    """Scene gradients of the L2 loss summed over `views`, dL/dC zeroed at flagged pixels."""
+    ref = {k: [np.zeros(np.asarray(s[k]).shape) for s in wl.scenes] for k in SCENE_KEYS}
+    for k in views:
+        cam = wl.cameras[k]
+        orc = orcs[k]
+        _, dL = oracle.loss_l2(orc["C"], wl.targets[k].astype(np.float64))
+        dL[:, orc["flags"] != 0] = 0.0
+        og = oracle.render_backward(wl.scenes[cam.scene], cam, prm, dL, state=orc)
+        for key in SCENE_KEYS:
+            ref[key][cam.scene] += og[key]
+    return {key: np.concatenate(v, axis=-1) for key, v in ref.items()}
+
+
+def compare_grads(step, ref):
+    for key in SCENE_KEYS:
+        got = step.grads[key].detach().cpu().numpy().astype(np.float64)
+        r = ref[key]
+        e = rel_err(got, r)
+        touched = int(np.count_nonzero(np.any(np.atleast_2d(r) != 0, axis=0)))
+        print(f"{key}: rel err {e:.2e} ({touched} Gaussians with a reference gradient)")
+        assert e <= GRAD_REL, (key, e)
+        if not elementwise_ok(got, r):
+            raise AssertionError((key, worst_element(got, r)))
 
 
 def test_c3_full_step_against_oracle():
@@ -94,33 +137,16 @@ def test_c3_full_step_against_oracle():
     g = bins_arrays(step.r, step.K)
     assert np.array_equal(g["keys"], orc["bins"]["keys"]) and np.array_equal(g["ids"], orc["bins"]["ids"])
 
-    # gradients of the L2 loss; near-tie pixels get zero upstream gradient in the reference
+    # the loss over every pixel, before any target is changed
     prm = oracle_params()
-    loss_ref, dL = oracle.loss_l2(orc["C"], wl.targets[0].astype(np.float64))
-    flagged = orc["flags"] != 0
-    dL[:, flagged] = 0.0
-    ref = oracle.render_backward(scene, cam, prm, dL, state=orc)
+    loss_ref, _ = oracle.loss_l2(orc["C"], wl.targets[0].astype(np.float64))
     assert abs(float(step.loss) - loss_ref) <= 1e-5 * loss_ref
-    # Gaussians listed in a tile that holds a near-tie pixel
-    excl = np.zeros(scene["opacities"].shape[0], dtype=bool)
-    rows, cols = np.nonzero(flagged)
-    tiles = np.unique((rows // 16) * cam.tiles_x + cols // 16)
-    for t in tiles:
-        a, b = orc["bins"]["ranges"][t]
-        excl[orc["bins"]["ids"][a:b]] = True
-    keep = ~excl
-    print(f"near-tie pixels {int(flagged.sum())} in {tiles.size} tiles; Gaussians left out {int(excl.sum())} "
-          f"of {excl.size}")
-    assert excl.sum() <= 0.10 * excl.size
-    for key in SCENE_KEYS:
-        got = step.grads[key].detach().cpu().numpy().astype(np.float64)
-        r = ref[key]
-        got_k, r_k = got[..., keep], r[..., keep]
-        e = rel_err(got_k, r_k)
-        print(f"{key}: rel err {e:.2e}")
-        assert e <= GRAD_REL, (key, e)
-        if not elementwise_ok(got_k, r_k):
-            raise AssertionError((key, worst_element(got_k, r_k)))
+    flagged = orc["flags"] != 0
+    neutralise_targets(wl, step, {0: flagged})
+    graph()
+    torch.cuda.synchronize()
+    print(f"near-tie pixels {int(flagged.sum())}; every Gaussian compared")
+    compare_grads(step, oracle_grads_over_views(wl, [0], {0: orc}, prm))
 
 
 @pytest.mark.parametrize("cfg,views", [(4, (0, 5, 11)), (5, None)])
@@ -135,5 +161,8 @@ def test_batched_full_size_sampled_views(cfg, views):
         order = np.argsort(px, kind="stable")
         views = (int(order[-1]), int(order[-2]), int(order[0]))
     check_projection(wl, step.r, views=views)
-    for k in views:
-        compare_view(wl, step, k, toffs)
+    orcs = {k: compare_view(wl, step, k, toffs) for k in views}
+    neutralise_targets(wl, step, {k: orcs[k]["flags"] != 0 for k in views})
+    graph()
+    torch.cuda.synchronize()
+    compare_grads(step, oracle_grads_over_views(wl, views, orcs, oracle_params()))

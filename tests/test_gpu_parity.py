@@ -12,9 +12,9 @@ import pytest
 import oracle
 from paper_2312_02121_amd import synth
 
-from gpu_helpers import (IMAGE_ATOL, GRAD_REL, bins_arrays, camera_images, elementwise_ok, gpu_forward,
-                         oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets, worst_element,
-                         check_projection)
+from gpu_helpers import (IMAGE_ATOL, GRAD_REL, bins_arrays, camera_images, elementwise_ok, flag_budget,
+                         gpu_forward, oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets,
+                         worst_element, check_projection)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,6 +91,7 @@ def _forward_compare(wl, r, st, prm=None):
         ok = orc["flags"] == 0
         flagged_total += int((~ok).sum())
         pixels += ok.size
+        assert (~ok).sum() <= flag_budget(ok.size), f"cam {k}: {int((~ok).sum())} near-tie pixels of {ok.size}"
         err = np.abs(g["C"] - orc["C"])[:, ok]
         assert err.max(initial=0.0) <= IMAGE_ATOL, f"cam {k}: image err {err.max()}"
         assert np.abs(g["T_final"] - orc["T_final"])[ok].max(initial=0.0) <= IMAGE_ATOL
@@ -106,7 +107,7 @@ def test_forward_image(name):
     r, st = gpu_forward(wl)
     flagged, pixels = _forward_compare(wl, r, st)
     print(f"flagged pixels {flagged} / {pixels} ({flagged / pixels:.2e})")
-    assert flagged <= max(3, 0.02 * pixels)
+    assert flagged <= flag_budget(pixels)
 
 
 def _backward_compare(wl, r, st, seed=0, with_pose=False, prm=None):
@@ -167,7 +168,7 @@ def test_background_forward_and_backward(name):
     r, st = gpu_forward(wl, params=pipeline.make_params(background=BG))
     prm = oracle_params(background=BG)
     flagged, pixels = _forward_compare(wl, r, st, prm=prm)
-    assert flagged <= max(3, 0.02 * pixels)
+    assert flagged <= flag_budget(pixels)
     res = _backward_compare(wl, r, st, prm=prm)
     print(res)
     for key, (rel, elem) in res.items():
@@ -192,7 +193,7 @@ def test_normalized_quats_projection_image_and_gradients(name):
     prm = oracle_params(normalize_quats=True)
     check_projection(wl, r, prm=prm)
     flagged, pixels = _forward_compare(wl, r, st, prm=prm)
-    assert flagged <= max(3, 0.02 * pixels)
+    assert flagged <= flag_budget(pixels)
     res = _backward_compare(wl, r, st, prm=prm)
     print(res)
     for key, (rel, elem) in res.items():
@@ -215,7 +216,7 @@ def test_lambda_max_box_projection_lists_image_and_gradients(name):
         K += oracle.bin_and_sort(oracle.project(wl.scenes[cam.scene], cam, prm), cam, tile_offset=toffs[k])["K"]
     assert st.K == K
     flagged, pixels = _forward_compare(wl, r, st, prm=prm)
-    assert flagged <= max(3, 0.02 * pixels)
+    assert flagged <= flag_budget(pixels)
     res = _backward_compare(wl, r, st, prm=prm)
     print(res)
     for key, (rel, elem) in res.items():
@@ -234,7 +235,7 @@ def test_multi_scene_multi_camera():
     r, st = gpu_forward(wl)
     check_projection(wl, r)
     flagged, pixels = _forward_compare(wl, r, st)
-    assert flagged <= max(3, 0.02 * pixels)
+    assert flagged <= flag_budget(pixels)
     res = _backward_compare(wl, r, st, seed=3)
     for key, (rel, elem) in res.items():
         assert rel <= GRAD_REL, (key, rel)
@@ -317,7 +318,8 @@ def test_edge_cases():
     r, st = gpu_forward(wl)
     check_projection(wl, r)
     flagged, pixels = _forward_compare(wl, r, st)
-    assert flagged <= 3
+    assert flagged <= flag_budget(pixels)
     res = _backward_compare(wl, r, st, seed=5)
     for key, (rel, elem) in res.items():
         assert rel <= GRAD_REL, (key, rel)
+        assert elem, key
