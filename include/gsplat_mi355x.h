@@ -287,12 +287,39 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * than 131072 pixels), which is not supported (nothing is listed). workspace: device
  * memory of at least gs_bin_and_sort_workspace_size() bytes, 256-byte aligned, contents
  * free on entry and exit. cams: as for gs_project.
+ * Concurrency: the single-pass sort launches deal their chunks to a grid of blocks that is
+ * resident all at once and whose blocks wait on each other (each wait bounded by a spin
+ * limit). No other kernel may run on the device while the call's launches do: a concurrent
+ * kernel can hold back some of those blocks until the waits give up, which sets
+ * counters[1] & 2 (the list is then invalid, every range empty). Issue the call on a
+ * stream that nothing else runs beside, or after a device-wide ordering point.
  * Errors: GS_ERR_INVALID (null pointers, capacity outside [1, 2^31 - 1], n_splats outside
  * [0, 2^31 - 1], more cameras than tiles, workspace not 256-byte aligned), GS_ERR_CAPACITY
  * (workspace too small).
  */
 int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
                     gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of the static workspace of gs_bin_and_sort_static (per GPU). */
+#define GS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/*
+ * gs_bin_and_sort without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same inputs, outputs, list, ranges, work list and flags as gs_bin_and_sort.
+ * The workspace is a static array of GS_STATIC_WORKSPACE_BYTES inside the library, one per
+ * GPU, which each GPU holds until the process ends; the call makes no allocation of its own.
+ * It serves every call whose gs_bin_and_sort_workspace_size(n_splats, capacity, n_tiles)
+ * fits in it (for example 1M splats with a 1.6M-entry list at 1920x1080). The array keeps
+ * the last call's contents; each call clears what it needs cleared. Calls that overlap on
+ * one GPU (on different streams, or from several host threads) share the array and race:
+ * the caller must order them. The concurrency rule of gs_bin_and_sort applies as well.
+ * Errors: as gs_bin_and_sort; GS_ERR_CAPACITY when the call needs more workspace than the
+ * static array holds (nothing is launched), GS_ERR_HIP if the array's device address
+ * cannot be obtained.
+ */
+int gs_bin_and_sort_static(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                           gs_bins *bins, void *stream);
 
 /*
  * Sec. 2.2, eq. (7): per pixel, composite its tile's list front to back with online

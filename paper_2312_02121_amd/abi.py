@@ -24,8 +24,11 @@ EXPORTED = (
     "gs_device_check", "gs_last_hip_error", "gs_last_error_message", "gs_version", "gs_zero", "gs_abi_layout",
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
     "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
-    "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning", "gs_splats_from_2d",
+    "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning", "gs_splats_from_2d", "gs_bin_and_sort_static",
 )
+
+# bytes of the library's static workspace of gs_bin_and_sort_static (GS_STATIC_WORKSPACE_BYTES)
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class GsError(RuntimeError):
@@ -121,6 +124,7 @@ def lib():
         "gs_bin_and_sort_workspace_size": (ctypes.c_size_t, [_I64, _I64, _I32]),
         "gs_schedule_size": (ctypes.c_int64, [_I32]),
         "gs_bin_and_sort": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P, ctypes.c_size_t, _P]),
+        "gs_bin_and_sort_static": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P]),
         "gs_rasterize_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
         "gs_rasterize_bwd": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "gs_project_bwd": (ctypes.c_int, [_P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
@@ -190,6 +194,11 @@ def gs_bin_and_sort(splats: GsSplats, n_splats: int, cams_ptr: int, n_cams: int,
                     ws_bytes: int, stream: int):
     _check("gs_bin_and_sort", lib().gs_bin_and_sort(_ref(splats), n_splats, cams_ptr, n_cams, _ref(bins), ws_ptr,
                                                     ws_bytes, stream))
+
+
+def gs_bin_and_sort_static(splats: GsSplats, n_splats: int, cams_ptr: int, n_cams: int, bins: GsBins, stream: int):
+    _check("gs_bin_and_sort_static", lib().gs_bin_and_sort_static(_ref(splats), n_splats, cams_ptr, n_cams,
+                                                                  _ref(bins), stream))
 
 
 def gs_rasterize_fwd(splats: GsSplats, bins: GsBins, cams_ptr: int, n_cams: int, prm: GsParams, n_pixels: int,

@@ -1352,10 +1352,10 @@ extern "C" size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capac
     return bin_layout(n_splats, capacity, n_tiles).total;
 }
 
-extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
-                               gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream)
+// Argument checks shared by the entry points of binning.
+static int check_bin_args(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                          const gs_bins *bins)
 {
-    clear_error();
     if (!s || !cams || !bins || n_cams < 1 || n_splats < 0)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null argument or bad size");
     if (bins->capacity < 1 || bins->capacity > 0x7fffffffll || bins->n_tiles < 1)
@@ -1367,13 +1367,15 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
     if (!bins->keys || !bins->ids || !bins->ranges || !bins->schedule || !bins->counters || !s->rect || !s->depth ||
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
+    return GS_OK;
+}
+
+// The launches of one call, on the workspace ws (layout L, 256-byte aligned); every part of
+// ws that must start at zero is cleared by the call's first launch.
+static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                            gs_bins *bins, char *ws, const BinLayout &L, hipStream_t st)
+{
     const int64_t cap = bins->capacity;
-    const BinLayout L = bin_layout(n_splats, cap, bins->n_tiles);
-    if (!workspace || workspace_bytes < L.total)
-        return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort: workspace too small");
-    if (((uintptr_t)workspace) & 255) return set_error(GS_ERR_INVALID, "gs_bin_and_sort: workspace not 256-byte aligned");
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
     uint32_t *dkeyA = (uint32_t *)(ws + L.dkeyA), *dkeyB = (uint32_t *)(ws + L.dkeyB);
     int32_t *dvalA = (int32_t *)(ws + L.dvalA), *dvalB = (int32_t *)(ws + L.dvalB);
     int64_t *dcount = (int64_t *)(ws + L.dcount);
@@ -1508,4 +1510,65 @@ extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_ca
 
     // 6. the work list
     return build_schedule(bins, (const int64_t *)err, st);
+}
+
+extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                               gs_bins *bins, void *workspace, size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_bin_args(s, n_splats, cams, n_cams, bins);
+    if (rc != GS_OK) return rc;
+    const BinLayout L = bin_layout(n_splats, bins->capacity, bins->n_tiles);
+    if (!workspace || workspace_bytes < L.total)
+        return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort: workspace too small");
+    if (((uintptr_t)workspace) & 255) return set_error(GS_ERR_INVALID, "gs_bin_and_sort: workspace not 256-byte aligned");
+    return bin_and_sort_run(s, n_splats, cams, n_cams, bins, (char *)workspace, L, (hipStream_t)stream);
+}
+
+// ------------------------------------------------- the variant that allocates nothing
+
+// The workspace of gs_bin_and_sort_static: a file-scope device array, one per GPU, held until
+// the process ends. In host code its name is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress, once per device, and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[GS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int scratch_for_current_device(char **out)
+{
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "gs_bin_and_sort_static: hipGetDevice");
+    if (rc != GS_OK) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(GS_ERR_DEVICE, "gs_bin_and_sort_static: device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "gs_bin_and_sort_static: hipGetSymbolAddress");
+        if (rc != GS_OK) return rc;
+        if (!p || (((uintptr_t)p) & 255))
+            return set_error(GS_ERR_HIP, "gs_bin_and_sort_static: scratch symbol has no aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return GS_OK;
+}
+
+extern "C" int gs_bin_and_sort_static(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,
+                                      gs_bins *bins, void *stream)
+{
+    clear_error();
+    int rc = check_bin_args(s, n_splats, cams, n_cams, bins);
+    if (rc != GS_OK) return rc;
+    const BinLayout L = bin_layout(n_splats, bins->capacity, bins->n_tiles);
+    if (L.total > (size_t)GS_STATIC_WORKSPACE_BYTES)
+        return set_error(GS_ERR_CAPACITY, "gs_bin_and_sort_static: the call needs more workspace than the library's "
+                                          "static GS_STATIC_WORKSPACE_BYTES; use gs_bin_and_sort with a workspace");
+    char *ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc != GS_OK) return rc;
+    return bin_and_sort_run(s, n_splats, cams, n_cams, bins, ws, L, (hipStream_t)stream);
 }

@@ -55,6 +55,7 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert lib.gs_project(None, None, 1, 10, None, None) == abi.GS_ERR_INVALID
     assert b"gs_project" in lib.gs_last_error_message()
     assert lib.gs_bin_and_sort(None, 0, None, 1, None, None, 0, None) == abi.GS_ERR_INVALID
+    assert lib.gs_bin_and_sort_static(None, 0, None, 1, None, None) == abi.GS_ERR_INVALID
     assert lib.gs_rasterize_fwd(None, None, None, 1, None, 0, None, None, None, None, None) == abi.GS_ERR_INVALID
     prm = abi.GsParams(0.0, 1.0, 0.0)
     sp = abi.GsSplats(rec=64, raster=64, depth=64, rect=64, tiles_touched=64, capacity=10)
