@@ -81,9 +81,53 @@ def cpu_baseline(wl, E_fwd: int, repeats: int = 3):
         times.append(time.perf_counter() - t0)
         log(f"oracle step {times[-1]:.2f} s")
     t = float(np.median(times))
-    return {"value": E_fwd / t, "unit": "evals/s", "cores": oracle.max_threads(), "kind": "oracle",
+    return {"value": E_fwd / t, "unit": "evals/s", "cores": oracle.max_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": f"the whole 1M-Gaussian 1920x1080 step (FP64 oracle, OpenMP), median of {repeats} runs",
             "seconds_per_step": t}
+
+
+def oracle_step_seconds(wl, threads: int) -> tuple:
+    """(seconds, E) of one whole training step of the FP64 oracle over every view of the
+    workload: projection, binning and sort, forward, L2 gradient, backward, projection
+    backward, summed over the views; `threads` OpenMP threads."""
+    import numpy as np
+    import oracle
+    prm = oracle.Params.standard(n_threads=threads)
+    t0 = time.perf_counter()
+    E = 0
+    for k, cam in enumerate(wl.cameras):
+        scene = wl.scenes[cam.scene]
+        pr = oracle.project(scene, cam, prm)
+        b = oracle.bin_and_sort(pr, cam)
+        f = oracle.rasterize_fwd(pr, scene["colors"], scene["opacities"], b, cam, prm)
+        _, dL = oracle.loss_l2(f["C"], wl.targets[k].astype(np.float64))
+        g2 = oracle.rasterize_bwd(pr, scene["colors"], scene["opacities"], b, cam, prm, dL, f)
+        oracle.project_bwd(scene, cam, prm, g2["mean2d"], g2["conic"])
+        E += int(f["visited"].sum())
+    return time.perf_counter() - t0, E
+
+
+def oracle_legs() -> dict:
+    """The oracle timed on this host beyond the bounded baseline: every workload once on all
+    cores (c1-c3 median of three), and c1, c2 on one core."""
+    import numpy as np
+    import oracle
+    from paper_2312_02121_amd import synth
+    allc = oracle.max_threads()
+    out = {"cpu": cpu_model(), "threads_all": allc}
+    for cfg in (1, 2, 3, 4, 5):
+        wl = synth.make_config(cfg)
+        runs = [oracle_step_seconds(wl, allc) for _ in range(3 if cfg <= 3 else 1)]
+        t = float(np.median([r[0] for r in runs]))
+        E = runs[0][1]
+        out[f"c{cfg}"] = {"threads": allc, "seconds_per_step": t, "evals_per_s": E / t,
+                          "ms_per_view": 1e3 * t / len(wl.cameras), "E_fwd": E, "views": len(wl.cameras)}
+        log(f"oracle c{cfg} on {allc} threads: {t:.2f} s/step")
+        if cfg <= 2:
+            t1, E1 = oracle_step_seconds(wl, 1)
+            out[f"c{cfg}_single_core"] = {"threads": 1, "seconds_per_step": t1, "evals_per_s": E1 / t1}
+            log(f"oracle c{cfg} on 1 thread: {t1:.2f} s/step")
+    return out
 
 
 def time_steps(fn, steps: int, warmup: int) -> float:
@@ -105,6 +149,69 @@ def time_steps_detail(fn, steps: int, warmup: int):
     torch.cuda.synchronize()
     per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def stage_times(step, steps: int, warmup: int) -> dict:
+    """Mean ms of each stage of an eager step, from events between the stages on the launch
+    stream."""
+    import numpy as np
+    import torch
+    n_st = len(step.STAGES)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_st + 1)] for _ in range(steps)]
+    for k in range(steps):
+        step(events=evs[k])
+    torch.cuda.synchronize()
+    return {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+            for i, name in enumerate(step.STAGES)}
+
+
+def executed_pairs(step) -> tuple:
+    """(forward, backward) Gaussian-pixel pairs the rasterizer kernels execute in one step:
+    list slots walked x pixels of the wave (gs_set_work_counter), one eager step."""
+    import torch
+    from paper_2312_02121_amd import abi
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    abi.gs_set_work_counter(cnt.data_ptr())
+    try:
+        step()
+        torch.cuda.synchronize()
+    finally:
+        abi.gs_set_work_counter(None)
+    return int(cnt[0]), int(cnt[1])
+
+
+def roofline_of(stage_ms: dict, E_fwd: int, E_bwd: int, executed=None) -> dict:
+    """VALU roofline of the dominant rasterizer kernel: algorithmic lane-operations per launch
+    (21 per forward pair, 46 per backward pair, pairs of the method: E_fwd, E_bwd) over its
+    time; alongside, the same price on the pairs the kernel executes."""
+    work = {"rasterize_fwd": SLOTS_FWD * E_fwd, "rasterize_bwd": SLOTS_BWD * E_bwd,
+            "fused": SLOTS_FWD * E_fwd + SLOTS_BWD * E_bwd}
+    dom = max((s for s in work if s in stage_ms), key=lambda s: stage_ms[s])
+    achieved = work[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    kname = {"rasterize_fwd": "raster_fwd_kernel", "rasterize_bwd": "raster_bwd_kernel",
+             "fused": "raster_fused_kernel"}[dom]
+    out = {"bound": "alu", "kernel": kname, "kernel_ms": stage_ms[dom], "achieved": achieved,
+           "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+           "slots_per_pair": {"fwd": SLOTS_FWD, "bwd": SLOTS_BWD}, "E_fwd": E_fwd, "E_bwd": E_bwd}
+    if executed is not None and dom == "fused":
+        xf, xb = executed
+        ach_x = (SLOTS_FWD * xf + SLOTS_BWD * xb) / (stage_ms[dom] * 1e-3) / 1e12
+        out["executed_pairs"] = {"fwd": xf, "bwd": xb}
+        out["frac_executed"] = ach_x / VALU_PEAK_TOPS
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def e_dense(step) -> int:
@@ -136,11 +243,14 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
     tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
     step = pipeline.TrainStep(g, cams, tgt, mode="fused", keep_image=False)
     tb = autotune.tune(step, cache_path=autotune.DEFAULT_CACHE) if tune else None
+    st_ms = stage_times(step, steps, warmup)
+    executed = executed_pairs(step)
     graph = pipeline.GraphStep(step)
     ms_b = time_steps(graph, steps, warmup)
     if step.overflowed():
         raise SystemExit(f"config {cfg}: list overflow in the captured step")
     E, K = step.E_fwd, step.K
+    roof = roofline_of(st_ms, step.E_fwd, step.E_bwd, executed)
     del graph, step
     torch.cuda.empty_cache()
     targets = [torch.from_numpy(t.reshape(3, -1)).cuda() for t in wl.targets]
@@ -156,7 +266,8 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
     autotune.apply(autotune.default_tuning())
     ms_v, ms_s = per_view_ms["fused"], per_view_ms["separate"]
     log(f"config {cfg}: batched {ms_b:.3f} ms, per-view {ms_v:.3f} ms (separate launches {ms_s:.3f} ms)")
-    return {"workload": wl.name, "views": cams.n_cams, "n_gaussians": g.n, "E_fwd": E,
+    return {"workload": wl.name, "views": cams.n_cams, "n_gaussians": g.n, "E_fwd": E, "E_bwd": roof["E_bwd"],
+            "K": K, "stages_ms": st_ms, "roofline": roof,
             "batched_ms_per_step": ms_b, "per_view_ms_per_step": ms_v,
             "batched_evals_per_s": E / (ms_b * 1e-3), "per_view_evals_per_s": E / (ms_v * 1e-3),
             "speedup": ms_v / ms_b, "batched_ms_per_view": ms_b / cams.n_cams,
@@ -165,20 +276,32 @@ def batched_vs_per_view(cfg: int, steps: int, warmup: int, tune: bool) -> dict:
             "per_view_separate_tuning": per_view_tuning["separate"]}
 
 
-def autograd_ms(wl, steps: int, warmup: int) -> float:
-    """ms per fwd + L2 + bwd step through the torch.autograd.Function (host sync included)."""
+def autograd_steps(wl):
+    """One training step through torch.autograd: the fused L2 form (autograd.l2_loss, a
+    torch.autograd.Function) and loss.backward(), gradients landing in the parameters' .grad;
+    and, for comparison, the image form (autograd.render, separate forward and backward
+    kernels) with the L2 loss in torch."""
     import numpy as np
     import torch
-    from paper_2312_02121_amd.autograd import render
-    s = wl.scenes[0]
-    ps = [torch.tensor(np.asarray(s[k]), device="cuda", requires_grad=True)
-          for k in ("means", "quats", "scales", "colors", "opacities")]
-    tgt = torch.from_numpy(wl.targets[0]).cuda()
+    from paper_2312_02121_amd.autograd import l2_loss, render
+    sizes = [s["opacities"].shape[0] for s in wl.scenes]
+    ps = [torch.tensor(np.concatenate([np.asarray(s[k]) for s in wl.scenes], axis=-1), device="cuda",
+                       requires_grad=True) for k in ("means", "quats", "scales", "colors", "opacities")]
+    tgt = torch.from_numpy(np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1)).cuda()
 
-    def one():
-        img = render(*ps, wl.cameras)[0]
-        ((img - tgt) ** 2).sum().backward()
-    return time_steps(one, steps, warmup)
+    def fused():
+        for p in ps:
+            p.grad = None                 # an optimiser's zero_grad(set_to_none=True)
+        l2_loss(*ps, wl.cameras, tgt, scene_sizes=sizes).backward()
+
+    tgt_img = [torch.from_numpy(t).cuda() for t in wl.targets]
+
+    def image():
+        for p in ps:
+            p.grad = None
+        imgs = render(*ps, wl.cameras, scene_sizes=sizes)
+        sum(((i - t) ** 2).sum() for i, t in zip(imgs, tgt_img)).backward()
+    return fused, image
 
 
 def main():
@@ -192,6 +315,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--oracle-legs", action="store_true",
+                    help="only time the FP64 oracle: every workload on all host cores, c1 and c2 on one core "
+                         "(minutes of CPU time; prints one JSON object)")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch tuning")
     ap.add_argument("--tuning", type=str, default=None,
                     help="JSON launch tuning to apply instead of searching (profiling runs)")
@@ -203,6 +329,10 @@ def main():
         print(f"bench.py runs on one GPU only (the rasterizer is built and measured on a single MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_legs:
+        print(json.dumps({"oracle_legs": oracle_legs()}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -238,17 +368,9 @@ def main():
             f"({tuned['evaluated']} candidates, {tuned['seconds']:.1f} s, cached {tuned['cached']})")
 
     # per-stage times (eager launches, events between stages on the launch stream)
-    n_st = len(step.STAGES)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_st + 1)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        step(events=evs[k])
-    torch.cuda.synchronize()
-    stage_ms = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-                for i, name in enumerate(step.STAGES)}
+    stage_ms = stage_times(step, args.steps, args.warmup)
     log("stages (ms): " + " ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
+    executed = executed_pairs(step) if args.mode == "fused" else None
 
     # the timed step: the whole path, captured once in a HIP graph and replayed
     runner = step if args.no_graph else pipeline.GraphStep(step)
@@ -257,15 +379,8 @@ def main():
         raise SystemExit("intersection list overflowed its capacity during the timed steps")
     log(f"step {ms_step:.4f} ms ({'eager' if args.no_graph else 'graph'})")
 
-    work = {"rasterize_fwd": SLOTS_FWD * step.E_fwd, "rasterize_bwd": SLOTS_BWD * step.E_bwd,
-            "fused": SLOTS_FWD * step.E_fwd + SLOTS_BWD * step.E_bwd}
-    dom = max((s for s in work if s in stage_ms), key=lambda s: stage_ms[s])
-    achieved = work[dom] / (stage_ms[dom] * 1e-3) / 1e12
-    kname = {"rasterize_fwd": "raster_fwd_kernel", "rasterize_bwd": "raster_bwd_kernel",
-             "fused": "raster_fused_kernel"}[dom]
-    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_from_profiles(kname),
-                "slots_per_pair": {"fwd": SLOTS_FWD, "bwd": SLOTS_BWD}}
+    roofline = roofline_of(stage_ms, step.E_fwd, step.E_bwd, executed)
+    roofline["traffic"] = traffic_from_profiles(roofline["kernel"])
 
     views = cams.n_cams
     line = {
@@ -285,9 +400,12 @@ def main():
                                                                      "cached")},
     }
     del runner
-    if not args.no_autograd and args.config == 3:
-        line["autograd_ms_per_step"] = autograd_ms(wl, max(3, args.steps // 4), 2)
-        log(f"autograd path {line['autograd_ms_per_step']:.3f} ms/step")
+    if not args.no_autograd:
+        fused, image = autograd_steps(wl)
+        line["autograd_ms_per_step"] = time_steps(fused, args.steps, args.warmup)
+        line["autograd_image_form_ms_per_step"] = time_steps(image, max(3, args.steps // 4), 2)
+        log(f"autograd: fused L2 form {line['autograd_ms_per_step']:.4f} ms/step, image form "
+            f"{line['autograd_image_form_ms_per_step']:.3f} ms/step")
     if not args.no_batched:
         del step
         torch.cuda.empty_cache()

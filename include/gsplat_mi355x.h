@@ -38,7 +38,10 @@
  *   the largest eigenvalue of Sigma'; tile k covers pixel coordinates [16k, 16k + 16).
  * - alpha = min(alpha_max, o exp(-sigma)); entries with alpha < alpha_min are
  *   skipped; compositing stops before the first entry whose T (1 - alpha) would drop
- *   below T_min (that entry is not composited).
+ *   below T_min (that entry is not composited). alpha_max must lie in (0, 1]; 1 with
+ *   alpha_min = T_min = 0 is the literal image formation of eq. (7), in which the kernels
+ *   cap alpha at the largest float32 below 1 (1 - alpha >= 2^-24, so the division of
+ *   eq. 17 stays defined; only opacities within 6e-8 of 1 are affected).
  * - the image formation of Sec. 2.2 has no background (gs_params.background = 0). A
  *   nonzero background bg is an option: C = sum c alpha T + T_final bg, and the
  *   backward counts bg, with weight T_final, in the colour behind every entry (S of
@@ -213,6 +216,26 @@ int gs_set_tuning(const gs_tuning *t);
 /* Reads the current launch tuning into *t. */
 int gs_get_tuning(gs_tuning *t);
 
+/*
+ * Polls a look-back wait inside gs_bin_and_sort's single-pass sort launches makes before it
+ * gives up (default 2^20), on the current device. A wait that gives up sets counters[1] & 2
+ * and the call builds no list (every range empty); every kernel still ends normally. A
+ * negative value makes every look-back give up at once: it drives that failure path on
+ * purpose, for tests of the caller's error handling. Synchronous (a copy to device memory);
+ * not to be called while binning runs.
+ */
+int gs_set_sort_wait_limit(int32_t polls);
+
+/*
+ * Measurement aid: with counts (device memory, two uint64, caller-zeroed) the rasterizer
+ * kernels add to counts[0] the Gaussian-pixel pairs their forward walks execute (list
+ * slots stepped through x pixels of the wave, padding slots and finished pixels included,
+ * left-out records not) and to counts[1] those of their backward walks; NULL (the default)
+ * turns counting off. Applies to launches made after the call on the current device.
+ * Synchronous (a copy to device memory).
+ */
+int gs_set_work_counter(unsigned long long *counts);
+
 /* Zeroes `bytes` bytes at device pointer `ptr` with a kernel (graph-capturable). */
 int gs_zero(void *ptr, size_t bytes, void *stream);
 
@@ -355,8 +378,7 @@ int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const gs_camera *c
  * gs_project_bwd multiplies them by Y on both sides (dL/dSigma' = -Y dL/dY Y): for a
  * needle-like splat float32 rounding of dL/dY, scaled by the square of Y's largest
  * eigenvalue, would dominate the gradient along the splat's thin axis.
- * Errors: GS_ERR_INVALID for null pointers, bad sizes, or alpha_max >= 1 (the
- * division of eq. 17 needs 1 - alpha > 0).
+ * Errors: GS_ERR_INVALID for null pointers, bad sizes, or alpha_max outside (0, 1].
  */
 int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
                      int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *dL_dimage,
@@ -370,8 +392,11 @@ int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_bins *bins, 
  * Sec. 3.1 run back to back inside one persistent launch, so the image, T and `last`
  * stay in registers. C includes the background term of prm. target [3][n_pixels].
  * image: optional (NULL) output of C. loss:
- * optional (NULL) device float to which L is added. Gradient outputs and errors as for
- * gs_rasterize_bwd (accumulated; zero them first).
+ * optional (NULL) device float to which L is added. When bins->counters[1] is nonzero
+ * (gs_bin_and_sort built no list: overflow or a failed sort) the launch writes NaN to
+ * *loss and nothing else, so a caller that does not synchronise after binning still sees
+ * that the step is void. Gradient outputs and errors as for gs_rasterize_bwd
+ * (accumulated; zero them first); bins->counters must not be NULL.
  */
 int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const gs_bins *bins, const gs_camera *cams,
                           int32_t n_cams, const gs_params *prm, int64_t n_pixels, const float *target,

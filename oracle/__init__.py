@@ -258,6 +258,8 @@ def splats_from_2d(mean2d, conic, depth, valid, cam, params: Params) -> dict:
         det = y00 * y11 - y01 * y01
         if not valid[n] or not np.isfinite(det) or not det > 0.0 or not y00 > 0.0 or not y11 > 0.0:
             continue
+        if not (np.isfinite(d[n]) and d[n] > 0.0):      # not a depth key: culled
+            continue
         c00, c01, c11 = y11 / det, -y01 / det, y00 / det
         if not (np.isfinite(c00) and np.isfinite(c01) and np.isfinite(c11) and np.isfinite(m[0, n])
                 and np.isfinite(m[1, n])):

@@ -25,7 +25,7 @@
  *     (dL/dq^ - q^ (q^ . dL/dq^)) / |q| with q^ = q / |q|.
  *   - Delta = mu' - p (pixel centre p), the sign for which dsigma/dmu' = Y Delta.
  *   - eq. (23): the second row uses h, and t means t' there.
- *   - near/far cull: keep only near < t_z < far.
+ *   - near/far cull: keep only near < t_z < far, and t_z > 0 (depth keys are float bits).
  *   - 3-sigma box: tight axis-aligned half extents 3 sqrt(Sigma'_00), 3 sqrt(Sigma'_11).
  *     As an option (box_lambda_max), a square of half extent 3 sqrt(lambda_max) with
  *     lambda_max = (a + c) / 2 + sqrt(((a - c) / 2)^2 + b^2), Sigma' = (a, b; b, c):
@@ -218,7 +218,9 @@ static int project_one(const orc_camera *cam, const orc_params *prm, orc_proj *g
     if (!all_finite(g->t, 3))
         return 0;
     const double tx = g->t[0], ty = g->t[1], tz = g->t[2];
-    if (!(tz > cam->near_plane) || !(tz < cam->far_plane))
+    /* keep near < t_z < far; t_z <= 0 is culled whatever the near plane: the depth order of
+     * Sec. 2.2 is taken on the float32 bits of t_z, which order only positive values */
+    if (!(tz > cam->near_plane) || !(tz > 0.0) || !(tz < cam->far_plane))
         return 0;
 
     /* t' = P t and mu' (eq. 2) */
@@ -428,13 +430,15 @@ static void composite_pixel(int64_t N, const double *mean2d, const double *conic
         ++nvis;
         if (fabs(a_raw - prm->alpha_max) <= prm->margin_clamp) fl |= 4;
         const double alpha = a_raw < prm->alpha_max ? a_raw : prm->alpha_max;
-        if (fabs(alpha - prm->alpha_min) <= prm->margin_alpha * prm->alpha_min) fl |= 1;
+        /* with alpha_min = 0 (literal mode) there is no skip decision to flag */
+        if (prm->alpha_min > 0.0 && fabs(alpha - prm->alpha_min) <= prm->margin_alpha * prm->alpha_min) fl |= 1;
         if (alpha < prm->alpha_min) continue;
         const double Tn = T * (1.0 - alpha);
         const double eTn = prm->margin_T > 0.0
             ? eT + prm->round_T + (a_raw >= prm->alpha_max ? 0.0 : prm->margin_alpha * alpha / (1.0 - alpha))
             : 0.0;
-        if (fabs(Tn - prm->T_min) <= eTn * (Tn > prm->T_min ? Tn : prm->T_min)) fl |= 2;
+        /* with T_min = 0 (literal mode) there is no termination decision to flag */
+        if (prm->T_min > 0.0 && fabs(Tn - prm->T_min) <= eTn * (Tn > prm->T_min ? Tn : prm->T_min)) fl |= 2;
         if (Tn < prm->T_min) break;
         eT = eTn;
         c0 += colors[g] * alpha * T;

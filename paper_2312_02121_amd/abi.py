@@ -25,7 +25,10 @@ EXPORTED = (
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
     "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
     "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning", "gs_splats_from_2d", "gs_bin_and_sort_static",
+    "gs_set_sort_wait_limit", "gs_set_work_counter",
 )
+
+DEFAULT_SORT_WAIT_LIMIT = 1 << 20
 
 # bytes of the library's static workspace of gs_bin_and_sort_static (GS_STATIC_WORKSPACE_BYTES)
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -125,6 +128,8 @@ def lib():
         "gs_schedule_size": (ctypes.c_int64, [_I32]),
         "gs_bin_and_sort": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P, ctypes.c_size_t, _P]),
         "gs_bin_and_sort_static": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P]),
+        "gs_set_sort_wait_limit": (ctypes.c_int, [_I32]),
+        "gs_set_work_counter": (ctypes.c_int, [_P]),
         "gs_rasterize_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
         "gs_rasterize_bwd": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "gs_project_bwd": (ctypes.c_int, [_P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
@@ -194,6 +199,14 @@ def gs_bin_and_sort(splats: GsSplats, n_splats: int, cams_ptr: int, n_cams: int,
                     ws_bytes: int, stream: int):
     _check("gs_bin_and_sort", lib().gs_bin_and_sort(_ref(splats), n_splats, cams_ptr, n_cams, _ref(bins), ws_ptr,
                                                     ws_bytes, stream))
+
+
+def gs_set_sort_wait_limit(polls: int):
+    _check("gs_set_sort_wait_limit", lib().gs_set_sort_wait_limit(polls))
+
+
+def gs_set_work_counter(ptr: int | None):
+    _check("gs_set_work_counter", lib().gs_set_work_counter(ptr))
 
 
 def gs_bin_and_sort_static(splats: GsSplats, n_splats: int, cams_ptr: int, n_cams: int, bins: GsBins, stream: int):

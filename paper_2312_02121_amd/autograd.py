@@ -10,6 +10,14 @@ state is stored.
 ``render`` is the user-facing wrapper: it takes parameter tensors and a list of cameras
 and returns one [3, H, W] image per camera.
 
+``l2_loss`` is the training form for the L2 image loss L = sum (C - target)^2 over a batch
+of cameras: ``RasterizeL2Loss`` runs projection, binning, the fused forward + dL/dC +
+backward launch and the projection backward in its forward (one HIP-graph replay of a
+step whose buffers are kept between calls), returns L, and hands the stored gradients,
+scaled by the incoming dL_out, to autograd in its backward. No call synchronises the host:
+the list length is read back asynchronously and the capacity regrown at the next call, and
+a step whose list overflowed returns a NaN loss.
+
 The per-stage form splits the same map at the 2D splats: ``ProjectGaussians`` (Sec. 2.1:
 means, quats, scales -> mu', Y, with gs_project and gs_project_bwd) and ``RasterizeSplats``
 (Sec. 2.2: mu', Y, colours, opacities -> image, with gs_splats_from_2d, the sort and the
@@ -21,6 +29,7 @@ from __future__ import annotations
 
 from typing import Sequence
 
+import numpy as np
 import torch
 
 from . import abi, pipeline
@@ -155,3 +164,98 @@ def render_stages(means, quats, scales, colors, opacities, cameras: Sequence, sc
         mean2d, conic = splat_hook(mean2d, conic)
     packed = RasterizeSplats.apply(mean2d, conic, colors, opacities, depth, valid, cams, params, sizes)
     return [cams.unpack(packed, k) for k in range(cams.n_cams)]
+
+
+# ------------------------------------------------------------------ fused L2 training form
+
+class _L2Step:
+    """A fused TrainStep over fixed parameter, target and camera buffers, captured in a HIP
+    graph, with the list length read back without blocking."""
+
+    def __init__(self, g: pipeline.GaussianSet, cams: pipeline.CameraSet, targets: torch.Tensor,
+                 params: abi.GsParams, capacity: int | None):
+        self.g, self.cams, self.targets, self.params = g, cams, targets, params
+        self.step = pipeline.TrainStep(g, cams, targets, params, capacity=capacity, mode="fused", keep_image=False)
+        self.graph = pipeline.GraphStep(self.step)
+        self.host_counters = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+        self.done = None
+
+    def run(self):
+        self.graph()
+        self.host_counters.copy_(self.step.r.bins.counters, non_blocking=True)
+        self.done = torch.cuda.Event()
+        self.done.record()
+
+    def previous_counts(self):
+        """(K, flags) of the last completed replay, or None while it is still running."""
+        if self.done is None or not self.done.query():
+            return None
+        return int(self.host_counters[0]), int(self.host_counters[1])
+
+
+_l2_steps: dict = {}
+
+
+def _camera_key(cameras) -> tuple:
+    return tuple((np.asarray(c.R, dtype=np.float64).tobytes(), np.asarray(c.t, dtype=np.float64).tobytes(),
+                  float(c.fx), float(c.fy), float(c.cx), float(c.cy), int(c.width), int(c.height), float(c.near),
+                  float(c.far), int(getattr(c, "scene", 0))) for c in cameras)
+
+
+class RasterizeL2Loss(torch.autograd.Function):
+    """(means, quats, scales, colors, opacities) -> L = sum over cameras, pixels and channels of
+    (C - target)^2, with the whole backward computed in the forward's fused launch."""
+
+    @staticmethod
+    def forward(ctx, means, quats, scales, colors, opacities, holder: _L2Step):
+        holder.run()
+        grads = holder.step.grads
+        # copies: the step's buffers are rewritten by the next call, which may come before
+        # this backward
+        ctx.grads = tuple(grads[k].clone() for k in ("means", "quats", "scales", "colors", "opacities"))
+        return grads["loss"].clone().view(())
+
+    @staticmethod
+    def backward(ctx, dL_out):
+        out = tuple(g.mul_(dL_out) for g in ctx.grads)
+        ctx.grads = None
+        return out + (None,)
+
+
+def l2_loss(means: torch.Tensor, quats: torch.Tensor, scales: torch.Tensor, colors: torch.Tensor,
+            opacities: torch.Tensor, cameras: Sequence, targets: torch.Tensor,
+            scene_sizes: Sequence[int] | None = None, params: abi.GsParams | None = None,
+            normalize_quats: bool = False) -> torch.Tensor:
+    """Differentiable L2 image loss over a batch of cameras: targets [3, n_pixels] packed in
+    camera order (each camera's [3, H, W] target flattened and concatenated along pixels).
+
+    The parameter and target tensors are used in place (not copied): the captured step keeps
+    their addresses and is rebuilt when an address, a shape, a camera or the parameters
+    change. An optimiser that updates the parameters in place keeps the cached step.
+    A NaN loss means the step's tile list overflowed its capacity; the capacity is regrown
+    and the next call is valid."""
+    sizes = tuple(scene_sizes) if scene_sizes is not None else (int(opacities.shape[-1]),)
+    params = params or pipeline.make_params()
+    ts = (means, quats, scales, colors, opacities)
+    for t in ts + (targets,):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("l2_loss: parameters and targets must be contiguous float32 device tensors")
+    key = (tuple(t.data_ptr() for t in ts), tuple(tuple(t.shape) for t in ts), targets.data_ptr(),
+           tuple(targets.shape), sizes, _camera_key(cameras), bytes(params), bool(normalize_quats))
+    holder = _l2_steps.get(key)
+    if holder is not None:
+        prev = holder.previous_counts()
+        if prev is not None and (prev[1] & 1 or prev[0] * 1.1 > holder.step.r.capacity):
+            # the last step overflowed, or came close: rebuild with room for its K
+            holder = _L2Step(holder.g, holder.cams, targets, params, int(prev[0] * 1.25) + 1024)
+            _l2_steps[key] = holder
+        elif prev is not None and prev[1] & 2:
+            pipeline.check_sort_flag(prev[1])
+    if holder is None:
+        if len(_l2_steps) >= 4:
+            _l2_steps.pop(next(iter(_l2_steps)))
+        g = pipeline.GaussianSet.from_tensors(*[t.detach() for t in ts], sizes, normalize_quats)
+        cams = pipeline.CameraSet(cameras, sizes, device=means.device)
+        holder = _L2Step(g, cams, targets, params, None)
+        _l2_steps[key] = holder
+    return RasterizeL2Loss.apply(means, quats, scales, colors, opacities, holder)

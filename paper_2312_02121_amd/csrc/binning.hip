@@ -160,6 +160,19 @@ constexpr uint64_t kStatInc = 2ull << 62;
 constexpr uint64_t kStatValue = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 20;   // bounded wait: a predecessor that never publishes ends the wait
 
+// Polls a look-back wait makes before it gives up (gs_set_sort_wait_limit; kSpinLimit by
+// default). A negative value makes every look-back give up at once, which lets a caller
+// drive the give-up path (flag 2, no list) with every kernel ending normally.
+__constant__ int g_wait_limit = kSpinLimit;
+
+// True when look-backs are to give up at once (a negative wait limit); sets the error word.
+__device__ inline bool forced_give_up(int64_t *err_flag)
+{
+    if (g_wait_limit >= 0) return false;
+    __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 // Chunks of a single-pass launch are dealt to a grid of blocks that are all resident at
 // once: block g takes chunks g, g + G, g + 2G, ... (G = gridDim.x) in turn. A chunk only
 // waits on lower chunks, which are held by running blocks, so every wait ends without a
@@ -176,12 +189,12 @@ __device__ inline bool chunk_stop(const int64_t *err_flag, int *sh_flag)
     return *sh_flag != 0;
 }
 
-// Gives up a look-back wait after kSpinLimit polls, or early once another block has given
+// Gives up a look-back wait after g_wait_limit polls, or early once another block has given
 // up (checked every 64 polls). Returns true when the wait is to end.
 __device__ inline bool spin_exhausted(int &spins, int64_t *err_flag)
 {
     ++spins;
-    if (spins > kSpinLimit ||
+    if (spins > g_wait_limit ||
         ((spins & 63) == 0 && __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
@@ -199,6 +212,7 @@ __device__ inline int64_t chained_prefix(const uint64_t *status, int b, int64_t 
     __shared__ uint64_t s_inc[kSortWaves], s_nr[kSortWaves];
     __shared__ int64_t s_sum[kSortWaves];
     __shared__ int s_stop;
+    if (forced_give_up(err_flag)) return -1;   // uniform: every thread reads the same constant
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int64_t acc = 0;
     int j = b - 1;
@@ -252,6 +266,7 @@ constexpr int kLookWindow = 8;
 
 __device__ inline int64_t digit_lookback(const uint64_t *status, int b, int d, int64_t *err_flag)
 {
+    if (forced_give_up(err_flag)) return -1;
     int64_t acc = 0;
     int j = b - 1;   // highest chunk not yet summed
     int window = 1;
@@ -1510,6 +1525,12 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
 
     // 6. the work list
     return build_schedule(bins, (const int64_t *)err, st);
+}
+
+extern "C" int gs_set_sort_wait_limit(int32_t polls)
+{
+    clear_error();
+    return check_hip(hipMemcpyToSymbol(HIP_SYMBOL(g_wait_limit), &polls, sizeof(polls)), "gs_set_sort_wait_limit");
 }
 
 extern "C" int gs_bin_and_sort(const gs_splats *s, int64_t n_splats, const gs_camera *cams, int32_t n_cams,

@@ -18,8 +18,10 @@ constexpr int kRecFloats = 12;           // floats per splat record
 //   alpha_raw(dx, dy) = exp2(lo + A dx^2 + B dx dy + C dy^2),  (dx, dy) = mu' - pixel centre
 // lo = log2(o); A = -log2(e)/2 Y00, B = -log2(e) Y01, C = -log2(e)/2 Y11 from the float32 conic.
 // The quadratic form is evaluated in float64: for thin splats Y is nearly singular and the three
-// terms cancel, which in float32 costs up to ~1e-5 of image accuracy. On CDNA a float64 FMA
-// issues at the rate of a non-packed float32 one, so this costs only two conversions per pixel.
+// terms cancel, which in float32 costs up to ~1e-5 of image accuracy. It is not free: measured
+// on gfx950, a wave64 float64 FMA or add takes ~4.3 clocks of its SIMD against ~2.2 for a float32
+// one, and a conversion ~3.4, so the per-pixel exponent (one subtraction, two FMAs and a
+// conversion in float64) costs about as much as eight float32 operations.
 struct alignas(64) RasterRec {
     float mx, my;     // mu', the same float32 values as in rec
     double lo;

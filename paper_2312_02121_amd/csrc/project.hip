@@ -92,7 +92,10 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     const double tx = R00 * mx + R01 * my + R02 * mz + (double)cam.t[0];
     const double ty = R10 * mx + R11 * my + R12 * mz + (double)cam.t[1];
     const double tz = R20 * mx + R21 * my + R22 * mz + (double)cam.t[2];
-    visible = visible && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz < (double)cam.far_plane;
+    // depth keys are the float bits of t_z, which order depths correctly only when t_z > 0:
+    // a near plane at or behind the camera still culls t_z <= 0
+    visible = visible && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz > 0.0 &&
+              tz < (double)cam.far_plane;
 
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     RasterRec rr = {};
@@ -200,15 +203,19 @@ __global__ __launch_bounds__(256) void splats_from_2d_kernel(gs_gaussians g, con
     const double C00 = Y11 / det, C01 = -Y01 / det, C11 = Y00 / det;
     int4 box = make_int4(0, 0, 0, 0);
     int32_t tiles = 0;
+    // a depth that is not positive and finite cannot be a depth key (float bits order only
+    // positive values): the slot is culled
+    const float dep = depth_in[p];
     bool visible = valid[p] != 0 && isfinite((double)m0) && isfinite((double)m1) && isfinite(det) && det > 0.0 &&
-                   Y00 > 0.0 && Y11 > 0.0 && isfinite(C00) && isfinite(C01) && isfinite(C11);
+                   Y00 > 0.0 && Y11 > 0.0 && isfinite(C00) && isfinite(C01) && isfinite(C11) && dep > 0.0f &&
+                   isfinite(dep);
     if (visible) visible = splat_box(m0, m1, C00, C01, C11, cam, g.flags, box, tiles);
     tiles_out[p] = visible ? tiles : 0;
     if (visible) {
         const float o = g.opacities[i];
         rrec[p] = make_record(m0, m1, y00, y01, y11, o, g.colors[i], g.colors[n + i], g.colors[2 * n + i], (int)i,
                               (int)p);
-        depth_out[p] = depth_in[p];
+        depth_out[p] = dep;
         rect_out[p] = box;
     }
 }

@@ -3,8 +3,8 @@
 // The arithmetic is float64: dL/dSigma' = -Y dL/dY Y grows with the square of the conic,
 // which is large for thin splats, and the chain that follows sums terms of both signs;
 // in float32 that costs up to ~1e-3 of relative accuracy on single quaternion gradients.
-// The kernel is HBM-bound and CDNA issues float64 FMAs at the float32 rate, so this is
-// free. The conic Y in dL/dSigma' is re-derived here in float64 from Sigma' rather than read
+// The kernel is HBM-bound (its float64 arithmetic, about half the float32 rate on gfx950,
+// stays below the memory time). The conic Y in dL/dSigma' is re-derived here in float64 from Sigma' rather than read
 // from the splat record: the record holds Y rounded to float32 for the compositing, and for a
 // needle-like splat that rounding moves Y's small eigenvalue by up to ~1e-2 relative, which
 // the product -Y dL/dY Y would carry into the gradient. The derivative of the inverse is

@@ -43,6 +43,12 @@ namespace gsx {
 constexpr int kBlockWaves = 4;
 constexpr int kBatch = kWave;   // list entries staged per wave and batch
 
+// Work counters (gs_set_work_counter): when set, [0] += (list slots a forward walk stepped
+// through) x (pixels of its wave), [1] += the same for the backward walks. A measurement aid:
+// the counts are the Gaussian-pixel pairs the kernels execute, padding and finished pixels
+// included, as opposed to the pairs the method defines.
+__constant__ unsigned long long *g_work_count = nullptr;
+
 // The wave's LDS slice for one batch of records.
 __device__ inline RasterRec *wave_slice()
 {
@@ -330,6 +336,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
 {
     bool snapped = snap_pos < 0;
     int walked = t.end - t.start;
+    int stepped = 0;   // list slots walked (work counters)
     const WaveRect wr = wave_rect<PX>(t, prm);
     RasterRec *slice = wave_slice();
     const int lane = threadIdx.x & (kWave - 1);
@@ -366,6 +373,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
                 for (int q = 1; q < PX; ++q) m = fmaxf(m, ps.T[q]);
                 if (__ballot(m >= 0.f) == 0) break;
             }
+            stepped += kGroup;
 #pragma unroll
             for (int j = 0; j < kGroup; ++j) {
             // the next record is read while this one is composited, and no further: the
@@ -402,6 +410,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
     if (!snapped) take_snapshot<PX>(ps, *sn);
 #pragma unroll
     for (int q = 0; q < PX; ++q) ps.T[q] = fabsf(ps.T[q]);
+    if (g_work_count && lane == 0) atomicAdd(&g_work_count[0], (unsigned long long)stepped * (kWave * PX));
     return walked;
 }
 
@@ -524,6 +533,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     RasterRec *slice = wave_slice();
     WaveAcc *acc = wave_acc();
     acc_clear(acc, lane);
+    int stepped = 0;   // list slots walked (work counters)
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
     // batch k covers entries [max(lo, e_k - 64), e_k) with e_k = kend - 64 k: its slots
     // are loaded two batches ahead, its records one batch ahead
@@ -540,6 +550,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         // records that miss the wave are left out of the staged batch
         const uint64_t keep = __ballot(lane < nb && !record_misses(next, wr));
         const int nk = __popcll(keep);
+        stepped += nk;
         stage_packed(slice, next, keep, lane, bstart - t.start + lane + 1);
         if (bstart > lo) next = gather(rr, nid);
         const int e2 = bstart - kBatch;   // end of the batch after next
@@ -641,6 +652,7 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         }
         acc_flush(slice, acc, nk, lane, out);
     }
+    if (g_work_count && lane == 0) atomicAdd(&g_work_count[1], (unsigned long long)stepped * (kWave * PX));
 }
 
 // ----------------------------------------------------------------------------- kernels
@@ -774,6 +786,7 @@ struct FusedIO {
     const float *target;
     float *image;   // optional
     float *loss;    // optional, accumulated sum of (C - target)^2
+    const int64_t *list_flags;   // gs_bins.counters: [1] != 0 when the list was not built
 };
 
 template <int PX>
@@ -845,6 +858,12 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
     BwdOut out, int prio, int grab, int prio_len, int n_tiles)
 {
     const int lane = threadIdx.x & (kWave - 1);
+    // no list (overflow or a failed sort): the step's result would be wrong, so the loss is
+    // set to NaN, which the caller sees without a host synchronisation, and nothing is done
+    if (io.list_flags[1] != 0) {
+        if (io.loss && blockIdx.x == 0 && threadIdx.x == 0) *io.loss = __builtin_nanf("");
+        return;
+    }
     const int n_items = __builtin_amdgcn_readfirstlane(sched[kSchedItems]);
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     const int segs = __builtin_amdgcn_readfirstlane(sched[kSchedSegs]);
@@ -877,13 +896,32 @@ static int check_raster_args(const gs_splats *s, const gs_bins *bins, const gs_c
     if (!s || !bins || !cams || !prm || n_cams < 1 || n_pixels < 0 || !s->raster || !bins->ids || !bins->ranges ||
         !bins->schedule || bins->n_tiles < 0)
         return set_error(GS_ERR_INVALID, "rasterize: null argument or bad size");
+    if (!(prm->alpha_max > 0.0f && prm->alpha_max <= 1.0f))
+        return set_error(GS_ERR_INVALID, "rasterize: alpha_max must be in (0, 1]");
     if (((uintptr_t)s->raster) & 63) return set_error(GS_ERR_INVALID, "rasterize: raster must be 64-byte aligned");
     return GS_OK;
+}
+
+// The thresholds as the kernels apply them. alpha_max = 1 (the literal image formation of
+// eq. 7) becomes the largest float32 below 1: then 1 - alpha >= 2^-24 for every composited
+// pair, so T after the pair stays positive and the backward's division of eq. (17) is
+// defined. Only alphas within 6e-8 of 1 (opacities that close to 1) are affected.
+static gs_params kernel_params(const gs_params *prm)
+{
+    gs_params k = *prm;
+    if (k.alpha_max >= 1.0f) k.alpha_max = 0x1.fffffep-1f;
+    return k;
 }
 
 }  // namespace gsx
 
 using namespace gsx;
+
+extern "C" int gs_set_work_counter(unsigned long long *counts)
+{
+    clear_error();
+    return check_hip(hipMemcpyToSymbol(HIP_SYMBOL(g_work_count), &counts, sizeof(counts)), "gs_set_work_counter");
+}
 
 extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const gs_camera *cams, int32_t n_cams,
                                 const gs_params *prm, int64_t n_pixels, float *image, float *T_final,
@@ -899,11 +937,11 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     const FwdOut o{n_pixels, image, T_final, last, visited};
     if (visited)
         hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, kernel_params(prm), o, current_tuning().split_priority,
                            current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     else
         hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, *prm, o, current_tuning().split_priority,
+                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, kernel_params(prm), o, current_tuning().split_priority,
                            current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_fwd");
 }
@@ -914,8 +952,6 @@ static int check_bwd_outputs(const gs_splats *s, int64_t n_splats, const gs_para
     if (!dL_dmean2d || !dL_dconic || !dL_dcolors || !dL_dopac || n_splats < 0 || n_splats > s->capacity ||
         n_gaussians < 1)
         return set_error(GS_ERR_INVALID, "rasterize backward: null gradient buffer or bad size");
-    if (!(prm->alpha_max < 1.0f))
-        return set_error(GS_ERR_INVALID, "rasterize backward: alpha_max must be below 1 (eq. 17 divides by 1 - alpha)");
     return GS_OK;
 }
 
@@ -936,7 +972,7 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
                      current_tuning().atomic_lanes};
     hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, in, out, current_tuning().split_priority,
+                       (int)n_cams, kernel_params(prm), in, out, current_tuning().split_priority,
                            current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_bwd");
 }
@@ -954,12 +990,13 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     rc = check_bwd_outputs(s, n_splats, prm, dL_dmean2d, dL_dconic, n_gaussians, dL_dcolors, dL_dopac);
     if (rc != GS_OK) return rc;
     if (bins->n_tiles == 0) return GS_OK;
-    const FusedIO io{n_pixels, target, image, loss};
+    if (!bins->counters) return set_error(GS_ERR_INVALID, "gs_rasterize_fused_l2: null bins->counters");
+    const FusedIO io{n_pixels, target, image, loss, (const int64_t *)bins->counters};
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac,
                      current_tuning().atomic_lanes};
     hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
                        (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, *prm, io, out, current_tuning().split_priority,
+                       (int)n_cams, kernel_params(prm), io, out, current_tuning().split_priority,
                            current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
     return check_launch("gs_rasterize_fused_l2");
 }

@@ -30,8 +30,8 @@ STANDARD_PARAMS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4)
 def make_params(alpha_min: float = STANDARD_PARAMS["alpha_min"], alpha_max: float = STANDARD_PARAMS["alpha_max"],
                 T_min: float = STANDARD_PARAMS["T_min"], background=(0.0, 0.0, 0.0)) -> abi.GsParams:
     """Compositing parameters: the thresholds (standard mode by default; literal mode is
-    alpha_min = 0, alpha_max = 1, T_min = 0, forward only) and the RGB background seen
-    through T_final (zero: the paper's image formation)."""
+    alpha_min = 0, alpha_max = 1, T_min = 0, the image formation of eq. 7 as printed) and
+    the RGB background seen through T_final (zero: the paper's image formation)."""
     bg = (ctypes.c_float * 3)(*[float(np.float32(x)) for x in background])
     return abi.GsParams(float(np.float32(alpha_min)), float(np.float32(alpha_max)), float(np.float32(T_min)), bg, 0)
 

@@ -57,7 +57,7 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert lib.gs_bin_and_sort(None, 0, None, 1, None, None, 0, None) == abi.GS_ERR_INVALID
     assert lib.gs_bin_and_sort_static(None, 0, None, 1, None, None) == abi.GS_ERR_INVALID
     assert lib.gs_rasterize_fwd(None, None, None, 1, None, 0, None, None, None, None, None) == abi.GS_ERR_INVALID
-    prm = abi.GsParams(0.0, 1.0, 0.0)
+    prm = abi.GsParams(0.0, 1.5, 0.0)          # alpha_max above 1: no valid compositing
     sp = abi.GsSplats(rec=64, raster=64, depth=64, rect=64, tiles_touched=64, capacity=10)
     bins = abi.GsBins(keys=64, ids=64, ranges=64, schedule=64, counters=64, capacity=10, n_tiles=1)
     rc = lib.gs_rasterize_bwd(abi._ref(sp), 10, abi._ref(bins), 16, 1, abi._ref(prm), 4, 16, 16, 16, 16, 16, 10, 16,

@@ -139,3 +139,75 @@ def test_camera_pose_gradient_many_cameras():
     print(f"camera-pose gradients of {len(wl.cameras)} cameras: rel err {e:.2e}")
     assert e <= GRAD_REL, e
     assert elementwise_ok(got, ref)
+
+
+@pytest.mark.parametrize("name", ["c1", "tilted", "c5_small"])
+def test_l2_loss_function_matches_oracle(name):
+    """The fused training form (autograd.l2_loss: one graph replay of project, sort, fused
+    forward + dL/dC + backward, project_bwd) against the oracle: the loss and every gradient,
+    over one camera or a batch of 32 cameras of 8 scenes, on repeated calls; near-tie pixels
+    get the GPU's own image as target (dL/dC exactly 0 there) and zero dL/dC in the oracle."""
+    _print_case("l2_loss", wl=name)
+    from paper_2312_02121_amd import pipeline
+    from paper_2312_02121_amd.autograd import l2_loss
+    from test_gpu_batched import small_c5
+    wl = {"c1": lambda: synth.make_config(1),
+          "tilted": lambda: synth.tilted_camera_scene(50, n=120, width=70, height=45), "c5_small": small_c5}[name]()
+    prm = oracle_params()
+    sizes = [s["opacities"].shape[0] for s in wl.scenes]
+    ps = [torch.tensor(np.concatenate([np.asarray(s[k]) for s in wl.scenes], axis=-1), device="cuda",
+                       requires_grad=True) for k in KEYS]
+    cams = pipeline.CameraSet(wl.cameras, sizes)
+    # the GPU image, for the near-tie pixels' targets
+    from paper_2312_02121_amd.autograd import render
+    with torch.no_grad():
+        imgs = render(*[p.detach() for p in ps], wl.cameras, scene_sizes=sizes)
+    tgt = np.concatenate([t.reshape(3, -1) for t in wl.targets], axis=1).astype(np.float32)
+    ref = {k: [np.zeros(np.asarray(s[k]).shape) for s in wl.scenes] for k in KEYS}
+    loss_ref = 0.0
+    for k, cam in enumerate(wl.cameras):
+        orc = oracle.render(wl.scenes[cam.scene], cam, prm)
+        fl = orc["flags"] != 0
+        off, H, W = cams.image_slice(k)
+        t = tgt[:, off:off + H * W].reshape(3, H, W)
+        t[:, fl] = imgs[k].cpu().numpy()[:, fl]
+        l, dL = oracle.loss_l2(orc["C"], t)
+        dL[:, fl] = 0.0
+        loss_ref += l
+        og = oracle.render_backward(wl.scenes[cam.scene], cam, prm, dL, state=orc)
+        for key in KEYS:
+            ref[key][cam.scene] += og[key]
+    target = torch.from_numpy(tgt).cuda()
+    for rep in range(3):
+        for p in ps:
+            p.grad = None
+        loss = l2_loss(*ps, wl.cameras, target, scene_sizes=sizes)
+        loss.backward()
+        torch.cuda.synchronize()
+        assert abs(float(loss) - loss_ref) <= 1e-5 * loss_ref, (rep, float(loss), loss_ref)
+        for k, p in zip(KEYS, ps):
+            got = p.grad.detach().cpu().numpy().astype(np.float64)
+            r = np.concatenate(ref[k], axis=-1)
+            assert rel_err(got, r) <= GRAD_REL, (rep, k, rel_err(got, r))
+            assert elementwise_ok(got, r), (rep, k)
+
+
+def test_l2_loss_overflow_gives_nan_then_regrows():
+    """A list that outgrows the captured step's capacity: that call's loss is NaN (the fused
+    launch sees the overflow flag) without any host synchronisation, and the next call, after
+    the step has finished, regrows the list and is valid again."""
+    _print_case("l2_overflow", wl="c1")
+    from paper_2312_02121_amd.autograd import l2_loss
+    wl = synth.make_config(1)
+    ps = [torch.tensor(np.asarray(wl.scenes[0][k]), device="cuda", requires_grad=True) for k in KEYS]
+    target = torch.from_numpy(wl.targets[0].reshape(3, -1)).cuda()
+    first = float(l2_loss(*ps, wl.cameras, target))
+    assert np.isfinite(first)
+    with torch.no_grad():
+        ps[2].mul_(8.0)              # scales x8: every box covers far more tiles
+    torch.cuda.synchronize()
+    assert np.isnan(float(l2_loss(*ps, wl.cameras, target)))
+    torch.cuda.synchronize()
+    grown = l2_loss(*ps, wl.cameras, target)
+    grown.backward()
+    assert np.isfinite(float(grown)) and float(grown) != first

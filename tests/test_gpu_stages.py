@@ -102,3 +102,33 @@ def test_per_stage_equals_fused_form_without_modification():
     assert np.abs(outs[0][0] - outs[1][0]).max() <= 1e-5
     for k in KEYS:
         assert rel_err(outs[1][1][k], outs[0][1][k]) <= 1e-4, k
+
+
+def test_per_stage_culls_non_positive_depth():
+    """Depth keys are float bits of the depth, which order only positive values: a slot
+    given a depth that is zero, negative or not finite is culled, on the GPU as in the oracle."""
+    _print_case("per_stage_depth", wl="c1")
+    from paper_2312_02121_amd import pipeline
+    wl = _workload("c1")
+    scene, cam = wl.scenes[0], wl.cameras[0]
+    prm = oracle_params()
+    pr = oracle.project(scene, cam, prm)
+    valid = (pr["tiles"] > 0).astype(np.int32)
+    depth = pr["depth"].astype(np.float32)
+    vis = np.nonzero(valid)[0]
+    depth[vis[0::4]] = 0.0
+    depth[vis[1::4]] = -depth[vis[1::4]]
+    depth[vis[2::8]] = np.nan
+    two = oracle.splats_from_2d(pr["mean2d"], pr["conic"], depth.astype(np.float64), valid, cam, prm)
+    g = pipeline.GaussianSet([scene])
+    cams = pipeline.CameraSet([cam], g.sizes)
+    r = pipeline.Rasterizer(cams)
+    P = cams.n_splats
+    st = r.forward_2d(g, torch.from_numpy(pr["mean2d"].astype(np.float32)).cuda().contiguous(),
+                      torch.from_numpy(pr["conic"].astype(np.float32)).cuda().contiguous(),
+                      torch.from_numpy(depth).cuda(), torch.from_numpy(valid).cuda())
+    torch.cuda.synchronize()
+    tiles = r.splats.tiles[:P].cpu().numpy()
+    assert np.array_equal(tiles, two["tiles"])
+    assert (tiles[vis[0::4]] == 0).all() and (tiles[vis[1::4]] == 0).all()
+    assert st.K == int(two["tiles"].sum())

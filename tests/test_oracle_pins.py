@@ -136,6 +136,21 @@ def test_near_far_culling():
         assert st["visible"] == vis, z
 
 
+def test_depth_keys_need_positive_depth():
+    """The depth order of Sec. 2.2 is taken on float32 bits of t_z, which order only positive
+    values: with a near plane at or behind the camera, t_z <= 0 is still culled, and the
+    per-stage input culls a depth that is not positive and finite."""
+    cam = _cam()
+    cam.near = -1.0
+    for z, vis in [(-0.5, False), (0.0, False), (1e-3, True), (3.0, True)]:
+        assert oracle.project_state([0, 0, z], [1, 0, 0, 0], [0.01] * 3, cam)["visible"] == vis, z
+    m = np.array([[32.5, 32.5, 32.5, 32.5], [32.5, 32.5, 32.5, 32.5]])
+    Y = np.array([[1.0] * 4, [0.0] * 4, [1.0] * 4])
+    d = np.array([3.0, 0.0, -2.0, np.nan])
+    out = oracle.splats_from_2d(m, Y, d, np.ones(4, np.int32), _cam(), oracle.Params.standard())
+    assert list(out["tiles"] > 0) == [True, False, False, False]
+
+
 def test_nonfinite_and_degenerate_inputs_are_culled():
     cam = _cam()
     assert not oracle.project_state([np.nan, 0, 3], [1, 0, 0, 0], [0.1] * 3, cam)["visible"]
