@@ -182,9 +182,10 @@ typedef struct gs_tuning {
                                 counter, 1..16 (fewer atomics on one address when items are
                                 many and short; more imbalance at the end of the list) */
     int32_t prio_len;        /* a wave also raises its issue priority on an unsplit tile whose
-                                list has at least this many entries; 0: never. Long walks are
-                                the end of the launch: priority keeps them at full speed while
-                                the SIMD is shared */
+                                walk has at least this many entries (level 1; level 2 from
+                                twice as many; split items take level 3); 0: never. Long walks
+                                are the end of the launch: priority keeps them near full speed
+                                while the SIMD is shared */
     int32_t bwd_segs;        /* 1, 2 or 4: the fused kernel walks the backward of a split tile's
                                 part as this many list segments, one work item each (every
                                 such item repeats the part's forward), so that the longest
@@ -238,6 +239,16 @@ int gs_set_work_counter(unsigned long long *counts);
 
 /* Zeroes `bytes` bytes at device pointer `ptr` with a kernel (graph-capturable). */
 int gs_zero(void *ptr, size_t bytes, void *stream);
+
+/*
+ * Zeroes dL_dmean2d [2][n_splats] and dL_dconic [3][n_splats] (float64, the per-slot
+ * gradients of gs_rasterize_bwd / gs_rasterize_fused_l2) at the slots the projection listed
+ * (s->tiles_touched > 0) only: those are the only slots the rasterizer adds to and
+ * gs_project_bwd reads, so this is enough before a backward that follows the same
+ * projection. Culled slots keep whatever they held. Graph-capturable.
+ */
+int gs_zero_listed_slot_grads(const gs_splats *s, int64_t n_splats, double *dL_dmean2d, double *dL_dconic,
+                              void *stream);
 
 /*
  * Host-only query of the ABI struct layout, for bindings that mirror the structs:

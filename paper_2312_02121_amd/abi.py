@@ -25,7 +25,7 @@ EXPORTED = (
     "gs_project", "gs_schedule_size", "gs_bin_and_sort_workspace_size", "gs_bin_and_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
     "gs_project_bwd", "gs_l2_grad", "gs_rasterize_fused_l2", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
     "gs_graph_destroy", "gs_set_tuning", "gs_get_tuning", "gs_splats_from_2d", "gs_bin_and_sort_static",
-    "gs_set_sort_wait_limit", "gs_set_work_counter",
+    "gs_set_sort_wait_limit", "gs_set_work_counter", "gs_zero_listed_slot_grads",
 )
 
 DEFAULT_SORT_WAIT_LIMIT = 1 << 20
@@ -130,6 +130,7 @@ def lib():
         "gs_bin_and_sort_static": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P]),
         "gs_set_sort_wait_limit": (ctypes.c_int, [_I32]),
         "gs_set_work_counter": (ctypes.c_int, [_P]),
+        "gs_zero_listed_slot_grads": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
         "gs_rasterize_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
         "gs_rasterize_bwd": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
         "gs_project_bwd": (ctypes.c_int, [_P, _P, _I32, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
@@ -203,6 +204,11 @@ def gs_bin_and_sort(splats: GsSplats, n_splats: int, cams_ptr: int, n_cams: int,
 
 def gs_set_sort_wait_limit(polls: int):
     _check("gs_set_sort_wait_limit", lib().gs_set_sort_wait_limit(polls))
+
+
+def gs_zero_listed_slot_grads(splats: GsSplats, n_splats: int, dmean2d: int, dconic: int, stream: int):
+    _check("gs_zero_listed_slot_grads", lib().gs_zero_listed_slot_grads(_ref(splats), n_splats, dmean2d, dconic,
+                                                                        stream))
 
 
 def gs_set_work_counter(ptr: int | None):

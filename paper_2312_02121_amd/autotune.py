@@ -38,7 +38,7 @@ KNOBS = {
     "waves_per_cu": (16, 32),
     "split_priority": (0, 1),
     "generate_entries": (0, 1),
-    "prio_len": (0, 256, 512, 1024),
+    "prio_len": (0, 96, 128, 192, 256, 512),
     "bwd_segs": (1, 2, 4),
     "atomic_lanes": (2, 4, 8),
 }

@@ -1,5 +1,5 @@
 // gs_project: projection of 3D Gaussians (Sec. 2.1, eqs. 1-6) and their 3-sigma tile
-// boxes (Sec. 2.2). One thread per (camera, Gaussian) slot.
+// boxes (Sec. 2.2). One thread per scene Gaussian, projected into every camera that views it.
 //
 // The arithmetic runs in float64 without FMA contraction and every sum is evaluated
 // left to right in the order the equations are written (matrix products row by
@@ -57,23 +57,26 @@ __device__ inline RasterRec make_record(float mx, float my, float y00, float y01
     return rr;
 }
 
-__global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
-                                                      int n_cams, int64_t n_splats, float4 *__restrict__ rec,
-                                                      RasterRec *__restrict__ rrec, float *__restrict__ depth_out,
-                                                      int4 *__restrict__ rect_out, int32_t *__restrict__ tiles_out)
+// One scene Gaussian as the projection reads it: mean, (normalised) quaternion and scale in
+// float64, whether all of them are finite, and Sigma = M M^T with M = R(q) S (eqs. 5, 6), which
+// does not depend on the camera.
+struct GaussIn {
+    double mx, my, mz;
+    bool finite;
+    double S00, S01, S02, S11, S12, S22;
+};
+
+__device__ inline GaussIn load_gaussian(const gs_gaussians &g, int64_t i)
 {
 #pragma clang fp contract(off)
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_splats) return;
-    const int c = camera_of_splat(cams, n_cams, p);
-    const gs_camera &cam = cams[c];
     const int64_t n = g.n;
-    const int64_t i = cam.gauss_offset + (p - cam.proj_offset);
-
-    const double mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
+    GaussIn gi;
+    gi.mx = g.means[i];
+    gi.my = g.means[n + i];
+    gi.mz = g.means[2 * n + i];
     double qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     if (g.flags & GS_NORMALIZE_QUATS) {
-        // q / |q|; a zero or non-finite q gives a non-finite result, which is culled below
+        // q / |q|; a zero or non-finite q gives a non-finite result, which is culled
         const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
         qw = qw / qn;
         qx = qx / qn;
@@ -81,10 +84,33 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
         qz = qz / qn;
     }
     const double s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
+    gi.finite = isfinite(gi.mx) && isfinite(gi.my) && isfinite(gi.mz) && isfinite(qw) && isfinite(qx) &&
+                isfinite(qy) && isfinite(qz) && isfinite(s0) && isfinite(s1) && isfinite(s2);
+    // R(q), eq. (5) with R11 = 1 - 2(x^2 + z^2); M = R S; Sigma = M M^T (eq. 6)
+    const double q00 = 1.0 - 2.0 * (qy * qy + qz * qz), q01 = 2.0 * (qx * qy - qw * qz), q02 = 2.0 * (qx * qz + qw * qy);
+    const double q10 = 2.0 * (qx * qy + qw * qz), q11 = 1.0 - 2.0 * (qx * qx + qz * qz), q12 = 2.0 * (qy * qz - qw * qx);
+    const double q20 = 2.0 * (qx * qz - qw * qy), q21 = 2.0 * (qy * qz + qw * qx), q22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+    const double M00 = q00 * s0, M01 = q01 * s1, M02 = q02 * s2;
+    const double M10 = q10 * s0, M11 = q11 * s1, M12 = q12 * s2;
+    const double M20 = q20 * s0, M21 = q21 * s1, M22 = q22 * s2;
+    gi.S00 = M00 * M00 + M01 * M01 + M02 * M02;
+    gi.S01 = M00 * M10 + M01 * M11 + M02 * M12;
+    gi.S02 = M00 * M20 + M01 * M21 + M02 * M22;
+    gi.S11 = M10 * M10 + M11 * M11 + M12 * M12;
+    gi.S12 = M10 * M20 + M11 * M21 + M12 * M22;
+    gi.S22 = M20 * M20 + M21 * M21 + M22 * M22;
+    return gi;
+}
 
-    int visible = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(qw) && isfinite(qx) &&
-                  isfinite(qy) && isfinite(qz) && isfinite(s0) && isfinite(s1) && isfinite(s2);
-
+// The projection of Gaussian i (loaded as gi) through camera c into its slot p.
+__device__ inline void project_slot(const gs_gaussians &g, const gs_camera &cam, int c, int64_t i, int64_t p,
+                                    const GaussIn &gi, float4 *__restrict__ rec, RasterRec *__restrict__ rrec,
+                                    float *__restrict__ depth_out, int4 *__restrict__ rect_out,
+                                    int32_t *__restrict__ tiles_out)
+{
+#pragma clang fp contract(off)
+    const int64_t n = g.n;
+    const double mx = gi.mx, my = gi.my, mz = gi.mz;
     // t = T_cw [mu; 1]
     const double R00 = cam.R[0], R01 = cam.R[1], R02 = cam.R[2];
     const double R10 = cam.R[3], R11 = cam.R[4], R12 = cam.R[5];
@@ -94,8 +120,8 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     const double tz = R20 * mx + R21 * my + R22 * mz + (double)cam.t[2];
     // depth keys are the float bits of t_z, which order depths correctly only when t_z > 0:
     // a near plane at or behind the camera still culls t_z <= 0
-    visible = visible && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz > 0.0 &&
-              tz < (double)cam.far_plane;
+    bool visible = gi.finite && isfinite(tx) && isfinite(ty) && tz > (double)cam.near_plane && tz > 0.0 &&
+                   tz < (double)cam.far_plane;
 
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
     RasterRec rr = {};
@@ -104,20 +130,6 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
     float dep = 0.f;
 
     if (visible) {
-        // R(q), eq. (5) with R11 = 1 - 2(x^2 + z^2); M = R S; Sigma = M M^T (eq. 6)
-        const double q00 = 1.0 - 2.0 * (qy * qy + qz * qz), q01 = 2.0 * (qx * qy - qw * qz), q02 = 2.0 * (qx * qz + qw * qy);
-        const double q10 = 2.0 * (qx * qy + qw * qz), q11 = 1.0 - 2.0 * (qx * qx + qz * qz), q12 = 2.0 * (qy * qz - qw * qx);
-        const double q20 = 2.0 * (qx * qz - qw * qy), q21 = 2.0 * (qy * qz + qw * qx), q22 = 1.0 - 2.0 * (qx * qx + qy * qy);
-        const double M00 = q00 * s0, M01 = q01 * s1, M02 = q02 * s2;
-        const double M10 = q10 * s0, M11 = q11 * s1, M12 = q12 * s2;
-        const double M20 = q20 * s0, M21 = q21 * s1, M22 = q22 * s2;
-        const double S00 = M00 * M00 + M01 * M01 + M02 * M02;
-        const double S01 = M00 * M10 + M01 * M11 + M02 * M12;
-        const double S02 = M00 * M20 + M01 * M21 + M02 * M22;
-        const double S11 = M10 * M10 + M11 * M11 + M12 * M12;
-        const double S12 = M10 * M20 + M11 * M21 + M12 * M22;
-        const double S22 = M20 * M20 + M21 * M21 + M22 * M22;
-
         // t' = P t with P of eq. (1); mu' of eq. (2)
         const double w = (double)cam.width, h = (double)cam.height;
         const double fx = cam.fx, fy = cam.fy;
@@ -133,12 +145,12 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
         const double T10 = J11 * R10 + J12 * R20, T11 = J11 * R11 + J12 * R21, T12 = J11 * R12 + J12 * R22;
 
         // Sigma' = (T Sigma) T^T, eq. (4)
-        const double U00 = T00 * S00 + T01 * S01 + T02 * S02;
-        const double U01 = T00 * S01 + T01 * S11 + T02 * S12;
-        const double U02 = T00 * S02 + T01 * S12 + T02 * S22;
-        const double U10 = T10 * S00 + T11 * S01 + T12 * S02;
-        const double U11 = T10 * S01 + T11 * S11 + T12 * S12;
-        const double U12 = T10 * S02 + T11 * S12 + T12 * S22;
+        const double U00 = T00 * gi.S00 + T01 * gi.S01 + T02 * gi.S02;
+        const double U01 = T00 * gi.S01 + T01 * gi.S11 + T02 * gi.S12;
+        const double U02 = T00 * gi.S02 + T01 * gi.S12 + T02 * gi.S22;
+        const double U10 = T10 * gi.S00 + T11 * gi.S01 + T12 * gi.S02;
+        const double U11 = T10 * gi.S01 + T11 * gi.S11 + T12 * gi.S12;
+        const double U12 = T10 * gi.S02 + T11 * gi.S12 + T12 * gi.S22;
         const double C00 = U00 * T00 + U01 * T01 + U02 * T02;
         const double C01 = U00 * T10 + U01 * T11 + U02 * T12;
         const double C11 = U10 * T10 + U11 * T11 + U12 * T12;
@@ -173,6 +185,29 @@ __global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_c
         rrec[p] = rr;
         depth_out[p] = dep;
         rect_out[p] = box;
+    }
+}
+
+// Gaussian-major: one thread per scene Gaussian, which is read once and projected into the
+// slot of every camera that views its scene (cameras hold contiguous slices of the Gaussian
+// planes and of the slots). A wave holds 64 consecutive Gaussians, so each camera's slots are
+// written 64 at a time, coalesced, and a batch of views reads the Gaussians once instead of
+// once per view.
+__global__ __launch_bounds__(256) void project_kernel(gs_gaussians g, const gs_camera *__restrict__ cams,
+                                                      int n_cams, int64_t n_splats, float4 *__restrict__ rec,
+                                                      RasterRec *__restrict__ rrec, float *__restrict__ depth_out,
+                                                      int4 *__restrict__ rect_out, int32_t *__restrict__ tiles_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const GaussIn gi = load_gaussian(g, i);
+    for (int c = 0; c < n_cams; ++c) {
+        const gs_camera &cam = cams[c];
+        const int64_t k = i - cam.gauss_offset;
+        if (k < 0 || k >= cam.gauss_count) continue;
+        const int64_t p = cam.proj_offset + k;
+        if (p >= n_splats) continue;
+        project_slot(g, cam, c, i, p, gi, rec, rrec, depth_out, rect_out, tiles_out);
     }
 }
 
@@ -259,7 +294,7 @@ extern "C" int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t 
         return set_error(GS_ERR_INVALID, "gs_project: null plane");
     if ((((uintptr_t)out->rec) & 15) || (((uintptr_t)out->rect) & 15) || (((uintptr_t)out->raster) & 63))
         return set_error(GS_ERR_INVALID, "gs_project: rec/rect must be 16-byte and raster 64-byte aligned");
-    hipLaunchKernelGGL(project_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream, *g, cams,
+    hipLaunchKernelGGL(project_kernel, dim3(grid_for(g->n, 256)), dim3(256), 0, (hipStream_t)stream, *g, cams,
                        (int)n_cams, n_splats, (float4 *)out->rec, (RasterRec *)out->raster, out->depth,
                        (int4 *)out->rect, out->tiles_touched);
     return check_launch("gs_project");

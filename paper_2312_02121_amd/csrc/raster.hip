@@ -11,8 +11,8 @@
 // snapshots T and the colour at the segment's end). The kernels are persistent: every wave
 // takes items from an atomic counter until the list is exhausted, and the last wave out
 // resets the counter so the next launch (or graph replay) starts from zero. A wave may raise
-// its issue priority (s_setprio) while it works on a split item or a long unsplit tile, so
-// that the longest walks keep their SIMD.
+// its issue priority (s_setprio) while it works on a split item or a long unsplit tile, in
+// levels by walk length, so that the longest walks keep most of their SIMD.
 //
 // Records. A wave walks its list in batches of 64 entries. For each batch every lane
 // gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
@@ -259,20 +259,31 @@ __device__ inline int next_item(int32_t *__restrict__ sched, int counter, int n_
     return -1;
 }
 
-// An unsplit tile whose walk has at least prio_len entries (prio_len > 0; the list length,
-// or the walk length the last rasterization recorded when it is shorter): its walk is among
-// the last to finish, so its wave takes issue priority.
-__device__ inline bool long_walk(const int32_t *__restrict__ ranges, const int32_t *__restrict__ sched,
-                                 int n_tiles, int item, int prio_len)
+// Issue priority of an unsplit tile (prio_len > 0): 2 when its walk has at least 2 prio_len
+// entries, 1 from prio_len, else 0 (the walk: the list length, or the walk length the last
+// rasterization recorded when it is shorter). Long walks are the end of the launch; under a
+// full GPU a wave gets about a quarter of its SIMD, so the longest walks, started first,
+// would run four times longer than alone. Graded levels give the longest the first claim on
+// issue and let shorter ones fill the cycles they leave (split items take level 3).
+__device__ inline int walk_priority(const int32_t *__restrict__ ranges, const int32_t *__restrict__ sched,
+                                    int n_tiles, int item, int prio_len)
 {
-    if (prio_len <= 0) return false;
+    if (prio_len <= 0) return 0;
     const int tile = item >> kItemTileShift;
     int len = ranges[2 * tile + 1] - ranges[2 * tile];
     if (sched[kSchedWalkStamp] == n_tiles) {
         const int walk = sched[sched_walk_offset(n_tiles) + tile];
         if (walk >= 1 && walk < len) len = walk;
     }
-    return len >= prio_len;
+    return len >= 2 * prio_len ? 2 : len >= prio_len ? 1 : 0;
+}
+
+// s_setprio takes an immediate: one branch per level (wave-uniform)
+__device__ inline void set_priority(int level)
+{
+    if (level >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (level == 2) __builtin_amdgcn_s_setprio(2);
+    else if (level == 1) __builtin_amdgcn_s_setprio(1);
 }
 
 // ----------------------------------------------------------------------------- forward
@@ -571,7 +582,9 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
             // per-lane sums over the lane's pixels; the lane's pixels share one row, so the
             // dy-weighted sums follow from sum v and sum v dx. The position sums are float64:
             // dL/dY along the thin axis of a needle-like splat is a small difference of
-            // these sums, which float32 rounding would swamp.
+            // these sums, which float32 rounding would swamp. (Float32 moments sum q^k v of
+            // the lane's pixels, combined in float64 once per splat, lost enough of it to move
+            // single quaternion gradients past the 1e-3 bar.)
             double s_v = 0.0, s_x = 0.0, s_xx = 0.0;
             float s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
             float live_sum = 0.f;
@@ -701,7 +714,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
         if (item < 0) break;
         if ((item >> 3) & 3) continue;   // a backward segment of the fused kernel
         if (item & 4) {
-            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (prio) set_priority(3);
             if (parts == 4)
                 fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                       item);
@@ -710,7 +723,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
                                       item);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
             fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                   item);
             __builtin_amdgcn_s_setprio(0);
@@ -766,14 +779,14 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
         if (item < 0) break;
         if ((item >> 3) & 3) continue;   // a backward segment of the fused kernel
         if (item & 4) {
-            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (prio) set_priority(3);
             if (parts == 4)
                 bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
             else
                 bwd_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
             bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         }
@@ -873,7 +886,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
         if (item < 0) break;
         if (item & 4) {
             const int seg = (item >> 3) & 3;
-            if (prio) __builtin_amdgcn_s_setprio(2);
+            if (prio) set_priority(3);
             if (parts == 4)
                 fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
                               sched, n_tiles, item);
@@ -882,7 +895,7 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
                               sched, n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            if (long_walk(ranges, sched, n_tiles, item, prio_len)) __builtin_amdgcn_s_setprio(2);
+            set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
             fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
                           n_tiles, item);
             __builtin_amdgcn_s_setprio(0);

@@ -67,9 +67,35 @@ __global__ __launch_bounds__(256) void zero_kernel(uint4 *__restrict__ p16, int6
     if (i < ntail) tail[i] = 0;
 }
 
+// Zeroes the per-slot gradients dL/dmu' [2][n] and dL/dY [3][n] of the listed slots
+// (tiles_touched > 0), the only ones the rasterizer backward adds to and gs_project_bwd reads.
+__global__ __launch_bounds__(256) void zero_listed_kernel(const int32_t *__restrict__ tiles, int64_t n,
+                                                          double *__restrict__ dm, double *__restrict__ dc)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || tiles[p] <= 0) return;
+    dm[p] = 0.0;
+    dm[n + p] = 0.0;
+    dc[p] = 0.0;
+    dc[n + p] = 0.0;
+    dc[2 * n + p] = 0.0;
+}
+
 }  // namespace gsx
 
 using namespace gsx;
+
+extern "C" int gs_zero_listed_slot_grads(const gs_splats *s, int64_t n_splats, double *dL_dmean2d, double *dL_dconic,
+                                         void *stream)
+{
+    clear_error();
+    if (!s || !s->tiles_touched || !dL_dmean2d || !dL_dconic || n_splats < 0 || n_splats > s->capacity)
+        return set_error(GS_ERR_INVALID, "gs_zero_listed_slot_grads: null argument or bad size");
+    if (n_splats == 0) return GS_OK;
+    hipLaunchKernelGGL(zero_listed_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const int32_t *)s->tiles_touched, n_splats, dL_dmean2d, dL_dconic);
+    return check_launch("gs_zero_listed_slot_grads");
+}
 
 extern "C" int gs_last_hip_error(void) { return t_hip_error; }
 
