@@ -194,6 +194,8 @@ typedef struct gs_tuning {
                                 alpha sit in at most this many lanes of a wave is summed with
                                 LDS atomics from those lanes; otherwise the wave sums it with
                                 DPP row operations (cheaper for large splats) */
+    int32_t batch;           /* 32 or 64: list entries a wave stages in LDS per batch (one per
+                                lane; gradients are moved to memory once per batch) */
 } gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */

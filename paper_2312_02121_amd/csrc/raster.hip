@@ -41,7 +41,10 @@
 namespace gsx {
 
 constexpr int kBlockWaves = 4;
-constexpr int kBatch = kWave;   // list entries staged per wave and batch
+// List entries staged per wave and batch: B = 32 or 64 (launch tuning, gs_tuning.batch; a
+// template parameter of the walks). One lane gathers one record, so B <= 64; the LDS slices
+// are sized for 64.
+constexpr int kBatch = kWave;
 
 // Work counters (gs_set_work_counter): when set, [0] += (list slots a forward walk stepped
 // through) x (pixels of its wave), [1] += the same for the backward walks. A measurement aid:
@@ -340,7 +343,7 @@ __device__ inline void take_snapshot(const PixState<PX> &ps, Snapshot<PX> &sn)
 // snap_pos set (a list position t.start + 64 m), sn receives the state before entry
 // snap_pos (the final state if the walk ends earlier). Returns the number of list entries
 // the walk went through (to the batch in which its last pixel finished).
-template <int PX, bool kVisited>
+template <int PX, bool kVisited, int B>
 __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
                                 const gs_params &prm, PixState<PX> &ps, int snap_pos = -1,
                                 Snapshot<PX> *sn = nullptr)
@@ -353,20 +356,20 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
     const int lane = threadIdx.x & (kWave - 1);
     // batch k covers entries [t.start + 64 k, ...): its slots are loaded two batches ahead,
     // its records one batch ahead
-    Gathered next = gather(rr, load_ids(ids, t.start, t.end - t.start, lane));
-    int nid = load_ids(ids, t.start + kBatch, t.end - t.start - kBatch, lane);
-    for (int b = t.start; b < t.end; b += kBatch) {
+    Gathered next = gather(rr, load_ids(ids, t.start, min(B, t.end - t.start), lane));
+    int nid = load_ids(ids, t.start + B, min(B, t.end - t.start - B), lane);
+    for (int b = t.start; b < t.end; b += B) {
         if (!snapped && b == snap_pos) {
             take_snapshot<PX>(ps, *sn);
             snapped = true;
         }
-        const int nb = min(kBatch, t.end - b);
+        const int nb = min(B, t.end - b);
         // records that miss the wave are left out of the staged batch; the counting pass
         // (kVisited) counts every pair it reaches and keeps them all
         const uint64_t keep = __ballot(lane < nb && (kVisited || !record_misses(next, wr)));
         const int np = stage_packed(slice, next, keep, lane, b - t.start + lane + 1);
-        if (b + kBatch < t.end) next = gather(rr, nid);
-        if (b + 2 * kBatch < t.end) nid = load_ids(ids, b + 2 * kBatch, t.end - b - 2 * kBatch, lane);
+        if (b + B < t.end) next = gather(rr, nid);
+        if (b + 2 * B < t.end) nid = load_ids(ids, b + 2 * B, min(B, t.end - b - 2 * B), lane);
         float tmax = ps.T[0];
 #pragma unroll
         for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
@@ -391,7 +394,7 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             // barrier lets only VALU and SALU work move across it, so later LDS reads are not
             // hoisted (two records in registers at most)
             const RasterRec r = rn;
-            rn = slice[j < kGroup - 1 ? j0 + j + 1 : min(j0 + kGroup, kBatch - 1)];
+            rn = slice[j < kGroup - 1 ? j0 + j + 1 : min(j0 + kGroup, B - 1)];
             __builtin_amdgcn_sched_barrier(0x0006);
             const double dy = (double)r.my - ps.pyd;
             const double bdy = r.B * dy;
@@ -527,7 +530,7 @@ __device__ inline void acc_flush(const RasterRec *slice, WaveAcc *acc, int nk, i
 // (T_final for the whole list), gS the sum of dL/dC(k) S(k) over the entries from hi on
 // (zero for the whole list), last the start positions and g0..g2 the upstream gradient
 // dL/dC of each pixel.
-template <int PX>
+template <int PX, int B>
 __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const ItemPixels &t,
                                 const gs_params &prm, const PixState<PX> &ps, float (&T)[PX], float (&gS)[PX],
                                 const float (&g0)[PX], const float (&g1)[PX], const float (&g2)[PX],
@@ -548,15 +551,15 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
     // batches run back to front: [bstart, bend) with bend = kend, kend - 64, ...
     // batch k covers entries [max(lo, e_k - 64), e_k) with e_k = kend - 64 k: its slots
     // are loaded two batches ahead, its records one batch ahead
-    const int s0 = max(lo, kend - kBatch);
+    const int s0 = max(lo, kend - B);
     Gathered next = gather(rr, load_ids(ids, s0, kend - s0, lane));
     int nid = -1;
     if (s0 > lo) {
-        const int s1 = max(lo, s0 - kBatch);
+        const int s1 = max(lo, s0 - B);
         nid = load_ids(ids, s1, s0 - s1, lane);
     }
-    for (int bend = kend; bend > lo; bend -= kBatch) {
-        const int bstart = max(lo, bend - kBatch);
+    for (int bend = kend; bend > lo; bend -= B) {
+        const int bstart = max(lo, bend - B);
         const int nb = bend - bstart;
         // records that miss the wave are left out of the staged batch
         const uint64_t keep = __ballot(lane < nb && !record_misses(next, wr));
@@ -564,9 +567,9 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         stepped += nk;
         stage_packed(slice, next, keep, lane, bstart - t.start + lane + 1);
         if (bstart > lo) next = gather(rr, nid);
-        const int e2 = bstart - kBatch;   // end of the batch after next
+        const int e2 = bstart - B;   // end of the batch after next
         if (e2 > lo) {
-            const int s2 = max(lo, e2 - kBatch);
+            const int s2 = max(lo, e2 - B);
             nid = load_ids(ids, s2, e2 - s2, lane);
         }
         RasterRec rn = slice[max(nk - 1, 0)];
@@ -676,14 +679,14 @@ struct FwdOut {
     int32_t *last_out, *visited_out;
 };
 
-template <int PX, bool kVisited>
+template <int PX, bool kVisited, int B>
 __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
                                 const ItemPixels &t, const gs_params &prm, const FwdOut &o, int32_t *sched,
                                 int n_tiles, int item)
 {
     PixState<PX> ps;
     init_state<PX>(t, ps);
-    record_walk(sched, n_tiles, item, fwd_walk<PX, kVisited>(rr, ids, t, prm, ps));
+    record_walk(sched, n_tiles, item, fwd_walk<PX, kVisited, B>(rr, ids, t, prm, ps));
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
         if (pixel_inside<PX>(t, q)) {
@@ -699,7 +702,7 @@ __device__ inline void fwd_item(const RasterRec *__restrict__ rr, const int32_t 
     }
 }
 
-template <bool kVisited>
+template <bool kVisited, int B>
 __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FwdOut o, int prio, int grab, int prio_len,
@@ -716,15 +719,15 @@ __global__ __launch_bounds__(kWave * kBlockWaves) void raster_fwd_kernel(
         if (item & 4) {
             if (prio) set_priority(3);
             if (parts == 4)
-                fwd_item<1, kVisited>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+                fwd_item<1, kVisited, B>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                       item);
             else
-                fwd_item<2, kVisited>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+                fwd_item<2, kVisited, B>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                       item);
             __builtin_amdgcn_s_setprio(0);
         } else {
             set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
-            fwd_item<4, kVisited>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
+            fwd_item<4, kVisited, B>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, o, sched, n_tiles,
                                   item);
             __builtin_amdgcn_s_setprio(0);
         }
@@ -737,7 +740,7 @@ struct BwdIn {
     const int32_t *last_in;
 };
 
-template <int PX>
+template <int PX, int B>
 __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
                                 const ItemPixels &t, const gs_params &prm, const BwdIn &in, const BwdOut &out)
 {
@@ -762,9 +765,10 @@ __device__ inline void bwd_item(const RasterRec *__restrict__ rr, const int32_t 
 #pragma unroll
     for (int q = 0; q < PX; ++q)
         gS[q] = (g0[q] * prm.background[0] + g1[q] * prm.background[1] + g2[q] * prm.background[2]) * T[q];
-    bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, t.start, t.end);
+    bwd_walk<PX, B>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, t.start, t.end);
 }
 
+template <int B>
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_bwd_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, BwdIn in, BwdOut out,
@@ -781,13 +785,13 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
         if (item & 4) {
             if (prio) set_priority(3);
             if (parts == 4)
-                bwd_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
+                bwd_item<1, B>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, in, out);
             else
-                bwd_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
+                bwd_item<2, B>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         } else {
             set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
-            bwd_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
+            bwd_item<4, B>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, in, out);
             __builtin_amdgcn_s_setprio(0);
         }
     }
@@ -802,21 +806,21 @@ struct FusedIO {
     const int64_t *list_flags;   // gs_bins.counters: [1] != 0 when the list was not built
 };
 
-template <int PX>
+template <int PX, int B>
 __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
                                   const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out,
                                   int seg, int segs, int32_t *sched, int n_tiles, int item)
 {
     // segment seg of segs: list positions [lo, hi), boundaries at multiples of 64 entries
     const int n = t.end - t.start;
-    const int per = ((n + segs - 1) / segs + kBatch - 1) / kBatch * kBatch;
+    const int per = ((n + segs - 1) / segs + B - 1) / B * B;
     const int lo = min(t.end, t.start + seg * per);
     const int hi = seg == segs - 1 ? t.end : min(t.end, lo + per);
     PixState<PX> ps;
     init_state<PX>(t, ps);
     Snapshot<PX> sn;
-    const int walked = hi < t.end ? fwd_walk<PX, false>(rr, ids, t, prm, ps, hi, &sn)
-                                  : fwd_walk<PX, false>(rr, ids, t, prm, ps);
+    const int walked = hi < t.end ? fwd_walk<PX, false, B>(rr, ids, t, prm, ps, hi, &sn)
+                                  : fwd_walk<PX, false, B>(rr, ids, t, prm, ps);
     record_walk(sched, n_tiles, item, walked);
     float g0[PX], g1[PX], g2[PX];
     float l2 = 0.f;
@@ -862,9 +866,10 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
             gS[q] = gbg;
         }
     }
-    bwd_walk<PX>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, lo, hi);
+    bwd_walk<PX, B>(rr, ids, t, prm, ps, T, gS, g0, g1, g2, out, lo, hi);
 }
 
+template <int B>
 __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_per_eu(4))) void raster_fused_kernel(
     const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids, const int32_t *__restrict__ ranges,
     int32_t *__restrict__ sched, const gs_camera *__restrict__ cams, int n_cams, gs_params prm, FusedIO io,
@@ -888,15 +893,15 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
             const int seg = (item >> 3) & 3;
             if (prio) set_priority(3);
             if (parts == 4)
-                fused_item<1>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
+                fused_item<1, B>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
                               sched, n_tiles, item);
             else
-                fused_item<2>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
+                fused_item<2, B>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
                               sched, n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         } else {
             set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
-            fused_item<4>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
+            fused_item<4, B>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
                           n_tiles, item);
             __builtin_amdgcn_s_setprio(0);
         }
@@ -948,14 +953,17 @@ extern "C" int gs_rasterize_fwd(const gs_splats *s, const gs_bins *bins, const g
     // every tile is on the work list, empty ones included, so each pixel is written exactly once
     const dim3 grid(persistent_blocks(kBlockWaves)), block(kWave * kBlockWaves);
     const FwdOut o{n_pixels, image, T_final, last, visited};
-    if (visited)
-        hipLaunchKernelGGL(raster_fwd_kernel<true>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, kernel_params(prm), o, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
-    else
-        hipLaunchKernelGGL(raster_fwd_kernel<false>, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster,
-                           bins->ids, bins->ranges, bins->schedule, cams, (int)n_cams, kernel_params(prm), o, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
+    const gs_tuning &tu = current_tuning();
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, block, 0, (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids,
+                           bins->ranges, bins->schedule, cams, (int)n_cams, kernel_params(prm), o, tu.split_priority,
+                           tu.item_grab, tu.prio_len, bins->n_tiles);
+    };
+    if (visited) {
+        if (tu.batch == 32) launch(raster_fwd_kernel<true, 32>); else launch(raster_fwd_kernel<true, 64>);
+    } else {
+        if (tu.batch == 32) launch(raster_fwd_kernel<false, 32>); else launch(raster_fwd_kernel<false, 64>);
+    }
     return check_launch("gs_rasterize_fwd");
 }
 
@@ -983,10 +991,14 @@ extern "C" int gs_rasterize_bwd(const gs_splats *s, int64_t n_splats, const gs_b
     const BwdIn in{n_pixels, dL_dimage, T_final, last};
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac,
                      current_tuning().atomic_lanes};
-    hipLaunchKernelGGL(raster_bwd_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
-                       (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, kernel_params(prm), in, out, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
+    const gs_tuning &tu = current_tuning();
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
+                           (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule,
+                           cams, (int)n_cams, kernel_params(prm), in, out, tu.split_priority, tu.item_grab, tu.prio_len,
+                           bins->n_tiles);
+    };
+    if (tu.batch == 32) launch(raster_bwd_kernel<32>); else launch(raster_bwd_kernel<64>);
     return check_launch("gs_rasterize_bwd");
 }
 
@@ -1007,9 +1019,13 @@ extern "C" int gs_rasterize_fused_l2(const gs_splats *s, int64_t n_splats, const
     const FusedIO io{n_pixels, target, image, loss, (const int64_t *)bins->counters};
     const BwdOut out{n_splats, n_gaussians, dL_dmean2d, dL_dconic, dL_dcolors, dL_dopac,
                      current_tuning().atomic_lanes};
-    hipLaunchKernelGGL(raster_fused_kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
-                       (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule, cams,
-                       (int)n_cams, kernel_params(prm), io, out, current_tuning().split_priority,
-                           current_tuning().item_grab, current_tuning().prio_len, bins->n_tiles);
+    const gs_tuning &tu = current_tuning();
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(persistent_blocks(kBlockWaves)), dim3(kWave * kBlockWaves), 0,
+                           (hipStream_t)stream, (const RasterRec *)s->raster, bins->ids, bins->ranges, bins->schedule,
+                           cams, (int)n_cams, kernel_params(prm), io, out, tu.split_priority, tu.item_grab, tu.prio_len,
+                           bins->n_tiles);
+    };
+    if (tu.batch == 32) launch(raster_fused_kernel<32>); else launch(raster_fused_kernel<64>);
     return check_launch("gs_rasterize_fused_l2");
 }

@@ -157,7 +157,11 @@ def test_results_do_not_depend_on_launch_tuning(name):
                   {"split_len": 64, "split_parts": 2, "waves_per_cu": 16, "split_priority": 1, "generate_entries": 0,
                    "item_grab": 16, "prio_len": 64, "bwd_segs": 4, "atomic_lanes": 64},
                   {"split_len": 1, "split_parts": 4, "waves_per_cu": 64, "split_priority": 0, "generate_entries": 1,
-                   "item_grab": 2, "bwd_segs": 2, "atomic_lanes": 1}):
+                   "item_grab": 2, "bwd_segs": 2, "atomic_lanes": 1},
+                  {"split_len": 64, "split_parts": 4, "waves_per_cu": 16, "bwd_segs": 4, "atomic_lanes": 4,
+                   "batch": 32},
+                  {"split_len": 256, "split_parts": 2, "waves_per_cu": 32, "bwd_segs": 2, "atomic_lanes": 64,
+                   "batch": 32, "prio_len": 96}):
             autotune.apply(t)
             _, _, _, step = build(wl, "fused")
             step()
