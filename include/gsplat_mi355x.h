@@ -147,9 +147,14 @@ typedef struct gs_params {
 /*
  * Tile-intersection list (Sec. 2.2): one entry per (splat, tile of its box), sorted by
  * key = (global tile << 32) | float32 bits of depth, equal keys in splat order.
+ * The rasterizer reads ids and ranges only. With GS_BINS_NO_KEYS in flags the sort does not
+ * write the sorted 64-bit keys (ids, ranges and the work list are the same); the keys buffer
+ * is still required, as the sort's scratch.
  */
+#define GS_BINS_NO_KEYS 1
+
 typedef struct gs_bins {
-    uint64_t *keys;          /* [capacity] */
+    uint64_t *keys;          /* [capacity]: the sorted keys, unless flags has GS_BINS_NO_KEYS */
     int32_t *ids;            /* [capacity] splat slot of each entry */
     int32_t *ranges;         /* [n_tiles][2] start, end of each tile's run; empty tile = (0, 0) */
     int32_t *schedule;       /* [gs_schedule_size(n_tiles)] rasterizer work list, written by
@@ -158,7 +163,7 @@ typedef struct gs_bins {
                                 (1 = overflow, 2 = sort failure, 4 = camera too wide) */
     int64_t capacity;        /* K_cap, at most 2^31 - 1 */
     int32_t n_tiles;         /* sum over cameras of tiles_x * tiles_y */
-    int32_t reserved;
+    int32_t flags;           /* 0 or GS_BINS_NO_KEYS; other bits are rejected */
 } gs_bins;
 
 /*

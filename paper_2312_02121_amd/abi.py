@@ -57,6 +57,7 @@ class GsGaussians(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+GS_BINS_NO_KEYS = 1           # gs_bins.flags: the sort does not write the 64-bit keys
 GS_NORMALIZE_QUATS = 1
 GS_BOX_LAMBDA_MAX = 2
 
@@ -84,7 +85,7 @@ class GsTuning(ctypes.Structure):
 class GsBins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
                 ("schedule", ctypes.c_void_p), ("counters", ctypes.c_void_p), ("capacity", ctypes.c_int64),
-                ("n_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_tiles", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 def expected_layout() -> list[int]:

@@ -47,7 +47,7 @@ class RasterizeGaussians(torch.autograd.Function):
                                               scales.detach().contiguous(), colors.detach().contiguous(),
                                               opacities.detach().contiguous(), sizes, normalize_quats)
         key = (cams.n_splats, cams.n_tiles)
-        r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key))
+        r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key), write_keys=False)
         st = r.forward(g)
         _capacity_hint[key] = max(r.capacity, int(st.K * 1.1) + 1024)
         ctx.state = st
@@ -134,7 +134,7 @@ class RasterizeSplats(torch.autograd.Function):
                                               opacities.detach().contiguous(), sizes)
         g.box_lambda_max = bool(box_lambda_max)
         key = (cams.n_splats, cams.n_tiles, "2d")
-        r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key))
+        r = pipeline.Rasterizer(cams, params, capacity=_capacity_hint.get(key), write_keys=False)
         st = r.forward_2d(g, mean2d.detach().to(torch.float32).contiguous(),
                           conic.detach().to(torch.float32).contiguous(), depth.contiguous(), valid.contiguous())
         _capacity_hint[key] = max(r.capacity, int(st.K * 1.1) + 1024)

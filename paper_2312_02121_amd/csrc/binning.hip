@@ -1379,6 +1379,8 @@ static int check_bin_args(const gs_splats *s, int64_t n_splats, const gs_camera 
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: n_splats must be below 2^31");
     if (n_cams > bins->n_tiles)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: more cameras than tiles");
+    if (bins->flags & ~GS_BINS_NO_KEYS)
+        return set_error(GS_ERR_INVALID, "gs_bin_and_sort: unknown bits in flags");
     if (!bins->keys || !bins->ids || !bins->ranges || !bins->schedule || !bins->counters || !s->rect || !s->depth ||
         !s->tiles_touched || n_splats > s->capacity)
         return set_error(GS_ERR_INVALID, "gs_bin_and_sort: null buffer or n_splats > capacity");
@@ -1476,7 +1478,10 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     const bool first_to_W = passes >= 2 && ((passes - 2) & 1) == 0;
     uint32_t *k0out = passes == 1 ? (uint32_t *)nullptr : (first_to_W ? kW : kX);
     int32_t *v0out = passes == 1 ? bins->ids : (first_to_W ? vW : vX);
-    uint64_t *k64 = passes == 1 ? bins->keys : (uint64_t *)nullptr;
+    // the sorted 64-bit keys, unless the caller does without them (the last pass then writes
+    // ids only and gathers no depth)
+    uint64_t *keys_final = (bins->flags & GS_BINS_NO_KEYS) ? (uint64_t *)nullptr : bins->keys;
+    uint64_t *k64 = passes == 1 ? keys_final : (uint64_t *)nullptr;
     if (current_tuning().generate_entries) {
         int32_t *chunk_rank = (int32_t *)(ws + L.chunk_rank);
         hipLaunchKernelGGL(chunk_rank_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
@@ -1510,7 +1515,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
                            pass * kRadixBits, ghist_tile + pass * kRadix,
                            stat_tile + (int64_t)pass * L.tile_nb * kRadix, last ? (uint32_t *)nullptr : kout,
                            last ? bins->ids : vout,
-                           last ? bins->keys : (uint64_t *)nullptr, s->depth, (const int32_t *)nullptr,
+                           last ? keys_final : (uint64_t *)nullptr, s->depth, (const int32_t *)nullptr,
                            (int32_t *)nullptr, n_splats, 1, err);
         kin = kout;
         vin = vout;

@@ -200,9 +200,9 @@ class Bins:
                     torch.zeros(2, dtype=torch.int64, device=device),
                     torch.empty(max(ws, 1), dtype=torch.uint8, device=device), capacity, n_tiles)
 
-    def struct(self) -> abi.GsBins:
+    def struct(self, flags: int = 0) -> abi.GsBins:
         return abi.GsBins(_ptr(self.keys), _ptr(self.ids), _ptr(self.ranges), _ptr(self.schedule),
-                          _ptr(self.counters), self.capacity, self.n_tiles, 0)
+                          _ptr(self.counters), self.capacity, self.n_tiles, flags)
 
 
 @dataclass
@@ -224,8 +224,10 @@ class Rasterizer:
     """Reusable buffers for one (GaussianSet layout, CameraSet) pair."""
 
     def __init__(self, cams: CameraSet, params: abi.GsParams | None = None, capacity: int | None = None,
-                 keep_visited: bool = False, keep_records: bool = False):
+                 keep_visited: bool = False, keep_records: bool = False, write_keys: bool = True):
         self.cams = cams
+        # the sorted 64-bit keys are written only on request: the rasterizer reads ids and ranges
+        self.write_keys = write_keys
         self.params = params or make_params()
         self.device = cams.device
         P = cams.n_splats
@@ -248,7 +250,8 @@ class Rasterizer:
         stream = current_stream() if stream is None else stream
         P = self.cams.n_splats
         b = self.bins
-        abi.gs_bin_and_sort(self.splats.struct(P), P, self.cams.ptr, self.cams.n_cams, b.struct(),
+        abi.gs_bin_and_sort(self.splats.struct(P), P, self.cams.ptr, self.cams.n_cams,
+                            b.struct(0 if self.write_keys else abi.GS_BINS_NO_KEYS),
                             _ptr(b.workspace), b.workspace.numel(), stream)
 
     def rasterize_fwd(self, stream: int | None = None):
@@ -365,10 +368,12 @@ class TrainStep:
 
     def __init__(self, g: GaussianSet, cams: CameraSet, targets: torch.Tensor, params: abi.GsParams | None = None,
                  capacity: int | None = None, capacity_margin: float = 1.25, mode: str = "separate",
-                 keep_image: bool = True, scene_grads: "TrainStep | None" = None, keep_records: bool = False):
+                 keep_image: bool = True, scene_grads: "TrainStep | None" = None, keep_records: bool = False,
+                 keep_keys: bool = False):
         self.g, self.cams, self.mode = g, cams, mode
         self.STAGES = self.STAGE_SETS[mode]
-        self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True, keep_records=keep_records)
+        self.r = Rasterizer(cams, params, capacity=capacity, keep_visited=True, keep_records=keep_records,
+                            write_keys=keep_keys)
         self.targets = targets.contiguous().view(3, -1).to(torch.float32)
         assert self.targets.shape[1] == cams.n_pixels
         st = self.r.forward(g)                      # sizes the list capacity

@@ -131,3 +131,20 @@ def check_projection(wl, r, views=None, prm=None):
         assert np.array_equal(s["color"][:, sl][:, vis], sc["colors"][:, vis])
         assert np.array_equal(s["src"][sl][vis], np.nonzero(vis)[0] + (sum(wl.scenes[j]["opacities"].shape[0]
                                                                           for j in range(cam.scene))))
+
+
+HEADER, BUCKETS, N_BUCKETS = 64, 8, 16   # work-list layout: header words, bucket counts
+
+
+def same_work_list(x, y):
+    """Work lists are equal up to the order of items inside a length bucket (which blocks
+    fill concurrently): the header and every bucket's set of items agree."""
+    assert np.array_equal(x[:HEADER], y[:HEADER])
+    n = int(x[0])
+    assert np.array_equal(x[HEADER + n:], y[HEADER + n:])
+    at = HEADER
+    for k in range(N_BUCKETS):
+        c = int(x[BUCKETS + k])
+        assert np.array_equal(np.sort(x[at:at + c]), np.sort(y[at:at + c])), k
+        at += c
+    assert at == HEADER + n

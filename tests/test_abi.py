@@ -69,6 +69,11 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     rc = lib.gs_bin_and_sort(abi._ref(sp), 10, 64, 1, abi._ref(bins), 4096 + 8, ws, None)
     assert rc == abi.GS_ERR_INVALID
     assert b"aligned" in lib.gs_last_error_message()
+    # flag bits other than GS_BINS_NO_KEYS
+    bad = abi.GsBins(keys=64, ids=64, ranges=64, schedule=64, counters=64, capacity=10, n_tiles=1, flags=2)
+    rc = lib.gs_bin_and_sort(abi._ref(sp), 10, 64, 1, abi._ref(bad), 4096, ws, None)
+    assert rc == abi.GS_ERR_INVALID
+    assert b"flags" in lib.gs_last_error_message()
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -54,6 +54,14 @@ def graph_step(wl):
         graph()
     torch.cuda.synchronize()
     assert not step.overflowed()
+    # the step writes no sorted 64-bit keys; one more sort that writes them must give the same
+    # ids and ranges, and the keys are compared with the oracle's
+    ids, ranges = step.r.bins.ids[: step.K].clone(), step.r.bins.ranges.clone()
+    step.r.write_keys = True
+    step.r.bin_and_sort()
+    step.r.write_keys = False
+    torch.cuda.synchronize()
+    assert torch.equal(ids, step.r.bins.ids[: step.K]) and torch.equal(ranges, step.r.bins.ranges)
     autotune.apply(autotune.default_tuning())
     return step, graph
 

@@ -14,7 +14,7 @@ from paper_2312_02121_amd import synth
 
 from gpu_helpers import (IMAGE_ATOL, GRAD_REL, bins_arrays, camera_images, elementwise_ok, flag_budget,
                          gpu_forward, oracle_camera, oracle_params, rel_err, splat_arrays, tile_offsets,
-                         worst_element, check_projection)
+                         worst_element, check_projection, same_work_list)
 
 pytestmark = pytest.mark.gpu
 
@@ -302,6 +302,41 @@ def test_projection_record_is_optional():
     torch.cuda.synchronize()
     assert st2.K == st.K
     assert torch.equal(r.bins.keys[: st.K], r2.bins.keys[: st2.K]) and torch.equal(st.image, st2.image)
+
+
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k"])
+@pytest.mark.parametrize("generate", [0, 1])
+def test_sorted_keys_are_optional(name, generate):
+    """With GS_BINS_NO_KEYS the sort writes no 64-bit keys; the ids, ranges, count, work list
+    and image are those of a call that writes them (one tile pass for the tiny scene, two at
+    512x512; entries emitted or generated inside the first pass)."""
+    _print_case("no_keys", wl=name, generate=generate)
+    from paper_2312_02121_amd import autotune, pipeline
+    wl = wl_cache()[name]
+    g = pipeline.GaussianSet(wl.scenes)
+    autotune.apply({**autotune.default_tuning(), "generate_entries": generate})
+    try:
+        out = []
+        for write_keys in (True, False):
+            r = pipeline.Rasterizer(pipeline.CameraSet(wl.cameras, g.sizes), write_keys=write_keys)
+            st = r.forward(g)
+            torch.cuda.synchronize()
+            out.append((r, st))
+    finally:
+        autotune.apply(autotune.default_tuning())
+    (r1, s1), (r2, s2) = out
+    assert s1.K == s2.K > 0
+    K = s1.K
+    for name_ in ("ids", "ranges", "counters"):
+        assert torch.equal(getattr(r1.bins, name_)[:K] if name_ == "ids" else getattr(r1.bins, name_),
+                           getattr(r2.bins, name_)[:K] if name_ == "ids" else getattr(r2.bins, name_)), name_
+    same_work_list(r1.bins.schedule.cpu().numpy(), r2.bins.schedule.cpu().numpy())
+    assert torch.equal(s1.image, s2.image)
+    # the keys the first call wrote are the oracle's
+    toffs = tile_offsets(wl)
+    keys = [oracle.bin_and_sort(oracle.project(wl.scenes[c.scene], c, oracle_params()), c,
+                                tile_offset=toffs[k])["keys"] for k, c in enumerate(wl.cameras)]
+    assert np.array_equal(r1.bins.keys[:K].cpu().numpy().view(np.uint64), np.concatenate(keys))
 
 
 def test_near_plane_behind_the_camera():

@@ -8,6 +8,8 @@ import pytest
 
 from paper_2312_02121_amd import synth
 
+from gpu_helpers import same_work_list
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -43,23 +45,6 @@ def _both(wl):
         assert torch.equal(a[name], b[name]), name
     same_work_list(a["schedule"].cpu().numpy(), b["schedule"].cpu().numpy())
     return r, P, cams
-
-
-HEADER, BUCKETS, N_BUCKETS = 64, 8, 16   # work-list layout: header words, bucket counts
-
-
-def same_work_list(x, y):
-    """Work lists are equal up to the order of items inside a length bucket (which blocks
-    fill concurrently): the header and every bucket's set of items agree."""
-    assert np.array_equal(x[:HEADER], y[:HEADER])
-    n = int(x[0])
-    assert np.array_equal(x[HEADER + n:], y[HEADER + n:])
-    at = HEADER
-    for k in range(N_BUCKETS):
-        c = int(x[BUCKETS + k])
-        assert np.array_equal(np.sort(x[at:at + c]), np.sort(y[at:at + c])), k
-        at += c
-    assert at == HEADER + n
 
 
 def test_static_workspace_matches_caller_workspace_twice():
