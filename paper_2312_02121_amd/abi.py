@@ -76,7 +76,8 @@ class GsTuning(ctypes.Structure):
     _fields_ = [("split_len", ctypes.c_int32), ("split_parts", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("split_priority", ctypes.c_int32), ("generate_entries", ctypes.c_int32),
                 ("item_grab", ctypes.c_int32), ("prio_len", ctypes.c_int32),
-                ("bwd_segs", ctypes.c_int32), ("atomic_lanes", ctypes.c_int32), ("batch", ctypes.c_int32)]
+                ("bwd_segs", ctypes.c_int32), ("atomic_lanes", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("big_tiles", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -96,7 +97,8 @@ def expected_layout() -> list[int]:
             ctypes.sizeof(GsGaussians), GsGaussians.n.offset,
             ctypes.sizeof(GsSplats), GsSplats.capacity.offset,
             ctypes.sizeof(GsParams), ctypes.sizeof(GsBins), GsBins.capacity.offset, GsBins.n_tiles.offset,
-            ctypes.sizeof(GsTuning), GsTuning.bwd_segs.offset, GsTuning.atomic_lanes.offset, GsTuning.batch.offset]
+            ctypes.sizeof(GsTuning), GsTuning.bwd_segs.offset, GsTuning.atomic_lanes.offset, GsTuning.batch.offset,
+            GsTuning.big_tiles.offset]
 
 
 # --------------------------------------------------------------------------- loading

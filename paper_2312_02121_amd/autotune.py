@@ -42,6 +42,7 @@ KNOBS = {
     "bwd_segs": (1, 2, 4),
     "atomic_lanes": (2, 4, 8),
     "batch": (32, 64),
+    "big_tiles": (0, 256, 1024),
 }
 # item_grab is left at 1: taking several items per atomic put consecutive long items (the
 # head of the longest-first list) on one wave and made the 1M-Gaussian and the 32-view
@@ -59,7 +60,7 @@ SEEDS = (
 
 def default_tuning() -> dict:
     return {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "split_priority": 1, "generate_entries": 0,
-            "item_grab": 1, "prio_len": 0, "bwd_segs": 1, "atomic_lanes": 4, "batch": 64}
+            "item_grab": 1, "prio_len": 0, "bwd_segs": 1, "atomic_lanes": 4, "batch": 64, "big_tiles": 0}
 
 
 def apply(t: dict):

@@ -86,6 +86,10 @@ constexpr int kMaxTilePassesDev = 4;   // tile ids are int32: at most four 8-bit
 constexpr int kDepthPasses = 4;        // depth keys are 32-bit float bits
 static_assert(kSortBlock == kRadix, "one thread per digit in the single-pass sort");
 
+// A splat whose box has more than big_tiles tiles (launch tuning; 0: none) is listed by the
+// per-tile merge instead of the tile sort.
+__device__ inline bool is_big(int tiles, int big_tiles) { return big_tiles > 0 && tiles > big_tiles; }
+
 __device__ inline int64_t sort_count(const int64_t *counter, int64_t cap)
 {
     const int64_t k = *counter;
@@ -758,8 +762,9 @@ __global__ __launch_bounds__(kSortBlock) void depth_hist_kernel(const uint32_t *
 // splats (rank_tiles, written in rank order by the last depth pass). Chunks of kSortChunk
 // ranks, 16 consecutive ranks per thread: per-chunk sums, their scan (chunk_scan_kernel,
 // which stores K and the overflow flag), then each chunk writes its offsets.
+// Tile counts of ranks i0 .. i0 + 15 (0 past V, and 0 for splats listed by the merge).
 __device__ inline void load_rank_tiles(const int32_t *__restrict__ rank_tiles, int64_t i0, int64_t V,
-                                       int32_t (&t)[kSortItems])
+                                       int32_t (&t)[kSortItems], int big_tiles)
 {
     if (i0 + kSortItems <= V) {
         const int4 *t4 = reinterpret_cast<const int4 *>(rank_tiles + i0);
@@ -772,16 +777,19 @@ __device__ inline void load_rank_tiles(const int32_t *__restrict__ rank_tiles, i
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) t[k] = i0 + k < V ? rank_tiles[i0 + k] : 0;
     }
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k)
+        if (is_big(t[k], big_tiles)) t[k] = 0;
 }
 
 __global__ __launch_bounds__(kSortBlock) void rank_sum_kernel(const int32_t *__restrict__ rank_tiles,
                                                               const int64_t *__restrict__ vcount,
-                                                              int64_t *__restrict__ chunk_sum)
+                                                              int64_t *__restrict__ chunk_sum, int big_tiles)
 {
     const int64_t V = *vcount;
     for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
         int32_t t[kSortItems];
-        load_rank_tiles(rank_tiles, c * kSortChunk + (int64_t)threadIdx.x * kSortItems, V, t);
+        load_rank_tiles(rank_tiles, c * kSortChunk + (int64_t)threadIdx.x * kSortItems, V, t, big_tiles);
         int64_t mine = 0;
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) mine += t[k];
@@ -794,13 +802,13 @@ __global__ __launch_bounds__(kSortBlock) void rank_sum_kernel(const int32_t *__r
 __global__ __launch_bounds__(kSortBlock) void rank_offsets_kernel(const int32_t *__restrict__ rank_tiles,
                                                                   const int64_t *__restrict__ vcount,
                                                                   const int64_t *__restrict__ chunk_off,
-                                                                  int64_t *__restrict__ offsets)
+                                                                  int64_t *__restrict__ offsets, int big_tiles)
 {
     const int64_t V = *vcount;
     for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
         const int64_t i0 = c * kSortChunk + (int64_t)threadIdx.x * kSortItems;
         int32_t t[kSortItems];
-        load_rank_tiles(rank_tiles, i0, V, t);
+        load_rank_tiles(rank_tiles, i0, V, t, big_tiles);
         int64_t mine = 0;
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) mine += t[k];
@@ -848,7 +856,7 @@ __global__ __launch_bounds__(kCornerBlock) void tile_corner_kernel(const int32_t
                                                                    const int64_t *__restrict__ vcount,
                                                                    const int4 *__restrict__ rect,
                                                                    const gs_camera *__restrict__ cams, int n_cams,
-                                                                   int64_t n_splats, int64_t span,
+                                                                   int64_t n_splats, int64_t span, int big_tiles,
                                                                    int32_t *__restrict__ gdiff)
 {
     __shared__ int diff[kCountLds];
@@ -878,8 +886,12 @@ __global__ __launch_bounds__(kCornerBlock) void tile_corner_kernel(const int32_t
                     sl[u] = i < s1 ? vis_slots[i] : -1;
                 }
 #pragma unroll
-                for (int u = 0; u < kU; ++u)
+                for (int u = 0; u < kU; ++u) {
                     bx[u] = sl[u] >= p_lo && sl[u] < p_hi ? rect[sl[u]] : make_int4(0, 0, -1, -1);
+                    // splats listed by the merge are not counted here (their tiles are added later)
+                    if (bx[u].z >= 0 && is_big((bx[u].z - bx[u].x + 1) * (bx[u].w - bx[u].y + 1), big_tiles))
+                        bx[u] = make_int4(0, 0, -1, -1);
+                }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     if (bx[u].z < 0) continue;   // not this camera's slot
@@ -998,10 +1010,19 @@ __global__ __launch_bounds__(kCountBlock) void tile_count_kernel(const gs_camera
 // within the capacity, no error). A range is written only when it ends within K, so the
 // rasterizer never reads past the list; a range past K, or a total different from K,
 // marks the lengths inconsistent with the list (error word). Empty tiles get (0, 0).
+// With big_len (the merge of large splats) the scan also gives big_before[t], the entries
+// of big splats in tiles before t: each tile's value is packed as length << 31 | big count
+// (both sums stay below 2^31 when the list is built, so the fields never carry into each
+// other and the packed prefix fits the 62-bit status value).
+constexpr int kPackShift = 31;
+constexpr int64_t kPackLow = (1ll << kPackShift) - 1;
+
 __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__restrict__ cnt, int32_t n_tiles,
                                                             const int64_t *__restrict__ K, int64_t cap,
                                                             uint64_t *__restrict__ status,
                                                             int32_t *__restrict__ ranges,
+                                                            const int32_t *__restrict__ big_len,
+                                                            int32_t *__restrict__ big_before,
                                                             int64_t *__restrict__ err_flag)
 {
     __shared__ int64_t prefix;
@@ -1012,12 +1033,15 @@ __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__res
     if (chunk_stop(err_flag, &stop)) break;
     const int64_t base = b * kSortChunk;
     const int64_t i0 = base + (int64_t)threadIdx.x * kSortItems;
-    int32_t n[kSortItems];
+    int32_t n[kSortItems], nb[kSortItems];
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) n[k] = i0 + k < n_tiles ? cnt[i0 + k] : 0;
+    for (int k = 0; k < kSortItems; ++k) {
+        n[k] = i0 + k < n_tiles ? cnt[i0 + k] : 0;
+        nb[k] = big_len && i0 + k < n_tiles ? big_len[i0 + k] : 0;
+    }
     int64_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) mine += n[k];
+    for (int k = 0; k < kSortItems; ++k) mine += ((int64_t)n[k] << kPackShift) + nb[k];
     int64_t total;
     const int64_t ex_thread = block_exclusive_scan<int64_t>(mine, &total);
     if (threadIdx.x == 0)
@@ -1029,7 +1053,7 @@ __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__res
             __hip_atomic_store(status + b, kStatInc | (uint64_t)(ex + total), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         prefix = ex;
-        if (ex >= 0 && base + kSortChunk >= n_tiles && ex + total != k_all)
+        if (ex >= 0 && base + kSortChunk >= n_tiles && ((ex + total) >> kPackShift) != k_all)
             __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -1038,16 +1062,17 @@ __global__ __launch_bounds__(kSortBlock) void ranges_kernel(const int32_t *__res
     bool past = false;
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t e = run + n[k];
+        const int64_t s0 = run >> kPackShift, e = s0 + n[k];
         if (i0 + k < n_tiles) {
             if (n[k] > 0 && e <= k_all) {
-                ranges[2 * (i0 + k)] = (int32_t)run;
+                ranges[2 * (i0 + k)] = (int32_t)s0;
                 ranges[2 * (i0 + k) + 1] = (int32_t)e;
             } else if (n[k] > 0) {
                 past = true;
             }
+            if (big_before) big_before[i0 + k] = (int32_t)(run & kPackLow);
         }
-        run = e;
+        run += ((int64_t)n[k] << kPackShift) + nb[k];
     }
     if (past) __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1071,6 +1096,8 @@ __device__ inline void emit_tiles(int64_t k0, int count_begin, int count_step, i
 
 // Emit in depth-rank order, one thread per rank: (global tile id, slot) for every tile of
 // the box, row-major, at the rank's offset. Nothing is written when K exceeds the capacity.
+// With big_tiles > 0, splats with more tiles than that are left out (the merge lists them)
+// and the value of an entry is the splat's depth rank instead of its slot.
 __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ rank_ids,
                                                    const int64_t *__restrict__ offsets,
                                                    const int32_t *__restrict__ rank_tiles, const int4 *__restrict__ rect,
@@ -1078,18 +1105,24 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
                                                    const int64_t *__restrict__ vcount,
                                                    const int64_t *__restrict__ K, int64_t cap,
                                                    uint32_t *__restrict__ tkey, int32_t *__restrict__ tval,
-                                                   const int64_t *__restrict__ err_flag)
+                                                   int big_tiles, const int64_t *__restrict__ err_flag)
 {
     if (*K > cap || *err_flag) return;   // uniform
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t V = *vcount;
     const int lane = threadIdx.x & (kWave - 1);
-    int32_t slot = 0;
+    // a grid of a few blocks per CU walks the V ranks (the grid is sized for the slots, of
+    // which V may be a small part)
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < V; r0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = r0 + threadIdx.x;
+    int32_t slot = 0, val = 0;
     int cnt = 0;
     int64_t k0 = 0;
-    if (r < *vcount) {
+    if (r < V) {
         slot = rank_ids[r];
         cnt = rank_tiles[r];
         k0 = offsets[r];
+        if (is_big(cnt, big_tiles)) cnt = 0;
+        val = big_tiles > 0 ? (int32_t)r : slot;
     }
     int toff = 0, tx_n = 1;
     int4 b = make_int4(0, 0, 0, 0);
@@ -1099,7 +1132,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
         tx_n = cams[c].tiles_x;
         b = rect[slot];
     }
-    if (cnt > 0 && cnt <= kEmitLaneMax) emit_tiles(k0, 0, 1, cnt, b, toff, tx_n, slot, tkey, tval);
+    if (cnt > 0 && cnt <= kEmitLaneMax) emit_tiles(k0, 0, 1, cnt, b, toff, tx_n, val, tkey, tval);
     // large boxes: the whole wave writes them, one splat at a time
     uint64_t big = __ballot(cnt > kEmitLaneMax);
     while (big) {
@@ -1107,11 +1140,444 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
         big &= big - 1;
         const int bcnt = __shfl(cnt, src, kWave);
         const int64_t bk0 = __shfl(k0, src, kWave);
-        const int32_t bslot = __shfl(slot, src, kWave);
+        const int32_t bslot = __shfl(val, src, kWave);
         const int btoff = __shfl(toff, src, kWave), btx = __shfl(tx_n, src, kWave);
         const int4 bb = make_int4(__shfl(b.x, src, kWave), __shfl(b.y, src, kWave), __shfl(b.z, src, kWave),
                                   __shfl(b.w, src, kWave));
         emit_tiles(bk0, lane, kWave, bcnt, bb, btoff, btx, bslot, tkey, tval);
+    }
+    }
+}
+
+// ------------------------------------------------------ the merge of large splats
+//
+// A splat that covers many tiles (typically one close to a camera) adds an entry to each of
+// them, and such entries can be most of the list. With big_tiles > 0 the splats with more
+// tiles than that are not emitted. Within a camera, the big splats listed in a tile are,
+// in depth-rank order, the camera's big splats whose box contains the tile, so each tile's
+// list is the merge by depth rank of two sorted runs: its run of the tile-sorted small
+// entries (whose values are ranks) and that filtered run of big splats. Ranks are distinct,
+// so the merge gives exactly the order of the full sort. Steps:
+//   big_count   per chunk of ranks: big splats per camera, and the sum of their tiles;
+//   big_scan    camera-major offsets of the big splats; K = small + big entries, overflow;
+//   big_scatter the big splats per camera in rank order (rank, camera-local box);
+//   big_len     per tile, the big splats whose box contains it (added to the tile lengths;
+//               the ranges scan also gives big_before, the big entries of earlier tiles);
+//   merge       per tile, the merge of its small run with its filtered big splats, written
+//               as ids (and keys).
+constexpr int kBigMaxCams = 64;   // cameras per call for which the merge is used
+constexpr int kBigMinTiles = 4;   // smallest big_tiles: the big splat arrays hold K_cap / 5
+// words of the call's big-splat state (after the per-camera starts)
+constexpr int kBigKSmall = 0;     // entries of small splats (written by the offset scan)
+constexpr int kBigKBig = 1;       // entries of big splats (summed by big_count)
+constexpr int kBigEffSmall = 2;   // entries the tile sort takes: K_small, or 0 when nothing is built
+constexpr int kBigOk = 3;         // 1 when the list is built
+constexpr int kBigCamStart = 8;   // [kBigMaxCams + 1] start of each camera's big splats
+constexpr int kBigCamTotal = kBigCamStart + kBigMaxCams + 1;   // [kBigMaxCams] big splats per camera
+constexpr int kBigWords = kBigCamTotal + kBigMaxCams;
+
+__device__ inline bool box_holds(const int4 &b, int tx, int ty)
+{
+    return b.x <= tx && tx <= b.z && b.y <= ty && ty <= b.w;
+}
+
+// Per chunk c of kSortChunk ranks: the count of big splats of each camera (mat[cam * stride
+// + c]; cameras' totals summed into words[kBigCamTotal + cam]) and the sum of their tiles
+// (summed into words[kBigKBig]).
+__global__ __launch_bounds__(kSortBlock) void big_count_kernel(const int32_t *__restrict__ rank_ids,
+                                                               const int32_t *__restrict__ rank_tiles,
+                                                               const int64_t *__restrict__ vcount,
+                                                               const gs_camera *__restrict__ cams, int n_cams,
+                                                               int big_tiles, int32_t *__restrict__ mat,
+                                                               int64_t stride, int64_t *__restrict__ words,
+                                                               const int64_t *__restrict__ err_flag)
+{
+    __shared__ int cnt[kBigMaxCams];
+    if (*err_flag) return;   // uniform
+    const int64_t V = *vcount;
+    for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
+        __syncthreads();
+        if (threadIdx.x < kBigMaxCams) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t i0 = c * kSortChunk + (int64_t)threadIdx.x * kSortItems;
+        int32_t t[kSortItems];
+        load_rank_tiles(rank_tiles, i0, V, t, 0);
+        int64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            if (i0 + k < V && is_big(t[k], big_tiles)) {
+                atomicAdd(&cnt[camera_of_splat(cams, n_cams, rank_ids[i0 + k])], 1);
+                mine += t[k];
+            }
+        }
+        int64_t tot;
+        block_exclusive_scan<int64_t>(mine, &tot);
+        if (threadIdx.x < n_cams) {
+            const int v = cnt[threadIdx.x];
+            mat[threadIdx.x * stride + c] = v;
+            if (v) atomicAdd((unsigned long long *)(words + kBigCamTotal + threadIdx.x), (unsigned long long)v);
+        }
+        if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)(words + kBigKBig), (unsigned long long)tot);
+    }
+}
+
+// One block per camera: its row of mat becomes the exclusive offsets of its big splats by
+// chunk, starting at the totals of the cameras before it. Block 0 also stores every camera's
+// start, sets K = K_small + K_big in counters[0] and the overflow flag in counters[1], and
+// decides whether the list is built (kBigOk, and the tile sort's count).
+__global__ __launch_bounds__(kScanBlock) void big_scan_kernel(int32_t *__restrict__ mat, int64_t stride,
+                                                              const int64_t *__restrict__ vcount, int n_cams,
+                                                              int64_t *__restrict__ words,
+                                                              int64_t *__restrict__ counters, int64_t cap,
+                                                              int64_t big_cap, int64_t *__restrict__ err_flag)
+{
+    const int cam = blockIdx.x;
+    const int64_t V = *vcount;
+    const int64_t n_chunks = (V + kSortChunk - 1) / kSortChunk;
+    int64_t base = 0;
+    for (int c = 0; c < cam; ++c) base += words[kBigCamTotal + c];
+    int32_t *row = mat + cam * stride;
+    for (int64_t b = 0; b < n_chunks; b += (int64_t)kScanBlock * kSortItems) {
+        const int64_t i0 = b + (int64_t)threadIdx.x * kSortItems;
+        int32_t v[kSortItems];
+        int64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            v[k] = i0 + k < n_chunks ? row[i0 + k] : 0;
+            mine += v[k];
+        }
+        int64_t tot;
+        int64_t run = base + block_exclusive_scan<int64_t>(mine, &tot);
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            if (i0 + k < n_chunks) row[i0 + k] = (int32_t)run;
+            run += v[k];
+        }
+        base += tot;
+    }
+    if (cam != 0 || threadIdx.x != 0) return;
+    int64_t n_big = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        words[kBigCamStart + c] = n_big;
+        n_big += words[kBigCamTotal + c];
+    }
+    words[kBigCamStart + n_cams] = n_big;
+    const int64_t k_small = words[kBigKSmall], total = k_small + words[kBigKBig];
+    const bool over = total > cap;
+    counters[0] = total;
+    counters[1] = over ? 1 : 0;
+    bool ok = !over && *err_flag == 0;
+    if (ok && n_big > big_cap) {   // unreachable: each big splat adds more than kBigMinTiles entries
+        __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+    }
+    words[kBigOk] = ok ? 1 : 0;
+    words[kBigEffSmall] = ok ? k_small : 0;
+}
+
+// Per chunk of ranks: the chunk's big splats in rank order (a block scan into LDS), then
+// one wave gives each its place in its camera's run (lanes of one camera in lane order,
+// each camera's cursor advanced by its group's leader): rank and camera-local box.
+__global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *__restrict__ rank_ids,
+                                                                 const int32_t *__restrict__ rank_tiles,
+                                                                 const int64_t *__restrict__ vcount,
+                                                                 const gs_camera *__restrict__ cams, int n_cams,
+                                                                 int big_tiles, const int4 *__restrict__ rect,
+                                                                 const int32_t *__restrict__ mat, int64_t stride,
+                                                                 const int64_t *__restrict__ words,
+                                                                 int32_t *__restrict__ big_rank,
+                                                                 int32_t *__restrict__ big_slot,
+                                                                 int4 *__restrict__ big_box,
+                                                                 const int64_t *__restrict__ err_flag)
+{
+    __shared__ int32_t lrank[kSortChunk];
+    __shared__ int cursor[kBigMaxCams];
+    if (!words[kBigOk] || *err_flag) return;   // uniform
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t V = *vcount, n_big = words[kBigCamStart + n_cams];
+    for (int64_t c = blockIdx.x; c * kSortChunk < V; c += gridDim.x) {
+        __syncthreads();   // the previous chunk's LDS reads have ended
+        const int64_t i0 = c * kSortChunk + (int64_t)threadIdx.x * kSortItems;
+        int32_t t[kSortItems];
+        load_rank_tiles(rank_tiles, i0, V, t, 0);
+        int mine = 0;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) mine += (i0 + k < V && is_big(t[k], big_tiles)) ? 1 : 0;
+        int nb;
+        int at = block_exclusive_scan<int>(mine, &nb);
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k)
+            if (i0 + k < V && is_big(t[k], big_tiles)) lrank[at++] = (int32_t)(i0 + k);
+        if (threadIdx.x < n_cams) cursor[threadIdx.x] = mat[threadIdx.x * stride + c];
+        __syncthreads();
+        if (wave != 0 || nb == 0) continue;   // wave-uniform; the next turn starts with a barrier
+        for (int b = 0; b < nb; b += kWave) {
+            const int i = b + lane;
+            const bool ok = i < nb;
+            const int32_t r = ok ? lrank[i] : 0;
+            const int32_t slot = ok ? rank_ids[r] : 0;
+            const int cam = ok ? camera_of_splat(cams, n_cams, slot) : 0;
+            const uint64_t peers = match_digit((unsigned)cam, __ballot(ok));
+            const int64_t pos = (int64_t)cursor[cam] + __popcll(peers & lanemask_lt());
+            __builtin_amdgcn_wave_barrier();
+            if (ok && pos >= 0 && pos < n_big) {   // always true when the counts agree
+                big_rank[pos] = r;
+                big_slot[pos] = slot;
+                big_box[pos] = rect[slot];
+            }
+            if (ok && (peers & lanemask_lt()) == 0) cursor[cam] = (int)(pos + __popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// Blocks of big_len take kBigGroup consecutive tiles; per camera among them, its big splats'
+// boxes pass through LDS kBigStage at a time and each wave tests its tiles (tile t of a
+// camera's part of the group to wave (t - first) mod 4) against them.
+constexpr int kBigGroup = 64;
+constexpr int kBigStage = 1024;
+constexpr int kBigUnroll = 4;   // boxes per lane in flight
+
+// Copies boxes k0 .. k0 + m - 1 into LDS, four per thread, loads issued first.
+__device__ inline void stage_boxes(int4 *sbox, const int4 *__restrict__ box, int64_t k0, int m)
+{
+    static_assert(kBigStage == 4 * 256, "four boxes per thread");
+    int4 b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int x = (int)threadIdx.x + u * 256;
+        b[u] = x < m ? box[k0 + x] : make_int4(1, 1, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int x = (int)threadIdx.x + u * 256;
+        if (x < m) sbox[x] = b[u];
+    }
+}
+
+// The number of its camera's big splats whose box contains each tile: kept in big_len and
+// added to the tile's list length.
+__global__ __launch_bounds__(256) void big_len_kernel(const gs_camera *__restrict__ cams, int n_cams, int n_tiles,
+                                                      const int64_t *__restrict__ words,
+                                                      const int4 *__restrict__ big_box, int32_t *__restrict__ cnt,
+                                                      int32_t *__restrict__ big_len,
+                                                      const int64_t *__restrict__ err_flag)
+{
+    __shared__ int4 sbox[kBigStage];
+    __shared__ int scount[kBigGroup];
+    if (!words[kBigOk] || *err_flag) return;   // uniform
+    const int g0 = blockIdx.x * kBigGroup, g1 = min(n_tiles, g0 + kBigGroup);
+    if (g0 >= n_tiles) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (threadIdx.x < kBigGroup) scount[threadIdx.x] = 0;
+    const int c_first = camera_of_tile(cams, n_cams, g0), c_last = camera_of_tile(cams, n_cams, g1 - 1);
+    for (int c = c_first; c <= c_last; ++c) {
+        const int toff = cams[c].tile_offset, tw = max(cams[c].tiles_x, 1);
+        const int t0 = max(g0, toff), t1 = min(g1, toff + cams[c].tiles_x * cams[c].tiles_y);
+        const int64_t b0 = words[kBigCamStart + c], b1 = words[kBigCamStart + c + 1];
+        if (t0 >= t1) continue;   // uniform
+        for (int64_t k0 = b0; k0 < b1; k0 += kBigStage) {
+            const int m = (int)min((int64_t)kBigStage, b1 - k0);
+            __syncthreads();   // the previous stage's reads have ended
+            stage_boxes(sbox, big_box, k0, m);
+            __syncthreads();
+            for (int t = t0 + wave; t < t1; t += 256 / kWave) {
+                const int local = t - toff, tx = local % tw, ty = local / tw;
+                int n = 0;
+                for (int x0 = 0; x0 < m; x0 += kBigUnroll * kWave) {
+                    int4 b[kBigUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBigUnroll; ++u) {
+                        const int x = x0 + u * kWave + lane;
+                        b[u] = x < m ? sbox[x] : make_int4(1, 1, 0, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBigUnroll; ++u) n += box_holds(b[u], tx, ty) ? 1 : 0;
+                }
+#pragma unroll
+                for (int o = kWave / 2; o >= 1; o >>= 1) n += __shfl_xor(n, o, kWave);
+                if (lane == 0) scount[t - g0] += n;
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < g1 - g0) {
+        const int n = scount[threadIdx.x];
+        big_len[g0 + threadIdx.x] = n;
+        cnt[g0 + threadIdx.x] += n;
+    }
+}
+
+constexpr int kMergeBlock = 256;
+constexpr int kMergeA = 1024;       // small-run entries a wave holds in LDS
+constexpr int kMergeUnroll = 4;     // searches per lane that proceed together
+
+// Count of the ascending values get(0 .. n - 1) below v, by binary lifting (the largest p
+// with get(p - 1) < v): the same steps for every v, so kMergeUnroll searches of a thread run
+// in lock step with their loads issued together (indices clamped into the run).
+template <typename Get>
+__device__ inline void count_below_x4(Get get, int n, const int32_t (&v)[kMergeUnroll], int (&pos)[kMergeUnroll])
+{
+    const int top = n > 0 ? 1 << (31 - __clz(n)) : 0;
+#pragma unroll
+    for (int u = 0; u < kMergeUnroll; ++u) pos[u] = 0;
+    for (int step = top; step > 0; step >>= 1) {
+        int32_t o[kMergeUnroll];
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) o[u] = get(min(pos[u] + step, n) - 1);
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) {
+            const int p = pos[u] + step;
+            pos[u] = (p <= n && o[u] < v[u]) ? p : pos[u];
+        }
+    }
+}
+
+// Writes list entry `at` (below `end`, the tile's range end; always, when the counts agree).
+__device__ inline void put_entry(int64_t at, int64_t end, int32_t id, int t, int32_t *__restrict__ ids,
+                                 uint64_t *__restrict__ keys64, const float *__restrict__ depth, int64_t n_splats)
+{
+    if (at >= end) return;
+    ids[at] = id;
+    if (keys64)
+        keys64[at] = ((uint64_t)(uint32_t)t << 32) |
+                     (uint64_t)((uint64_t)(uint32_t)id < (uint64_t)n_splats ? __float_as_uint(depth[id]) : 0u);
+}
+
+constexpr int kMergeWaves = kMergeBlock / kWave;   // tiles per block, one per wave
+
+// The walk of merge_kernel for one tile, with the small run read through small_at (the
+// wave's LDS copy, or the run itself when it is longer than kMergeA).
+template <typename SmallAt>
+__device__ inline void merge_walk(SmallAt small_at, int na, int32_t *sChunk, int t, int tx, int ty, int64_t start,
+                                  int64_t end, int64_t b0, int n_cam, const int32_t *__restrict__ big_rank,
+                                  const int32_t *__restrict__ big_slot, const int4 *__restrict__ big_box,
+                                  const int32_t *__restrict__ rank_ids, int64_t V, int32_t *__restrict__ ids,
+                                  uint64_t *__restrict__ keys64, const float *__restrict__ depth, int64_t n_splats,
+                                  int nb, int64_t *__restrict__ err_flag)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int j = 0;   // contained big splats placed so far
+    int p = 0;   // small entries placed so far
+    const int n_chunks = (n_cam + kWave - 1) / kWave;
+    for (int c0 = 0; c0 < n_chunks; c0 += kMergeUnroll) {
+        bool in[kMergeUnroll];
+        int32_t rk[kMergeUnroll], sl[kMergeUnroll];
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) {
+            const int k = (c0 + u) * kWave + lane;
+            const bool ok = k < n_cam;
+            const int64_t kc = b0 + (ok ? k : 0);
+            in[u] = ok && box_holds(big_box[kc], tx, ty);
+            rk[u] = ok ? big_rank[kc] : INT32_MAX;
+            sl[u] = big_slot[kc];
+        }
+        int below[kMergeUnroll];
+        count_below_x4(small_at, na, rk, below);
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) {
+            if (c0 + u >= n_chunks) break;   // uniform
+            const uint64_t m = __ballot(in[u]);
+            if (in[u])
+                put_entry(start + j + __popcll(m & lanemask_lt()) + below[u], end, sl[u], t, ids, keys64, depth,
+                          n_splats);
+            // the small entries below this chunk's last rank
+            const int last_lane = min(n_cam - 1 - (c0 + u) * kWave, kWave - 1);
+            const int32_t hi = __shfl(rk[u], last_lane, kWave);
+            sChunk[lane] = rk[u];   // ascending; INT32_MAX past the camera's last big splat
+            __builtin_amdgcn_wave_barrier();
+            while (true) {   // wave-uniform
+                const int i = p + lane;
+                const int32_t v = i < na ? small_at(i) : INT32_MAX;
+                const bool here = i < na && v < hi;
+                const int cnt = __popcll(__ballot(here));
+                if (here) {
+                    // q = this chunk's ranks below v (at most last_lane, as v < hi): binary
+                    // lifting over lanes 0 .. 62, then lane q itself
+                    int q = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1) q = sChunk[q + step - 1] < v ? q + step : q;
+                    q = sChunk[q] < v ? q + 1 : q;
+                    q = min(q, kWave - 1);
+                    put_entry(start + i + j + __popcll(m & ((1ull << q) - 1)), end,
+                              rank_ids[(int64_t)(uint32_t)v < V ? v : 0], t, ids, keys64, depth, n_splats);
+                }
+                p += cnt;
+                if (cnt < kWave) break;
+            }
+            __builtin_amdgcn_wave_barrier();   // sChunk is rewritten by the next chunk
+            j += __popcll(m);
+        }
+    }
+    // the rest of the small run lies above every big rank
+    for (int i = p + lane; i < na; i += kWave) {
+        const int32_t v = small_at(i);
+        put_entry(start + i + j, end, rank_ids[(int64_t)(uint32_t)v < V ? v : 0], t, ids, keys64, depth, n_splats);
+    }
+    if (lane == 0 && j != nb)   // unreachable: big_len counted the same boxes
+        __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave per tile: its list is the merge, by depth rank, of its small run (the tile-sorted
+// small entries, ranks, at svals[ranges[t].start - big_before[t]]) and its big run (its
+// camera's big splats whose box contains the tile, in rank order); ranks are distinct. The
+// wave walks its camera's big splats in rank order, 64 at a time (one per lane): a contained
+// one goes to start + (contained ones before it) + (small ranks below it). After each chunk,
+// the small entries below the chunk's last rank that are not yet placed (the next ones of the
+// small run, found by a ballot) go to start + i + (contained big ranks below them): the
+// contained ones of earlier chunks plus those of this chunk's lanes below them. What is left
+// of the small run after the last chunk lies above every big rank. The small run is read
+// from the wave's LDS when it fits. Entry = slot; the key (tile << 32 | depth bits) only when
+// asked for. No block barriers: the waves share nothing.
+__global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__restrict__ cams, int n_cams,
+                                                            int n_tiles, const int64_t *__restrict__ words,
+                                                            const int32_t *__restrict__ ranges,
+                                                            const int32_t *__restrict__ big_len,
+                                                            const int32_t *__restrict__ big_before,
+                                                            const int32_t *__restrict__ big_rank,
+                                                            const int32_t *__restrict__ big_slot,
+                                                            const int4 *__restrict__ big_box,
+                                                            const int32_t *__restrict__ svals,
+                                                            const int32_t *__restrict__ rank_ids,
+                                                            const int64_t *__restrict__ vcount,
+                                                            int32_t *__restrict__ ids, uint64_t *__restrict__ keys64,
+                                                            const float *__restrict__ depth, int64_t n_splats,
+                                                            int64_t *__restrict__ err_flag)
+{
+    __shared__ int32_t sA_all[kMergeWaves][kMergeA];
+    __shared__ int32_t sChunk_all[kMergeWaves][kWave];
+    if (!words[kBigOk] || *err_flag) return;   // uniform
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int t = (int)(blockIdx.x * kMergeWaves + wave);
+    if (t >= n_tiles) return;   // wave-uniform; the waves of a block share no barrier
+    const int64_t start = ranges[2 * t], n = (int64_t)ranges[2 * t + 1] - start, end = start + n;
+    if (n <= 0) return;
+    const int nb = big_len[t], na = (int)n - nb;
+    const int64_t k_small = words[kBigEffSmall], V = *vcount;
+    const int64_t ss = start - big_before[t];
+    if (na < 0 || ss < 0 || ss + na > k_small) {   // unreachable when the counts agree
+        if (lane == 0) __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int32_t *A = svals + ss;
+    const int cam = camera_of_tile(cams, n_cams, t);
+    const int local = t - cams[cam].tile_offset, tw = max(cams[cam].tiles_x, 1), tx = local % tw, ty = local / tw;
+    const int64_t b0 = words[kBigCamStart + cam];
+    const int n_cam = (int)(words[kBigCamStart + cam + 1] - b0);
+    if (na <= kMergeA) {   // wave-uniform: the small run in the wave's LDS
+        for (int x0 = lane; x0 < na; x0 += kWave * 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = A[min(x0 + u * kWave, na - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (x0 + u * kWave < na) sA_all[wave][x0 + u * kWave] = v[u];
+        }
+        merge_walk([&](int i) { return sA_all[wave][i]; }, na, sChunk_all[wave], t, tx, ty, start, end, b0, n_cam,
+                   big_rank, big_slot, big_box, rank_ids, V, ids, keys64, depth, n_splats, nb, err_flag);
+    } else {
+        merge_walk([&](int i) { return A[i]; }, na, sChunk_all[wave], t, tx, ty, start, end, b0, n_cam, big_rank,
+                   big_slot, big_box, rank_ids, V, ids, keys64, depth, n_splats, nb, err_flag);
     }
 }
 
@@ -1254,10 +1720,11 @@ constexpr int kMaxTilePasses = 4;
 
 struct BinLayout {
     size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, chunk_cnt, chunk_sum, tkey, tval, chunk_rank;
+    size_t big_mat, big_rank, big_slot, big_box, big_len, big_before;
     size_t zero_begin, gdiff, stat_ranges, stat_depth, stat_tile, ghist_depth, ghist_tile;
-    size_t err;
+    size_t big_words, err;
     size_t total;
-    int64_t depth_nb, tile_nb;
+    int64_t depth_nb, tile_nb, big_cap;
     int tile_passes;
 };
 
@@ -1295,6 +1762,14 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.tkey = o;        o += align256((size_t)cap * 4);
     L.tval = o;        o += align256((size_t)cap * 4);
     L.chunk_rank = o;  o += align256((size_t)(L.tile_nb + 1) * sizeof(int32_t));
+    // splats listed by the merge: each adds more than kBigMinTiles entries to a list that fits
+    L.big_cap = min(n_splats, cap / (kBigMinTiles + 1));
+    L.big_mat = o;     o += align256((size_t)L.depth_nb * kBigMaxCams * sizeof(int32_t));
+    L.big_rank = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
+    L.big_slot = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
+    L.big_box = o;     o += align256((size_t)L.big_cap * sizeof(int4));
+    L.big_len = o;     o += align256((size_t)n_tiles * sizeof(int32_t));
+    L.big_before = o;  o += align256((size_t)n_tiles * sizeof(int32_t));
     L.zero_begin = o;
     L.gdiff = o;       o += align256((size_t)n_tiles * sizeof(int32_t));
     L.stat_ranges = o; o += align256((size_t)((n_tiles + kSortChunk - 1) / kSortChunk) * sizeof(uint64_t));
@@ -1302,6 +1777,7 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.stat_tile = o;   o += align256((size_t)L.tile_passes * L.tile_nb * stat_row);
     L.ghist_depth = o; o += align256((size_t)kDepthPasses * kRadix * sizeof(unsigned));
     L.ghist_tile = o;  o += align256((size_t)kMaxTilePasses * kRadix * sizeof(unsigned));
+    L.big_words = o;   o += align256((size_t)kBigWords * sizeof(int64_t));
     L.err = o;         o += 256;
     L.total = o;
     return L;
@@ -1405,6 +1881,14 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     unsigned *ghist_depth = (unsigned *)(ws + L.ghist_depth), *ghist_tile = (unsigned *)(ws + L.ghist_tile);
     int64_t *err = (int64_t *)(ws + L.err);
     const int64_t *K = (const int64_t *)bins->counters;
+    // splats with more than big_tiles tiles are listed by the per-tile merge (launch tuning;
+    // calls with more cameras than the merge's table take the plain sort)
+    const int big_tiles = (current_tuning().big_tiles > 0 && n_cams <= kBigMaxCams) ? current_tuning().big_tiles : 0;
+    int32_t *big_mat = (int32_t *)(ws + L.big_mat), *big_rank = (int32_t *)(ws + L.big_rank);
+    int32_t *big_slot = (int32_t *)(ws + L.big_slot);
+    int4 *big_box = (int4 *)(ws + L.big_box);
+    int32_t *big_len = (int32_t *)(ws + L.big_len), *big_before = (int32_t *)(ws + L.big_before);
+    int64_t *big_words = (int64_t *)(ws + L.big_words);
 
     // ranges start empty, (0, 0); the look-back state, counts, histograms and the work-list header start at zero
     if (n_splats == 0) {
@@ -1437,7 +1921,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     const int64_t span = max((int64_t)8192, (n_splats + 511) / 512);
     hipLaunchKernelGGL(tile_corner_kernel, dim3(grid_for(n_splats, (int)span)), dim3(kCornerBlock), 0, st,
                        (const int32_t *)dvalA, (const int64_t *)dcount, (const int4 *)s->rect, cams, (int)n_cams,
-                       n_splats, span, tile_cnt);
+                       n_splats, span, big_tiles, tile_cnt);
     hipLaunchKernelGGL(tile_count_kernel, dim3((unsigned)n_cams), dim3(kCountBlock), 0, st, cams, passes, tile_cnt,
                        ghist_tile, err);
 
@@ -1461,11 +1945,26 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
 
     // 3. emit offsets in depth-rank order; K and the overflow flag go to bins->counters
     hipLaunchKernelGGL(rank_sum_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, (const int32_t *)rank_tiles,
-                       (const int64_t *)dcount, chunk_sum);
+                       (const int64_t *)dcount, chunk_sum, big_tiles);
+    // with the merge, the scan gives the entries of small splats; big_scan then sets K
     hipLaunchKernelGGL(chunk_scan_kernel<int64_t>, dim3(1), dim3(kScanBlock), 0, st, chunk_sum, (int64_t)0,
-                       (const int64_t *)dcount, bins->counters, bins->counters + 1, cap);
+                       (const int64_t *)dcount, big_tiles ? big_words + kBigKSmall : bins->counters,
+                       big_tiles ? (int64_t *)nullptr : bins->counters + 1, cap);
     hipLaunchKernelGGL(rank_offsets_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, (const int32_t *)rank_tiles,
-                       (const int64_t *)dcount, (const int64_t *)chunk_sum, offsets);
+                       (const int64_t *)dcount, (const int64_t *)chunk_sum, offsets, big_tiles);
+    if (big_tiles) {
+        hipLaunchKernelGGL(big_count_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, rank_ids,
+                           (const int32_t *)rank_tiles, (const int64_t *)dcount, cams, (int)n_cams, big_tiles, big_mat,
+                           L.depth_nb, big_words, (const int64_t *)err);
+        hipLaunchKernelGGL(big_scan_kernel, dim3((unsigned)n_cams), dim3(kScanBlock), 0, st, big_mat, L.depth_nb,
+                           (const int64_t *)dcount, (int)n_cams, big_words, bins->counters, cap, L.big_cap, err);
+        hipLaunchKernelGGL(big_scatter_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, rank_ids,
+                           (const int32_t *)rank_tiles, (const int64_t *)dcount, cams, (int)n_cams, big_tiles,
+                           (const int4 *)s->rect, (const int32_t *)big_mat, L.depth_nb, (const int64_t *)big_words,
+                           big_rank, big_slot, big_box, (const int64_t *)err);
+    }
+    // entries the tile passes sort: all K (or none on overflow), or the small splats' ones
+    const int64_t *sort_n = big_tiles ? (const int64_t *)(big_words + kBigEffSmall) : K;
 
     // 4. stable passes by tile id. The first pass takes the entries in depth-rank order,
     // either emitted into a buffer or generated inside the pass (launch tuning); the last
@@ -1474,15 +1973,18 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     const unsigned g_tile = resident_grid((const void *)onesweep_kernel, kSortBlock, L.tile_nb);
     uint32_t *kW = (uint32_t *)(ws + L.tkey), *kX = (uint32_t *)bins->keys;
     int32_t *vW = (int32_t *)(ws + L.tval), *vX = bins->ids;
-    // the buffer pass i >= 1 reads: W when (passes - 1 - i) is even
-    const bool first_to_W = passes >= 2 && ((passes - 2) & 1) == 0;
-    uint32_t *k0out = passes == 1 ? (uint32_t *)nullptr : (first_to_W ? kW : kX);
-    int32_t *v0out = passes == 1 ? bins->ids : (first_to_W ? vW : vX);
     // the sorted 64-bit keys, unless the caller does without them (the last pass then writes
     // ids only and gathers no depth)
     uint64_t *keys_final = (bins->flags & GS_BINS_NO_KEYS) ? (uint64_t *)nullptr : bins->keys;
-    uint64_t *k64 = passes == 1 ? keys_final : (uint64_t *)nullptr;
-    if (current_tuning().generate_entries) {
+    // Without the merge the last pass writes the list (ids, keys) into bins; with it, the
+    // last pass writes tile keys and ranks into W, which the merge reads. Pass i writes the
+    // pair the last pass writes when (passes - 1 - i) is even, the other pair otherwise.
+    const bool first_to_W = big_tiles ? ((passes - 1) & 1) == 0 : passes >= 2 && ((passes - 2) & 1) == 0;
+    // (with the merge, the last pass writes only the ranks: nothing reads its tile keys)
+    uint32_t *k0out = passes == 1 ? (uint32_t *)nullptr : (first_to_W ? kW : kX);
+    int32_t *v0out = passes == 1 && !big_tiles ? bins->ids : (first_to_W ? vW : vX);
+    uint64_t *k64 = passes == 1 && !big_tiles ? keys_final : (uint64_t *)nullptr;
+    if (current_tuning().generate_entries && !big_tiles) {
         int32_t *chunk_rank = (int32_t *)(ws + L.chunk_rank);
         hipLaunchKernelGGL(chunk_rank_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
                            (const int32_t *)rank_tiles, (const int64_t *)dcount, K, cap, chunk_rank,
@@ -1495,25 +1997,27 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
                            ghist_tile, stat_tile, k0out, v0out, k64, s->depth, err);
     } else {
         // the emitted entries go to the pair the first pass does not write
-        const bool emit_to_X = passes >= 2 && first_to_W;
+        const bool emit_to_X = big_tiles ? first_to_W : passes >= 2 && first_to_W;
         uint32_t *ek = emit_to_X ? kX : kW;
         int32_t *ev = emit_to_X ? vX : vW;
-        hipLaunchKernelGGL(emit_kernel, dim3(grid_for(n_splats, 256)), dim3(256), 0, st, rank_ids, offsets,
+        hipLaunchKernelGGL(emit_kernel, dim3(min(grid_for(n_splats, 256), (unsigned)device_cu_count() * 8)), dim3(256),
+                           0, st, rank_ids, offsets,
                            (const int32_t *)rank_tiles, (const int4 *)s->rect, cams, (int)n_cams, n_splats,
-                           (const int64_t *)dcount, K, cap, ek, ev, (const int64_t *)err);
-        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, ek, ev, K, cap, 0, ghist_tile,
+                           (const int64_t *)dcount, K, cap, ek, ev, big_tiles, (const int64_t *)err);
+        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, ek, ev, sort_n, cap, 0, ghist_tile,
                            stat_tile, k0out, v0out, k64, s->depth, (const int32_t *)nullptr, (int32_t *)nullptr,
                            n_splats, 1, err);
     }
     uint32_t *kin = first_to_W ? kW : kX;
     int32_t *vin = first_to_W ? vW : vX;
     for (int pass = 1; pass < passes; ++pass) {
-        const bool last = pass == passes - 1;
+        const bool last = pass == passes - 1 && !big_tiles;
         uint32_t *kout = kin == kW ? kX : kW;
         int32_t *vout = vin == vW ? vX : vW;
-        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, kin, vin, K, cap,
+        hipLaunchKernelGGL(onesweep_kernel, dim3(g_tile), dim3(kSortBlock), 0, st, kin, vin, sort_n, cap,
                            pass * kRadixBits, ghist_tile + pass * kRadix,
-                           stat_tile + (int64_t)pass * L.tile_nb * kRadix, last ? (uint32_t *)nullptr : kout,
+                           stat_tile + (int64_t)pass * L.tile_nb * kRadix,
+                           pass == passes - 1 ? (uint32_t *)nullptr : kout,
                            last ? bins->ids : vout,
                            last ? keys_final : (uint64_t *)nullptr, s->depth, (const int32_t *)nullptr,
                            (int32_t *)nullptr, n_splats, 1, err);
@@ -1522,11 +2026,27 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     }
     rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
+    const unsigned g_big_tiles = grid_for(bins->n_tiles, kBigGroup);
+    if (big_tiles)   // the big splats' tiles join the list lengths
+        hipLaunchKernelGGL(big_len_kernel, dim3(g_big_tiles), dim3(256), 0, st, cams, (int)n_cams, bins->n_tiles,
+                           (const int64_t *)big_words, (const int4 *)big_box, tile_cnt, big_len,
+                           (const int64_t *)err);
     // 5. ranges from the list lengths, when the list was built
     hipLaunchKernelGGL(ranges_kernel,
                        dim3(resident_grid((const void *)ranges_kernel, kSortBlock, grid_for(bins->n_tiles, kSortChunk))),
                        dim3(kSortBlock), 0, st, (const int32_t *)tile_cnt, bins->n_tiles, K, cap, stat_ranges,
-                       bins->ranges, err);
+                       bins->ranges, big_tiles ? (const int32_t *)big_len : (const int32_t *)nullptr,
+                       big_tiles ? big_before : (int32_t *)nullptr, err);
+    if (big_tiles) {   // the small run (sorted into W) and the big run of each tile, merged into bins
+        hipLaunchKernelGGL(merge_kernel, dim3(grid_for(bins->n_tiles, kMergeWaves)), dim3(kMergeBlock), 0, st, cams,
+                           (int)n_cams,
+                           bins->n_tiles, (const int64_t *)big_words, (const int32_t *)bins->ranges,
+                           (const int32_t *)big_len, (const int32_t *)big_before, (const int32_t *)big_rank,
+                           (const int32_t *)big_slot, (const int4 *)big_box, (const int32_t *)vW, rank_ids,
+                           (const int64_t *)dcount, bins->ids, keys_final, s->depth, n_splats, err);
+        rc = check_launch("merge");
+        if (rc != GS_OK) return rc;
+    }
 
     // 6. the work list
     return build_schedule(bins, (const int64_t *)err, st);

@@ -34,7 +34,7 @@ int check_hip(hipError_t e, const char *what)
 
 int check_launch(const char *what) { return check_hip(hipGetLastError(), what); }
 
-static gs_tuning g_tuning = {256, 4, 32, 1, 0, 1, 0, 1, 4, 64};
+static gs_tuning g_tuning = {256, 4, 32, 1, 0, 1, 0, 1, 4, 64, 0};
 
 const gs_tuning &current_tuning() { return g_tuning; }
 
@@ -150,7 +150,8 @@ extern "C" int gs_abi_layout(int64_t *out, int n)
         (int64_t)sizeof(gs_splats), (int64_t)offsetof(gs_splats, capacity),
         (int64_t)sizeof(gs_params), (int64_t)sizeof(gs_bins), (int64_t)offsetof(gs_bins, capacity),
         (int64_t)offsetof(gs_bins, n_tiles), (int64_t)sizeof(gs_tuning), (int64_t)offsetof(gs_tuning, bwd_segs),
-        (int64_t)offsetof(gs_tuning, atomic_lanes), (int64_t)offsetof(gs_tuning, batch)};
+        (int64_t)offsetof(gs_tuning, atomic_lanes), (int64_t)offsetof(gs_tuning, batch),
+        (int64_t)offsetof(gs_tuning, big_tiles)};
     const int m = (int)(sizeof(v) / sizeof(v[0]));
     for (int k = 0; k < n && k < m; ++k) out[k] = v[k];
     return m;
@@ -251,10 +252,12 @@ extern "C" int gs_set_tuning(const gs_tuning *t)
     if (t->split_len < 1 || (t->split_parts != 2 && t->split_parts != 4) || t->waves_per_cu < 4 ||
         t->waves_per_cu > 64 || (t->generate_entries != 0 && t->generate_entries != 1) || t->item_grab < 1 ||
         t->item_grab > 16 || t->prio_len < 0 || (t->bwd_segs != 1 && t->bwd_segs != 2 && t->bwd_segs != 4) ||
-        t->atomic_lanes < 1 || t->atomic_lanes > 64 || (t->batch != 32 && t->batch != 64))
+        t->atomic_lanes < 1 || t->atomic_lanes > 64 || (t->batch != 32 && t->batch != 64) ||
+        (t->big_tiles != 0 && t->big_tiles < 4))
         return set_error(GS_ERR_INVALID, "gs_set_tuning: split_len >= 1, split_parts in {2, 4}, waves_per_cu in "
                                          "[4, 64], generate_entries in {0, 1}, item_grab in [1, 16], prio_len >= 0, "
-                                         "bwd_segs in {1, 2, 4}, atomic_lanes in [1, 64], batch in {32, 64}");
+                                         "bwd_segs in {1, 2, 4}, atomic_lanes in [1, 64], batch in {32, 64}, "
+                                         "big_tiles 0 or >= 4");
     g_tuning = *t;
     return GS_OK;
 }

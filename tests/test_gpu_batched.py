@@ -144,8 +144,9 @@ def test_batched_gradients_match_oracle_sum_over_views():
 
 @pytest.mark.parametrize("name", ["c2_20k", "c5_small"])
 def test_results_do_not_depend_on_launch_tuning(name):
-    """Splitting, grid size and priority change only the schedule: the image is bit-identical
-    (each pixel runs the same arithmetic) and gradients agree up to atomic ordering."""
+    """Splitting, grid size, priority and the sort's merge of large splats change only the
+    schedule or how the same list is built: the image is bit-identical (each pixel runs the
+    same arithmetic) and gradients agree up to atomic ordering."""
     _print_case("tuning", wl=name)
     from paper_2312_02121_amd import autotune
     wl = {"c2_20k": lambda: synth.make_config(2, n_override=20_000), "c5_small": small_c5}[name]()
@@ -161,7 +162,9 @@ def test_results_do_not_depend_on_launch_tuning(name):
                   {"split_len": 64, "split_parts": 4, "waves_per_cu": 16, "bwd_segs": 4, "atomic_lanes": 4,
                    "batch": 32},
                   {"split_len": 256, "split_parts": 2, "waves_per_cu": 32, "bwd_segs": 2, "atomic_lanes": 64,
-                   "batch": 32, "prio_len": 96}):
+                   "batch": 32, "prio_len": 96},
+                  {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "big_tiles": 4},
+                  {"split_len": 128, "split_parts": 4, "waves_per_cu": 16, "bwd_segs": 2, "big_tiles": 64}):
             autotune.apply(t)
             _, _, _, step = build(wl, "fused")
             step()

@@ -33,6 +33,8 @@ def _workloads():
         "dense_small": synth.tiny_scene(41, n=600, width=100, height=77, log_scale=(-1.5, 0.6), opac_sd=2.5),
         # 257 x 125 tiles: more than one LDS band of the per-tile length count
         "wide_4k": synth.tiny_scene(42, n=500, width=4100, height=2000, f=2000.0, log_scale=(-2.0, 0.8)),
+        # 16 orbit views inside the scene: splats near a camera cover most of its tiles
+        "c4_20k": synth.make_config(4, n_override=20_000),
     }
 
 
@@ -81,6 +83,83 @@ def test_bins_bit_exact(name, generate):
     assert np.array_equal(g["keys"], okeys)
     assert np.array_equal(g["ids"], oids.astype(np.int32))
     assert np.array_equal(g["ranges"], np.concatenate(oranges).astype(np.int32))
+
+
+def _oracle_list(wl, r):
+    toffs = tile_offsets(wl)
+    okeys, oids, oranges = [], [], []
+    for k, cam in enumerate(wl.cameras):
+        o = oracle.project(wl.scenes[cam.scene], cam, oracle_params())
+        b = oracle.bin_and_sort(o, cam, tile_offset=toffs[k])
+        poff = int(r.cams.host[k]["proj_offset"])
+        okeys.append(b["keys"])
+        oids.append(b["ids"] + poff)
+        oranges.append(np.where(b["ranges"][:, 1:] > b["ranges"][:, :1], b["ranges"] + sum(map(len, okeys[:-1])), 0))
+    return np.concatenate(okeys), np.concatenate(oids).astype(np.int32), np.concatenate(oranges).astype(np.int32)
+
+
+@pytest.mark.parametrize("big_tiles", [4, 16, 1024])
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small", "wide_4k", "c4_20k"])
+def test_bins_bit_exact_with_merge(name, big_tiles):
+    """Splats with more than big_tiles tiles listed by the per-tile merge instead of the tile
+    sort: keys, ids and ranges bit-exact, and the image as the oracle's."""
+    from paper_2312_02121_amd import autotune
+    wl = wl_cache()[name]
+    autotune.apply({**autotune.default_tuning(), "big_tiles": big_tiles})
+    try:
+        r, st = gpu_forward(wl)
+    finally:
+        autotune.apply(autotune.default_tuning())
+    okeys, oids, oranges = _oracle_list(wl, r)
+    tiles = r.splats.tiles[: r.cams.n_splats].cpu().numpy()
+    n_big = int((tiles > big_tiles).sum())
+    _print_case("bins_merge", wl=name, big_tiles=big_tiles, big_splats=n_big,
+                big_entries=int(tiles[tiles > big_tiles].sum()), K=okeys.size)
+    assert st.K == okeys.size
+    g = bins_arrays(r, st.K)
+    assert np.array_equal(g["keys"], okeys)
+    assert np.array_equal(g["ids"], oids)
+    assert np.array_equal(g["ranges"], oranges)
+    if name in ("c1", "dense_small"):
+        _forward_compare(wl, r, st)
+
+
+def test_merge_overflow_and_give_up_build_no_list():
+    """With the merge: a capacity below K reports overflow and builds nothing (buffers filled
+    with garbage first); a forced give-up of the sort's look-back reports flag 2 and builds
+    nothing; a regrown call builds the oracle's list."""
+    _print_case("merge_overflow", wl="c4_20k")
+    from paper_2312_02121_amd import abi, autotune, pipeline
+    wl = wl_cache()["c4_20k"]
+    g = pipeline.GaussianSet(wl.scenes)
+    cams = pipeline.CameraSet(wl.cameras, g.sizes)
+    autotune.apply({**autotune.default_tuning(), "big_tiles": 16})
+    try:
+        r = pipeline.Rasterizer(cams, capacity=4096)
+        r.project(g)
+        b = r.bins
+        for t in (b.keys, b.ids, b.ranges, b.workspace):
+            t.view(torch.uint8).fill_(0x7F)
+        r.bin_and_sort()
+        torch.cuda.synchronize()
+        K, over = r.read_count()
+        assert over and K > 4096
+        assert int(b.ranges.abs().max()) == 0
+        st = r.forward(g)                         # regrows and builds the full list
+        torch.cuda.synchronize()
+        okeys, oids, oranges = _oracle_list(wl, r)
+        assert st.K == K == okeys.size
+        assert np.array_equal(bins_arrays(r, st.K)["ids"], oids)
+        abi.gs_set_sort_wait_limit(-1)
+        try:
+            r.bin_and_sort()
+            torch.cuda.synchronize()
+        finally:
+            abi.gs_set_sort_wait_limit(abi.DEFAULT_SORT_WAIT_LIMIT)
+        assert int(r.bins.counters[1]) & 2
+        assert int(r.bins.ranges.abs().max()) == 0
+    finally:
+        autotune.apply(autotune.default_tuning())
 
 
 def _forward_compare(wl, r, st, prm=None, check_last=True):
@@ -304,8 +383,8 @@ def test_projection_record_is_optional():
     assert torch.equal(r.bins.keys[: st.K], r2.bins.keys[: st2.K]) and torch.equal(st.image, st2.image)
 
 
-@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k"])
-@pytest.mark.parametrize("generate", [0, 1])
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k", "c4_20k"])
+@pytest.mark.parametrize("generate", [0, 1, "merge"])
 def test_sorted_keys_are_optional(name, generate):
     """With GS_BINS_NO_KEYS the sort writes no 64-bit keys; the ids, ranges, count, work list
     and image are those of a call that writes them (one tile pass for the tiny scene, two at
@@ -314,7 +393,8 @@ def test_sorted_keys_are_optional(name, generate):
     from paper_2312_02121_amd import autotune, pipeline
     wl = wl_cache()[name]
     g = pipeline.GaussianSet(wl.scenes)
-    autotune.apply({**autotune.default_tuning(), "generate_entries": generate})
+    knob = {"big_tiles": 16} if generate == "merge" else {"generate_entries": generate}
+    autotune.apply({**autotune.default_tuning(), **knob})
     try:
         out = []
         for write_keys in (True, False):
