@@ -201,10 +201,11 @@ typedef struct gs_tuning {
                                 DPP row operations (cheaper for large splats) */
     int32_t batch;           /* 32 or 64: list entries a wave stages in LDS per batch (one per
                                 lane; gradients are moved to memory once per batch) */
-    int32_t big_tiles;       /* 0, or >= 4: gs_bin_and_sort lists a splat whose box has more than
+    int32_t big_tiles;       /* 0, or >= 16: gs_bin_and_sort lists a splat whose box has more than
                                 this many tiles by a per-tile merge instead of sorting its entries
-                                by tile (the list is the same; for calls of at most 64 cameras).
-                                Pays off when a few splats cover most tiles of a view */
+                                by tile (the list is the same; for calls of at most 64 cameras,
+                                with tile coordinates below 65536, else flag 2). Pays off when a
+                                few splats cover most tiles of a view */
 } gs_tuning;
 
 /* ------------------------------------------------------------------------- utilities */

@@ -1166,7 +1166,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
 //   merge       per tile, the merge of its small run with its filtered big splats, written
 //               as ids (and keys).
 constexpr int kBigMaxCams = 64;   // cameras per call for which the merge is used
-constexpr int kBigMinTiles = 4;   // smallest big_tiles: the big splat arrays hold K_cap / 5
+constexpr int kBigMinTiles = 16;  // smallest big_tiles: the big splat arrays hold K_cap / 17
 // words of the call's big-splat state (after the per-camera starts)
 constexpr int kBigKSmall = 0;     // entries of small splats (written by the offset scan)
 constexpr int kBigKBig = 1;       // entries of big splats (summed by big_count)
@@ -1176,10 +1176,19 @@ constexpr int kBigCamStart = 8;   // [kBigMaxCams + 1] start of each camera's bi
 constexpr int kBigCamTotal = kBigCamStart + kBigMaxCams + 1;   // [kBigMaxCams] big splats per camera
 constexpr int kBigWords = kBigCamTotal + kBigMaxCams;
 
-__device__ inline bool box_holds(const int4 &b, int tx, int ty)
+// A big splat's camera-local tile box, x0 | y0 << 16 and x1 | y1 << 16 (tile coordinates
+// below 2^16; a larger one makes the sort fail with flag 2 instead).
+__device__ inline uint2 pack_box(const int4 &b)
 {
-    return b.x <= tx && tx <= b.z && b.y <= ty && ty <= b.w;
+    return make_uint2((uint32_t)b.x | ((uint32_t)b.y << 16), (uint32_t)b.z | ((uint32_t)b.w << 16));
 }
+
+__device__ inline bool box_holds(const uint2 &b, int tx, int ty)
+{
+    return (int)(b.x & 0xffff) <= tx && tx <= (int)(b.y & 0xffff) && (int)(b.x >> 16) <= ty && ty <= (int)(b.y >> 16);
+}
+
+constexpr uint2 kEmptyBox = {1u, 0u};   // x0 = 1 > x1 = 0: holds no tile
 
 // Per chunk c of kSortChunk ranks: the count of big splats of each camera (mat[cam * stride
 // + c]; cameras' totals summed into words[kBigCamTotal + cam]) and the sum of their tiles
@@ -1287,8 +1296,8 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
                                                                  const int64_t *__restrict__ words,
                                                                  int32_t *__restrict__ big_rank,
                                                                  int32_t *__restrict__ big_slot,
-                                                                 int4 *__restrict__ big_box,
-                                                                 const int64_t *__restrict__ err_flag)
+                                                                 uint2 *__restrict__ big_box,
+                                                                 int64_t *__restrict__ err_flag)
 {
     __shared__ int32_t lrank[kSortChunk];
     __shared__ int cursor[kBigMaxCams];
@@ -1323,7 +1332,10 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
             if (ok && pos >= 0 && pos < n_big) {   // always true when the counts agree
                 big_rank[pos] = r;
                 big_slot[pos] = slot;
-                big_box[pos] = rect[slot];
+                const int4 b = rect[slot];
+                if ((uint32_t)(b.x | b.y | b.z | b.w) > 0xffffu)
+                    __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                big_box[pos] = pack_box(b);
             }
             if (ok && (peers & lanemask_lt()) == 0) cursor[cam] = (int)(pos + __popcll(peers));
             __builtin_amdgcn_wave_barrier();
@@ -1339,14 +1351,14 @@ constexpr int kBigStage = 1024;
 constexpr int kBigUnroll = 4;   // boxes per lane in flight
 
 // Copies boxes k0 .. k0 + m - 1 into LDS, four per thread, loads issued first.
-__device__ inline void stage_boxes(int4 *sbox, const int4 *__restrict__ box, int64_t k0, int m)
+__device__ inline void stage_boxes(uint2 *sbox, const uint2 *__restrict__ box, int64_t k0, int m)
 {
     static_assert(kBigStage == 4 * 256, "four boxes per thread");
-    int4 b[4];
+    uint2 b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int x = (int)threadIdx.x + u * 256;
-        b[u] = x < m ? box[k0 + x] : make_int4(1, 1, 0, 0);
+        b[u] = x < m ? box[k0 + x] : kEmptyBox;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -1359,11 +1371,11 @@ __device__ inline void stage_boxes(int4 *sbox, const int4 *__restrict__ box, int
 // added to the tile's list length.
 __global__ __launch_bounds__(256) void big_len_kernel(const gs_camera *__restrict__ cams, int n_cams, int n_tiles,
                                                       const int64_t *__restrict__ words,
-                                                      const int4 *__restrict__ big_box, int32_t *__restrict__ cnt,
+                                                      const uint2 *__restrict__ big_box, int32_t *__restrict__ cnt,
                                                       int32_t *__restrict__ big_len,
                                                       const int64_t *__restrict__ err_flag)
 {
-    __shared__ int4 sbox[kBigStage];
+    __shared__ uint2 sbox[kBigStage];
     __shared__ int scount[kBigGroup];
     if (!words[kBigOk] || *err_flag) return;   // uniform
     const int g0 = blockIdx.x * kBigGroup, g1 = min(n_tiles, g0 + kBigGroup);
@@ -1385,11 +1397,11 @@ __global__ __launch_bounds__(256) void big_len_kernel(const gs_camera *__restric
                 const int local = t - toff, tx = local % tw, ty = local / tw;
                 int n = 0;
                 for (int x0 = 0; x0 < m; x0 += kBigUnroll * kWave) {
-                    int4 b[kBigUnroll];
+                    uint2 b[kBigUnroll];
 #pragma unroll
                     for (int u = 0; u < kBigUnroll; ++u) {
                         const int x = x0 + u * kWave + lane;
-                        b[u] = x < m ? sbox[x] : make_int4(1, 1, 0, 0);
+                        b[u] = x < m ? sbox[x] : kEmptyBox;
                     }
 #pragma unroll
                     for (int u = 0; u < kBigUnroll; ++u) n += box_holds(b[u], tx, ty) ? 1 : 0;
@@ -1451,7 +1463,7 @@ constexpr int kMergeWaves = kMergeBlock / kWave;   // tiles per block, one per w
 template <typename SmallAt>
 __device__ inline void merge_walk(SmallAt small_at, int na, int32_t *sChunk, int t, int tx, int ty, int64_t start,
                                   int64_t end, int64_t b0, int n_cam, const int32_t *__restrict__ big_rank,
-                                  const int32_t *__restrict__ big_slot, const int4 *__restrict__ big_box,
+                                  const int32_t *__restrict__ big_slot, const uint2 *__restrict__ big_box,
                                   const int32_t *__restrict__ rank_ids, int64_t V, int32_t *__restrict__ ids,
                                   uint64_t *__restrict__ keys64, const float *__restrict__ depth, int64_t n_splats,
                                   int nb, int64_t *__restrict__ err_flag)
@@ -1536,7 +1548,7 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
                                                             const int32_t *__restrict__ big_before,
                                                             const int32_t *__restrict__ big_rank,
                                                             const int32_t *__restrict__ big_slot,
-                                                            const int4 *__restrict__ big_box,
+                                                            const uint2 *__restrict__ big_box,
                                                             const int32_t *__restrict__ svals,
                                                             const int32_t *__restrict__ rank_ids,
                                                             const int64_t *__restrict__ vcount,
@@ -1767,7 +1779,7 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     L.big_mat = o;     o += align256((size_t)L.depth_nb * kBigMaxCams * sizeof(int32_t));
     L.big_rank = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
     L.big_slot = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
-    L.big_box = o;     o += align256((size_t)L.big_cap * sizeof(int4));
+    L.big_box = o;     o += align256((size_t)L.big_cap * sizeof(uint2));
     L.big_len = o;     o += align256((size_t)n_tiles * sizeof(int32_t));
     L.big_before = o;  o += align256((size_t)n_tiles * sizeof(int32_t));
     L.zero_begin = o;
@@ -1886,7 +1898,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     const int big_tiles = (current_tuning().big_tiles > 0 && n_cams <= kBigMaxCams) ? current_tuning().big_tiles : 0;
     int32_t *big_mat = (int32_t *)(ws + L.big_mat), *big_rank = (int32_t *)(ws + L.big_rank);
     int32_t *big_slot = (int32_t *)(ws + L.big_slot);
-    int4 *big_box = (int4 *)(ws + L.big_box);
+    uint2 *big_box = (uint2 *)(ws + L.big_box);
     int32_t *big_len = (int32_t *)(ws + L.big_len), *big_before = (int32_t *)(ws + L.big_before);
     int64_t *big_words = (int64_t *)(ws + L.big_words);
 
@@ -1961,7 +1973,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
         hipLaunchKernelGGL(big_scatter_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, rank_ids,
                            (const int32_t *)rank_tiles, (const int64_t *)dcount, cams, (int)n_cams, big_tiles,
                            (const int4 *)s->rect, (const int32_t *)big_mat, L.depth_nb, (const int64_t *)big_words,
-                           big_rank, big_slot, big_box, (const int64_t *)err);
+                           big_rank, big_slot, big_box, err);
     }
     // entries the tile passes sort: all K (or none on overflow), or the small splats' ones
     const int64_t *sort_n = big_tiles ? (const int64_t *)(big_words + kBigEffSmall) : K;
@@ -2029,7 +2041,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     const unsigned g_big_tiles = grid_for(bins->n_tiles, kBigGroup);
     if (big_tiles)   // the big splats' tiles join the list lengths
         hipLaunchKernelGGL(big_len_kernel, dim3(g_big_tiles), dim3(256), 0, st, cams, (int)n_cams, bins->n_tiles,
-                           (const int64_t *)big_words, (const int4 *)big_box, tile_cnt, big_len,
+                           (const int64_t *)big_words, (const uint2 *)big_box, tile_cnt, big_len,
                            (const int64_t *)err);
     // 5. ranges from the list lengths, when the list was built
     hipLaunchKernelGGL(ranges_kernel,
@@ -2042,7 +2054,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
                            (int)n_cams,
                            bins->n_tiles, (const int64_t *)big_words, (const int32_t *)bins->ranges,
                            (const int32_t *)big_len, (const int32_t *)big_before, (const int32_t *)big_rank,
-                           (const int32_t *)big_slot, (const int4 *)big_box, (const int32_t *)vW, rank_ids,
+                           (const int32_t *)big_slot, (const uint2 *)big_box, (const int32_t *)vW, rank_ids,
                            (const int64_t *)dcount, bins->ids, keys_final, s->depth, n_splats, err);
         rc = check_launch("merge");
         if (rc != GS_OK) return rc;

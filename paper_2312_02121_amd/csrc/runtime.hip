@@ -253,11 +253,11 @@ extern "C" int gs_set_tuning(const gs_tuning *t)
         t->waves_per_cu > 64 || (t->generate_entries != 0 && t->generate_entries != 1) || t->item_grab < 1 ||
         t->item_grab > 16 || t->prio_len < 0 || (t->bwd_segs != 1 && t->bwd_segs != 2 && t->bwd_segs != 4) ||
         t->atomic_lanes < 1 || t->atomic_lanes > 64 || (t->batch != 32 && t->batch != 64) ||
-        (t->big_tiles != 0 && t->big_tiles < 4))
+        (t->big_tiles != 0 && t->big_tiles < 16))
         return set_error(GS_ERR_INVALID, "gs_set_tuning: split_len >= 1, split_parts in {2, 4}, waves_per_cu in "
                                          "[4, 64], generate_entries in {0, 1}, item_grab in [1, 16], prio_len >= 0, "
                                          "bwd_segs in {1, 2, 4}, atomic_lanes in [1, 64], batch in {32, 64}, "
-                                         "big_tiles 0 or >= 4");
+                                         "big_tiles 0 or >= 16");
     g_tuning = *t;
     return GS_OK;
 }

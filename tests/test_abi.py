@@ -89,14 +89,14 @@ def test_tuning_is_validated_and_round_trips(lib):
                       "item_grab": 1, "prio_len": 0, "bwd_segs": 1, "atomic_lanes": 4, "batch": 64, "big_tiles": 0}
     for bad in ({"split_len": 0}, {"split_parts": 3}, {"waves_per_cu": 2}, {"waves_per_cu": 65},
                 {"generate_entries": 2}, {"item_grab": 0}, {"item_grab": 17}, {"prio_len": -1}, {"bwd_segs": 3},
-                {"atomic_lanes": 0}, {"atomic_lanes": 65}, {"batch": 128}, {"batch": 48}, {"big_tiles": 3},
+                {"atomic_lanes": 0}, {"atomic_lanes": 65}, {"batch": 128}, {"batch": 48}, {"big_tiles": 15},
                 {"big_tiles": -1}):
         t = abi.GsTuning(**{**before, **bad})
         with pytest.raises(abi.GsError):
             abi.gs_set_tuning(t)
         assert abi.gs_get_tuning().as_dict() == before
     want = {"split_len": 1024, "split_parts": 2, "waves_per_cu": 16, "split_priority": 0, "generate_entries": 1,
-            "item_grab": 4, "prio_len": 512, "bwd_segs": 4, "atomic_lanes": 64, "batch": 32, "big_tiles": 4}
+            "item_grab": 4, "prio_len": 512, "bwd_segs": 4, "atomic_lanes": 64, "batch": 32, "big_tiles": 16}
     abi.gs_set_tuning(abi.GsTuning(**want))
     try:
         assert abi.gs_get_tuning().as_dict() == want

@@ -163,7 +163,7 @@ def test_results_do_not_depend_on_launch_tuning(name):
                    "batch": 32},
                   {"split_len": 256, "split_parts": 2, "waves_per_cu": 32, "bwd_segs": 2, "atomic_lanes": 64,
                    "batch": 32, "prio_len": 96},
-                  {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "big_tiles": 4},
+                  {"split_len": 256, "split_parts": 4, "waves_per_cu": 32, "big_tiles": 16},
                   {"split_len": 128, "split_parts": 4, "waves_per_cu": 16, "bwd_segs": 2, "big_tiles": 64}):
             autotune.apply(t)
             _, _, _, step = build(wl, "fused")

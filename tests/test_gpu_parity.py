@@ -98,7 +98,7 @@ def _oracle_list(wl, r):
     return np.concatenate(okeys), np.concatenate(oids).astype(np.int32), np.concatenate(oranges).astype(np.int32)
 
 
-@pytest.mark.parametrize("big_tiles", [4, 16, 1024])
+@pytest.mark.parametrize("big_tiles", [16, 64, 1024])
 @pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small", "wide_4k", "c4_20k"])
 def test_bins_bit_exact_with_merge(name, big_tiles):
     """Splats with more than big_tiles tiles listed by the per-tile merge instead of the tile
