@@ -321,8 +321,10 @@ size_t gs_bin_and_sort_workspace_size(int64_t n_splats, int64_t capacity, int32_
  * 64-bit keys -- and find each tile's [start, end), then write the rasterizer's work list
  * (tiles in decreasing list length, long ones split into four parts). The sort is done as
  * a stable depth sort of the splats followed by a stable tile-id sort of the entries
- * emitted in depth order, which yields the same list; the ranges come from each tile's
- * list length, counted from the boxes (a 2D difference array per camera). K is written to
+ * emitted in depth order, which yields the same list (with gs_tuning.big_tiles, splats
+ * covering more tiles skip the tile sort and are merged into each tile's run by depth rank,
+ * again the same list); the ranges come from each tile's list length, counted from the
+ * boxes (a 2D difference array per camera). K is written to
  * bins->counters[0]; if K exceeds bins->capacity the list is not built (every tile's
  * range is empty, so a rasterize call made before the caller looks renders nothing and
  * reads nothing from the list), counters[1] is set to 1, and the caller regrows and calls
