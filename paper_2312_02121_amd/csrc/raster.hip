@@ -169,11 +169,13 @@ __device__ __forceinline__ float alpha_raw(const RasterRec &r, double dx, double
     return __builtin_amdgcn_exp2f((float)e);
 }
 
-// Records of a staged batch that cannot reach alpha_min at any pixel of the wave are skipped
-// by both walks: for them every pixel's alpha is below alpha_min, so their step is a no-op
-// (T, the colour, the last index and every gradient sum stay unchanged). The test is made once
-// per record and batch, by the lane that gathered it, against the rectangle of the wave's
-// pixel centres.
+// Records of a batch that cannot reach alpha_min at any pixel the walk still changes are
+// skipped by both walks: for them every such pixel's alpha is below alpha_min, so their step
+// is a no-op (T, the colour, the last index and every gradient sum stay unchanged). The test
+// is made once per record and batch, by the lane that gathered it, against the rectangle of
+// the pixel centres of the lanes still active: with an unfinished pixel in the forward, with a
+// pixel whose last entry is at or after the batch's first in the backward (a finished pixel,
+// or one past its last entry, takes no step).
 struct WaveRect {
     double x_lo, x_hi, y_lo, y_hi;   // pixel centres of the wave: [x_lo, x_hi] x [y_lo, y_hi]
     double thr;                       // log2(alpha_min) less a margin
@@ -194,12 +196,39 @@ __device__ inline WaveRect wave_rect(const ItemPixels &t, const gs_params &prm)
     return w;
 }
 
-// True when the gathered record cannot reach alpha_min inside the rectangle. The exponent
+// The rectangle of the pixel centres of the lanes in `act` (a lane mask, not empty) within
+// the wave's rectangle `w`: lanes are laid out row-major, 16 / PX lanes per pixel row, each
+// with PX adjacent pixels. Scalar arithmetic on the mask only.
+template <int PX>
+__device__ inline WaveRect lanes_rect(const WaveRect &w, uint64_t act)
+{
+    constexpr int kLanesPerRow = kTile / PX;
+    uint64_t cols = act;   // fold the rows onto the first: bit c set when column c has an active lane
+#pragma unroll
+    for (int sh = 32; sh >= kLanesPerRow; sh >>= 1) cols |= cols >> sh;
+    cols &= (1ull << kLanesPerRow) - 1;
+    const int c_lo = (int)__builtin_ctzll(cols), c_hi = 63 - (int)__builtin_clzll(cols);
+    const int l_lo = (int)__builtin_ctzll(act), l_hi = 63 - (int)__builtin_clzll(act);
+    WaveRect r = w;
+    r.x_lo = w.x_lo + (double)(c_lo * PX);
+    r.x_hi = w.x_lo + (double)(c_hi * PX + PX - 1);
+    r.y_lo = w.y_lo + (double)(l_lo / kLanesPerRow);
+    r.y_hi = w.y_lo + (double)(l_hi / kLanesPerRow);
+    return r;
+}
+
+// True when the gathered record cannot reach alpha_min inside the rectangle (the pixel
+// centres of the lanes that are still active, lanes_rect). The exponent
 // lo + A dx^2 + B dx dy + C dy^2 (a concave quadratic) is at least thr only inside an ellipse
 // around mu' whose bounding box has half-widths sqrt(k (-4C) / D) and sqrt(k (-4A) / D), with
-// k = lo - thr and D = 4AC - B^2; the record is skipped when k < 0 or that box, widened by a
-// relative 2^-20 and an absolute 2^-20, misses the rectangle. Records whose D carries more
-// than 2^-20 relative cancellation, and any NaN, are kept.
+// k = lo - thr and D = 4AC - B^2. The record is skipped when k < 0, when that box, widened by
+// a relative 2^-20 and an absolute 2^-20, misses the rectangle, or when the largest exponent
+// over the rectangle is below thr: with mu' outside the rectangle that largest value lies on
+// an edge that faces mu', and on an edge the quadratic is a concave parabola whose largest
+// value is at its vertex clamped to the edge (the ellipse of a thin, tilted splat can miss a
+// rectangle its bounding box meets). The D test bounds the relative rounding of those values by about
+// 2^-32, and they are compared with a relative allowance of 2^-28. Records whose D carries
+// more than 2^-20 relative cancellation, and any NaN, are kept.
 // A float64 field of the gathered record from its two 32-bit halves (low word first).
 __device__ __forceinline__ double rec_f64(float lo_word, float hi_word)
 {
@@ -219,7 +248,22 @@ __device__ inline bool record_misses(const Gathered &g, const WaveRect &w)
     const double sx = sqrt(k * (-4.0 * C) / D) * (1.0 + 0x1p-20) + 0x1p-20;
     const double sy = sqrt(k * (-4.0 * A) / D) * (1.0 + 0x1p-20) + 0x1p-20;
     const double mx = g.q0.x, my = g.q0.y;
-    return mx + sx < w.x_lo || mx - sx > w.x_hi || my + sy < w.y_lo || my - sy > w.y_hi;
+    if (mx + sx < w.x_lo || mx - sx > w.x_hi || my + sy < w.y_lo || my - sy > w.y_hi) return true;
+    if (!(A < 0.0) || (mx >= w.x_lo && mx <= w.x_hi && my >= w.y_lo && my <= w.y_hi)) return false;
+    // only the edges that face mu' can hold the largest value (for a positive definite form
+    // the constrained maximum never lies inside an edge whose outward side points away from mu')
+    const double dx0 = w.x_lo - mx, dx1 = w.x_hi - mx, dy0 = w.y_lo - my, dy1 = w.y_hi - my;
+    auto quad = [&](double dx, double dy) { return __builtin_fma(__builtin_fma(A, dx, B * dy), dx, C * dy * dy); };
+    double best = -INFINITY;
+    if (dx0 > 0.0 || dx1 < 0.0) {   // the edge x = x_lo or x = x_hi; its vertex at dy = B dx / (-2C)
+        const double dx = dx0 > 0.0 ? dx0 : dx1;
+        best = quad(dx, fmin(fmax(B * dx * (-0.5 / C), dy0), dy1));
+    }
+    if (dy0 > 0.0 || dy1 < 0.0) {   // the edge y = y_lo or y = y_hi; its vertex at dx = B dy / (-2A)
+        const double dy = dy0 > 0.0 ? dy0 : dy1;
+        best = fmax(best, quad(fmin(fmax(B * dy * (-0.5 / A), dx0), dx1), dy));
+    }
+    return best * (1.0 - 0x1p-28) < -k;
 }
 
 // Work-list cursor of a wave: positions [pos, end) taken from the counter and not yet used.
@@ -364,19 +408,21 @@ __device__ inline int fwd_walk(const RasterRec *__restrict__ rr, const int32_t *
             snapped = true;
         }
         const int nb = min(B, t.end - b);
-        // records that miss the wave are left out of the staged batch; the counting pass
-        // (kVisited) counts every pair it reaches and keeps them all
-        const uint64_t keep = __ballot(lane < nb && (kVisited || !record_misses(next, wr)));
-        const int np = stage_packed(slice, next, keep, lane, b - t.start + lane + 1);
-        if (b + B < t.end) next = gather(rr, nid);
-        if (b + 2 * B < t.end) nid = load_ids(ids, b + 2 * B, min(B, t.end - b - 2 * B), lane);
         float tmax = ps.T[0];
 #pragma unroll
         for (int q = 1; q < PX; ++q) tmax = fmaxf(tmax, ps.T[q]);
-        if (__ballot(tmax >= 0.f) == 0) {               // every pixel of the item is finished
+        const uint64_t act = __ballot(tmax >= 0.f);     // lanes with an unfinished pixel
+        if (act == 0) {                                  // every pixel of the item is finished
             walked = b - t.start;
             break;
         }
+        // records that miss the unfinished pixels are left out of the staged batch; the
+        // counting pass (kVisited) counts every pair it reaches and keeps them all
+        const WaveRect ar = lanes_rect<PX>(wr, act);
+        const uint64_t keep = __ballot(lane < nb && (kVisited || !record_misses(next, ar)));
+        const int np = stage_packed(slice, next, keep, lane, b - t.start + lane + 1);
+        if (b + B < t.end) next = gather(rr, nid);
+        if (b + 2 * B < t.end) nid = load_ids(ids, b + 2 * B, min(B, t.end - b - 2 * B), lane);
         // whole groups of staged slots, straight-line code inside a group (constant LDS
         // offsets, no per-entry branch), with the all-finished test between groups
         RasterRec rn = slice[0];
@@ -558,11 +604,18 @@ __device__ inline void bwd_walk(const RasterRec *__restrict__ rr, const int32_t 
         const int s1 = max(lo, s0 - B);
         nid = load_ids(ids, s1, s0 - s1, lane);
     }
+    int lane_last = 0;   // the lane's pixels are active for list positions up to this one
+#pragma unroll
+    for (int q = 0; q < PX; ++q) lane_last = max(lane_last, ps.last[q]);
     for (int bend = kend; bend > lo; bend -= B) {
         const int bstart = max(lo, bend - B);
         const int nb = bend - bstart;
-        // records that miss the wave are left out of the staged batch
-        const uint64_t keep = __ballot(lane < nb && !record_misses(next, wr));
+        // records that miss the pixels active in this batch (last at or after its first
+        // entry) are left out of the staged batch; some lane is active, since kend is the
+        // largest last
+        const uint64_t act = __ballot(lane_last >= bstart - t.start + 1);
+        const WaveRect ar = lanes_rect<PX>(wr, act);
+        const uint64_t keep = __ballot(lane < nb && !record_misses(next, ar));
         const int nk = __popcll(keep);
         stepped += nk;
         stage_packed(slice, next, keep, lane, bstart - t.start + lane + 1);
