@@ -17,7 +17,8 @@
 // Records. A wave walks its list in batches of 64 entries. For each batch every lane
 // gathers one entry's 64-byte RasterRec with vector loads (64 records in flight per wave)
 // into registers, one batch ahead, so the random record reads stay off the critical path.
-// Each lane then tests its record against the rectangle of the wave's pixel centres;
+// Each lane then tests its record against the rectangle of the pixel centres of the lanes
+// still active (unfinished in the forward, not past their last entry in the backward);
 // records that cannot reach alpha_min there are dropped, and the rest are staged packed,
 // in list order, into the wave's own LDS slice (the forward pads them to a multiple of 8
 // with null records and composites groups of 8 as straight-line code). The walk reads each
