@@ -190,6 +190,28 @@ def test_forward_image(name):
     assert flagged <= flag_budget(pixels)
 
 
+@pytest.mark.parametrize("tuning", [{}, {"split_len": 32, "split_parts": 4}, {"split_len": 32, "split_parts": 2}])
+@pytest.mark.parametrize("name", ["tiny_tilted", "c2_20k", "dense_small"])
+def test_skipped_records_change_nothing(name, tuning):
+    """The walks leave out records that cannot reach alpha_min at the pixels still active
+    (their rectangle, the exact largest exponent over it). The forward that counts visits
+    keeps every record, so the two forwards must agree bit for bit on image, T_final and
+    last, for whole tiles and for halves and quarters of split tiles."""
+    _print_case("skip_exact", wl=name, **tuning)
+    from paper_2312_02121_amd import autotune
+    wl = wl_cache()[name]
+    autotune.apply({**autotune.default_tuning(), **tuning})
+    try:
+        r_all, _ = gpu_forward(wl, keep_visited=True)
+        r_skip, _ = gpu_forward(wl, keep_visited=False)
+    finally:
+        autotune.apply(autotune.default_tuning())
+    assert r_skip.visited is None and r_all.visited is not None
+    assert torch.equal(r_skip.image, r_all.image)
+    assert torch.equal(r_skip.T_final, r_all.T_final)
+    assert torch.equal(r_skip.last, r_all.last)
+
+
 def _backward_compare(wl, r, st, seed=0, with_pose=False, prm=None):
     rng = np.random.default_rng(seed)
     cams = r.cams
