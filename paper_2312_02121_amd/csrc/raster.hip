@@ -863,7 +863,7 @@ struct FusedIO {
 template <int PX, int B>
 __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_t *__restrict__ ids,
                                   const ItemPixels &t, const gs_params &prm, const FusedIO &io, const BwdOut &out,
-                                  int seg, int segs, int32_t *sched, int n_tiles, int item)
+                                  int seg, int segs, int32_t *sched, int n_tiles, int item, float &loss_acc)
 {
     // segment seg of segs: list positions [lo, hi), boundaries at multiples of 64 entries
     const int n = t.end - t.start;
@@ -900,10 +900,7 @@ __device__ inline void fused_item(const RasterRec *__restrict__ rr, const int32_
             }
         }
     }
-    if (io.loss && seg == 0) {
-        l2 = wave_sum_to_lane63(l2);
-        if ((threadIdx.x & (kWave - 1)) == kWave - 1) atomic_add_f32(io.loss, l2);
-    }
+    if (seg == 0) loss_acc += l2;   // summed over the wave's items, added to the loss once per wave
     // the walk back over [lo, hi) starts from the state after entry hi - 1: for the last
     // segment T_final and only the background behind (weight T_final); otherwise the
     // snapshot, with the colour added from hi on carried by gS = dL/dC . (C_final - C(hi))
@@ -940,6 +937,9 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
     const int parts = __builtin_amdgcn_readfirstlane(sched[kSchedParts]);
     const int segs = __builtin_amdgcn_readfirstlane(sched[kSchedSegs]);
     ItemCursor cur = first_cursor(grab);
+    // this lane's share of the loss over the wave's items: one atomic per wave at the end, since
+    // one per item queues on the loss's address once the items are short (the list's end)
+    float loss_acc = 0.f;
     for (;;) {
         const int item = next_item(sched, kSchedFused, n_items, grab, cur, lane, n_tiles);
         if (item < 0) break;
@@ -948,17 +948,21 @@ __global__ __launch_bounds__(kWave * kBlockWaves) __attribute__((amdgpu_waves_pe
             if (prio) set_priority(3);
             if (parts == 4)
                 fused_item<1, B>(rr, ids, item_pixels<1>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
-                              sched, n_tiles, item);
+                              sched, n_tiles, item, loss_acc);
             else
                 fused_item<2, B>(rr, ids, item_pixels<2>(cams, n_cams, ranges, item, lane), prm, io, out, seg, segs,
-                              sched, n_tiles, item);
+                              sched, n_tiles, item, loss_acc);
             __builtin_amdgcn_s_setprio(0);
         } else {
             set_priority(__builtin_amdgcn_readfirstlane(walk_priority(ranges, sched, n_tiles, item, prio_len)));
             fused_item<4, B>(rr, ids, item_pixels<4>(cams, n_cams, ranges, item, lane), prm, io, out, 0, 1, sched,
-                          n_tiles, item);
+                          n_tiles, item, loss_acc);
             __builtin_amdgcn_s_setprio(0);
         }
+    }
+    if (io.loss) {
+        const float l2 = wave_sum_to_lane63(loss_acc);
+        if (lane == kWave - 1 && l2 != 0.f) atomic_add_f32(io.loss, l2);   // a NaN is added too
     }
 }
 
