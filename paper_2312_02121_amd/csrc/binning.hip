@@ -1343,106 +1343,127 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
     }
 }
 
-// Blocks of big_len take kBigGroup consecutive tiles; per camera among them, its big splats'
-// boxes pass through LDS kBigStage at a time and each wave tests its tiles (tile t of a
-// camera's part of the group to wave (t - first) mod 4) against them.
-constexpr int kBigGroup = 64;
-constexpr int kBigStage = 1024;
-constexpr int kBigUnroll = 4;   // boxes per lane in flight
-
-// Copies boxes k0 .. k0 + m - 1 into LDS, four per thread, loads issued first.
-__device__ inline void stage_boxes(uint2 *sbox, const uint2 *__restrict__ box, int64_t k0, int m)
+// One block per camera: its big splats' boxes (clipped to its grid) go into an LDS difference
+// array over its tile grid, in bands of rows of at most kCountLds cells (a box enters a band
+// at its first row inside it), and 2D prefix sums (a wave scans a row, then a column) give
+// the number of boxes containing each tile: kept in big_len and added to the tile's list
+// length. The same count as testing every tile against every box, in four LDS atomics per
+// box and band.
+__global__ __launch_bounds__(kCountBlock) void big_len_kernel(const gs_camera *__restrict__ cams, int n_cams,
+                                                              const int64_t *__restrict__ words,
+                                                              const uint2 *__restrict__ big_box,
+                                                              int32_t *__restrict__ cnt, int32_t *__restrict__ big_len,
+                                                              const int64_t *__restrict__ err_flag)
 {
-    static_assert(kBigStage == 4 * 256, "four boxes per thread");
-    uint2 b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int x = (int)threadIdx.x + u * 256;
-        b[u] = x < m ? box[k0 + x] : kEmptyBox;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int x = (int)threadIdx.x + u * 256;
-        if (x < m) sbox[x] = b[u];
-    }
-}
-
-// The number of its camera's big splats whose box contains each tile: kept in big_len and
-// added to the tile's list length.
-__global__ __launch_bounds__(256) void big_len_kernel(const gs_camera *__restrict__ cams, int n_cams, int n_tiles,
-                                                      const int64_t *__restrict__ words,
-                                                      const uint2 *__restrict__ big_box, int32_t *__restrict__ cnt,
-                                                      int32_t *__restrict__ big_len,
-                                                      const int64_t *__restrict__ err_flag)
-{
-    __shared__ uint2 sbox[kBigStage];
-    __shared__ int scount[kBigGroup];
+    __shared__ int cells[kCountLds];
+    constexpr int kWaves = kCountBlock / kWave;
     if (!words[kBigOk] || *err_flag) return;   // uniform
-    const int g0 = blockIdx.x * kBigGroup, g1 = min(n_tiles, g0 + kBigGroup);
-    if (g0 >= n_tiles) return;
+    const int c = blockIdx.x;
+    if (c >= n_cams) return;
+    const int W = cams[c].tiles_x, H = cams[c].tiles_y, toff = cams[c].tile_offset;
+    if (W < 1 || H < 1 || W > kCountLds) return;   // uniform; tile_count_kernel reports a grid too wide
+    const int64_t b0 = words[kBigCamStart + c], b1 = words[kBigCamStart + c + 1];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    if (threadIdx.x < kBigGroup) scount[threadIdx.x] = 0;
-    const int c_first = camera_of_tile(cams, n_cams, g0), c_last = camera_of_tile(cams, n_cams, g1 - 1);
-    for (int c = c_first; c <= c_last; ++c) {
-        const int toff = cams[c].tile_offset, tw = max(cams[c].tiles_x, 1);
-        const int t0 = max(g0, toff), t1 = min(g1, toff + cams[c].tiles_x * cams[c].tiles_y);
-        const int64_t b0 = words[kBigCamStart + c], b1 = words[kBigCamStart + c + 1];
-        if (t0 >= t1) continue;   // uniform
-        for (int64_t k0 = b0; k0 < b1; k0 += kBigStage) {
-            const int m = (int)min((int64_t)kBigStage, b1 - k0);
-            __syncthreads();   // the previous stage's reads have ended
-            stage_boxes(sbox, big_box, k0, m);
-            __syncthreads();
-            for (int t = t0 + wave; t < t1; t += 256 / kWave) {
-                const int local = t - toff, tx = local % tw, ty = local / tw;
-                int n = 0;
-                for (int x0 = 0; x0 < m; x0 += kBigUnroll * kWave) {
-                    uint2 b[kBigUnroll];
-#pragma unroll
-                    for (int u = 0; u < kBigUnroll; ++u) {
-                        const int x = x0 + u * kWave + lane;
-                        b[u] = x < m ? sbox[x] : kEmptyBox;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kBigUnroll; ++u) n += box_holds(b[u], tx, ty) ? 1 : 0;
-                }
-#pragma unroll
-                for (int o = kWave / 2; o >= 1; o >>= 1) n += __shfl_xor(n, o, kWave);
-                if (lane == 0) scount[t - g0] += n;
+    const int band = kCountLds / W;
+    for (int yb = 0; yb < H; yb += band) {
+        const int rows = min(band, H - yb), n = rows * W;
+        for (int i = threadIdx.x; i < n; i += kCountBlock) cells[i] = 0;
+        __syncthreads();
+        for (int64_t k = b0 + threadIdx.x; k < b1; k += kCountBlock) {
+            const uint2 b = big_box[k];
+            const int x0 = (int)(b.x & 0xffff), x1 = min((int)(b.y & 0xffff), W - 1);
+            const int y0 = max((int)(b.x >> 16), yb), y1 = min((int)(b.y >> 16), H - 1);
+            if (x0 > x1 || y0 > y1 || y0 >= yb + rows) continue;   // no tile of this band
+            const int r0 = y0 - yb, r1 = y1 + 1 - yb;
+            atomicAdd(&cells[r0 * W + x0], 1);
+            if (x1 + 1 < W) atomicAdd(&cells[r0 * W + x1 + 1], -1);
+            if (r1 < rows) {
+                atomicAdd(&cells[r1 * W + x0], -1);
+                if (x1 + 1 < W) atomicAdd(&cells[r1 * W + x1 + 1], 1);
             }
         }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < g1 - g0) {
-        const int n = scount[threadIdx.x];
-        big_len[g0 + threadIdx.x] = n;
-        cnt[g0 + threadIdx.x] += n;
+        __syncthreads();
+        for (int r = wave; r < rows; r += kWaves) {
+            int carry = 0;
+            for (int x0 = 0; x0 < W; x0 += kWave) {
+                const int x = x0 + lane;
+                const int v = wave_inclusive_scan(x < W ? cells[r * W + x] : 0) + carry;
+                if (x < W) cells[r * W + x] = v;
+                carry = __shfl(v, kWave - 1, kWave);
+            }
+        }
+        __syncthreads();
+        for (int x = wave; x < W; x += kWaves) {
+            int carry = 0;
+            for (int r0 = 0; r0 < rows; r0 += kWave) {
+                const int r = r0 + lane;
+                const int v = wave_inclusive_scan(r < rows ? cells[r * W + x] : 0) + carry;
+                if (r < rows) cells[r * W + x] = v;
+                carry = __shfl(v, kWave - 1, kWave);
+            }
+        }
+        __syncthreads();
+        const int64_t t0 = toff + (int64_t)yb * W;
+        for (int i = threadIdx.x; i < n; i += kCountBlock) {
+            const int v = cells[i];
+            big_len[t0 + i] = v;
+            if (v) cnt[t0 + i] += v;
+        }
+        __syncthreads();   // the next band clears the cells
     }
 }
 
 constexpr int kMergeBlock = 256;
-constexpr int kMergeA = 1024;       // small-run entries a wave holds in LDS
-constexpr int kMergeUnroll = 4;     // searches per lane that proceed together
+constexpr int kMergeWaves = kMergeBlock / kWave;   // tiles per block, one per wave
+constexpr int kMergeRing = 512;     // small entries (rank, slot) a wave holds in LDS, as a ring
+constexpr int kMergeFill = 256;     // small entries one refill stages
+constexpr int kMergeUnroll = 4;     // chunks of big splats whose loads are issued together
+constexpr int kMergeLoop = 16;      // groups of up to this many small entries: one ballot per entry
 
-// Count of the ascending values get(0 .. n - 1) below v, by binary lifting (the largest p
-// with get(p - 1) < v): the same steps for every v, so kMergeUnroll searches of a thread run
-// in lock step with their loads issued together (indices clamped into the run).
-template <typename Get>
-__device__ inline void count_below_x4(Get get, int n, const int32_t (&v)[kMergeUnroll], int (&pos)[kMergeUnroll])
+// The LDS of one merge wave: the ring of staged small entries, and for a group of more than
+// kMergeLoop small entries, the chunk's big ranks and the group's small ranks.
+struct MergeLds {
+    int2 ring[kMergeRing];   // small entry i (rank, slot) at i mod kMergeRing
+    int32_t big[kWave];
+    int32_t grp[kWave];
+};
+
+// Stages the small entries [w_hi, w_hi + kMergeFill) below na: ranks from the tile's small
+// run A, slots from rank_ids. Called only when w_hi - p < kWave (p: entries placed), so the
+// staged entries not yet placed, at most kWave + kMergeFill <= kMergeRing, stay in the ring.
+__device__ __forceinline__ void merge_fill(MergeLds &L, const int32_t *__restrict__ A, const int32_t *__restrict__ rank_ids,
+                                  int64_t V, int na, int &w_hi)
 {
-    const int top = n > 0 ? 1 << (31 - __clz(n)) : 0;
+    constexpr int kPer = kMergeFill / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t r[kPer], s[kPer];
 #pragma unroll
-    for (int u = 0; u < kMergeUnroll; ++u) pos[u] = 0;
-    for (int step = top; step > 0; step >>= 1) {
-        int32_t o[kMergeUnroll];
-#pragma unroll
-        for (int u = 0; u < kMergeUnroll; ++u) o[u] = get(min(pos[u] + step, n) - 1);
-#pragma unroll
-        for (int u = 0; u < kMergeUnroll; ++u) {
-            const int p = pos[u] + step;
-            pos[u] = (p <= n && o[u] < v[u]) ? p : pos[u];
-        }
+    for (int u = 0; u < kPer; ++u) {
+        const int i = w_hi + u * kWave + lane;
+        r[u] = i < na ? A[i] : 0;
     }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = w_hi + u * kWave + lane;
+        s[u] = i < na ? rank_ids[(int64_t)(uint32_t)r[u] < V ? r[u] : 0] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = w_hi + u * kWave + lane;
+        if (i < na) L.ring[i & (kMergeRing - 1)] = make_int2(r[u], s[u]);
+    }
+    w_hi = min(na, w_hi + kMergeFill);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Count of the values of an ascending array of kWave below x (binary lifting over 0 .. 62,
+// then entry q itself).
+__device__ __forceinline__ int count_below64(const int32_t *arr, int32_t x)
+{
+    int q = 0;
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1) q = arr[q + step - 1] < x ? q + step : q;
+    return arr[q] < x ? q + 1 : q;
 }
 
 // Writes list entry `at` (below `end`, the tile's range end; always, when the counts agree).
@@ -1456,21 +1477,19 @@ __device__ inline void put_entry(int64_t at, int64_t end, int32_t id, int t, int
                      (uint64_t)((uint64_t)(uint32_t)id < (uint64_t)n_splats ? __float_as_uint(depth[id]) : 0u);
 }
 
-constexpr int kMergeWaves = kMergeBlock / kWave;   // tiles per block, one per wave
-
-// The walk of merge_kernel for one tile, with the small run read through small_at (the
-// wave's LDS copy, or the run itself when it is longer than kMergeA).
-template <typename SmallAt>
-__device__ inline void merge_walk(SmallAt small_at, int na, int32_t *sChunk, int t, int tx, int ty, int64_t start,
-                                  int64_t end, int64_t b0, int n_cam, const int32_t *__restrict__ big_rank,
-                                  const int32_t *__restrict__ big_slot, const uint2 *__restrict__ big_box,
-                                  const int32_t *__restrict__ rank_ids, int64_t V, int32_t *__restrict__ ids,
-                                  uint64_t *__restrict__ keys64, const float *__restrict__ depth, int64_t n_splats,
-                                  int nb, int64_t *__restrict__ err_flag)
+// The walk of merge_kernel for one tile.
+__device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restrict__ A, int na, int t, int tx, int ty,
+                                  int64_t start, int64_t end, int64_t b0, int n_cam,
+                                  const int32_t *__restrict__ big_rank, const int32_t *__restrict__ big_slot,
+                                  const uint2 *__restrict__ big_box, const int32_t *__restrict__ rank_ids, int64_t V,
+                                  int32_t *__restrict__ ids, uint64_t *__restrict__ keys64,
+                                  const float *__restrict__ depth, int64_t n_splats, int nb,
+                                  int64_t *__restrict__ err_flag)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    int j = 0;   // contained big splats placed so far
-    int p = 0;   // small entries placed so far
+    int j = 0;      // contained big splats placed so far
+    int p = 0;      // small entries placed so far
+    int w_hi = 0;   // small entries staged so far (p <= w_hi)
     const int n_chunks = (n_cam + kWave - 1) / kWave;
     for (int c0 = 0; c0 < n_chunks; c0 += kMergeUnroll) {
         bool in[kMergeUnroll];
@@ -1484,47 +1503,56 @@ __device__ inline void merge_walk(SmallAt small_at, int na, int32_t *sChunk, int
             rk[u] = ok ? big_rank[kc] : INT32_MAX;
             sl[u] = big_slot[kc];
         }
-        int below[kMergeUnroll];
-        count_below_x4(small_at, na, rk, below);
 #pragma unroll
         for (int u = 0; u < kMergeUnroll; ++u) {
             if (c0 + u >= n_chunks) break;   // uniform
             const uint64_t m = __ballot(in[u]);
-            if (in[u])
-                put_entry(start + j + __popcll(m & lanemask_lt()) + below[u], end, sl[u], t, ids, keys64, depth,
-                          n_splats);
-            // the small entries below this chunk's last rank
             const int last_lane = min(n_cam - 1 - (c0 + u) * kWave, kWave - 1);
-            const int32_t hi = __shfl(rk[u], last_lane, kWave);
-            sChunk[lane] = rk[u];   // ascending; INT32_MAX past the camera's last big splat
-            __builtin_amdgcn_wave_barrier();
-            while (true) {   // wave-uniform
+            const int32_t hi = __builtin_amdgcn_readlane(rk[u], last_lane);   // the chunk's last rank
+            const int p0 = p;
+            int below = 0;   // small entries placed with this chunk that rank below rk[u]
+            bool big_staged = false;
+            while (p < na) {   // wave-uniform: the next small entries below hi, kWave at a time
+                if (w_hi < na && w_hi < p + kWave) merge_fill(L, A, rank_ids, V, na, w_hi);
                 const int i = p + lane;
-                const int32_t v = i < na ? small_at(i) : INT32_MAX;
-                const bool here = i < na && v < hi;
+                const int2 e = i < na ? L.ring[i & (kMergeRing - 1)] : make_int2(INT32_MAX, 0);
+                const bool here = e.x < hi;   // lanes 0 .. cnt - 1 (the run ascends)
                 const int cnt = __popcll(__ballot(here));
-                if (here) {
-                    // q = this chunk's ranks below v (at most last_lane, as v < hi): binary
-                    // lifting over lanes 0 .. 62, then lane q itself
-                    int q = 0;
-#pragma unroll
-                    for (int step = kWave / 2; step > 0; step >>= 1) q = sChunk[q + step - 1] < v ? q + step : q;
-                    q = sChunk[q] < v ? q + 1 : q;
-                    q = min(q, kWave - 1);
-                    put_entry(start + i + j + __popcll(m & ((1ull << q) - 1)), end,
-                              rank_ids[(int64_t)(uint32_t)v < V ? v : 0], t, ids, keys64, depth, n_splats);
+                if (cnt == 0) break;
+                int q = 0;   // of a small lane: the contained big splats of this chunk below it
+                if (cnt <= kMergeLoop) {   // uniform: one ballot per small entry
+                    for (int s = 0; s < cnt; ++s) {
+                        const int32_t vs = __builtin_amdgcn_readlane(e.x, s);
+                        const bool lo = rk[u] < vs;
+                        const int qs = __popcll(__ballot(lo) & m);
+                        below += lo ? 0 : 1;
+                        q = lane == s ? qs : q;
+                    }
+                } else {   // binary lifting, each side over the other's ranks in LDS
+                    if (!big_staged) {
+                        L.big[lane] = rk[u];   // ascending; INT32_MAX past the camera's last big splat
+                        big_staged = true;
+                    }
+                    L.grp[lane] = here ? e.x : INT32_MAX;
+                    __builtin_amdgcn_wave_barrier();
+                    below += count_below64(L.grp, rk[u]);
+                    if (here) q = __popcll(m & ((1ull << count_below64(L.big, e.x)) - 1));   // below hi: < 64
+                    __builtin_amdgcn_wave_barrier();   // grp is rewritten by the next group
                 }
+                if (here) put_entry(start + i + j + q, end, e.y, t, ids, keys64, depth, n_splats);
                 p += cnt;
                 if (cnt < kWave) break;
             }
-            __builtin_amdgcn_wave_barrier();   // sChunk is rewritten by the next chunk
+            if (in[u]) put_entry(start + p0 + below + j + __popcll(m & lanemask_lt()), end, sl[u], t, ids, keys64,
+                                 depth, n_splats);
             j += __popcll(m);
         }
     }
     // the rest of the small run lies above every big rank
-    for (int i = p + lane; i < na; i += kWave) {
-        const int32_t v = small_at(i);
-        put_entry(start + i + j, end, rank_ids[(int64_t)(uint32_t)v < V ? v : 0], t, ids, keys64, depth, n_splats);
+    for (; p < na; p += kWave) {
+        if (w_hi < na && w_hi < p + kWave) merge_fill(L, A, rank_ids, V, na, w_hi);
+        const int i = p + lane;
+        if (i < na) put_entry(start + i + j, end, L.ring[i & (kMergeRing - 1)].y, t, ids, keys64, depth, n_splats);
     }
     if (lane == 0 && j != nb)   // unreachable: big_len counted the same boxes
         __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1533,14 +1561,15 @@ __device__ inline void merge_walk(SmallAt small_at, int na, int32_t *sChunk, int
 // One wave per tile: its list is the merge, by depth rank, of its small run (the tile-sorted
 // small entries, ranks, at svals[ranges[t].start - big_before[t]]) and its big run (its
 // camera's big splats whose box contains the tile, in rank order); ranks are distinct. The
-// wave walks its camera's big splats in rank order, 64 at a time (one per lane): a contained
-// one goes to start + (contained ones before it) + (small ranks below it). After each chunk,
-// the small entries below the chunk's last rank that are not yet placed (the next ones of the
-// small run, found by a ballot) go to start + i + (contained big ranks below them): the
-// contained ones of earlier chunks plus those of this chunk's lanes below them. What is left
-// of the small run after the last chunk lies above every big rank. The small run is read
-// from the wave's LDS when it fits. Entry = slot; the key (tile << 32 | depth bits) only when
-// asked for. No block barriers: the waves share nothing.
+// wave walks its camera's big splats in rank order, 64 at a time (one per lane). Per such
+// chunk, the small entries not yet placed that rank below the chunk's last rank (the next
+// ones of the small run, found by a ballot, up to 64 at a time) are placed: entry i goes to
+// start + i + (contained big splats of earlier chunks) + (those of this chunk below it), and
+// each big lane counts those below its rank; then a contained big splat goes to start +
+// (small entries below it) + (contained big splats before it). What is left of the small
+// run after the last chunk lies above every big rank. The small run passes through a ring in
+// the wave's LDS, with each entry's slot fetched when it is staged. Entry = slot; the key
+// (tile << 32 | depth bits) only when asked for. No block barriers: the waves share nothing.
 __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__restrict__ cams, int n_cams,
                                                             int n_tiles, const int64_t *__restrict__ words,
                                                             const int32_t *__restrict__ ranges,
@@ -1556,10 +1585,9 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
                                                             const float *__restrict__ depth, int64_t n_splats,
                                                             int64_t *__restrict__ err_flag)
 {
-    __shared__ int32_t sA_all[kMergeWaves][kMergeA];
-    __shared__ int32_t sChunk_all[kMergeWaves][kWave];
+    __shared__ MergeLds lds[kMergeWaves];
     if (!words[kBigOk] || *err_flag) return;   // uniform
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int wave = threadIdx.x / kWave;
     const int t = (int)(blockIdx.x * kMergeWaves + wave);
     if (t >= n_tiles) return;   // wave-uniform; the waves of a block share no barrier
     const int64_t start = ranges[2 * t], n = (int64_t)ranges[2 * t + 1] - start, end = start + n;
@@ -1568,29 +1596,16 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
     const int64_t k_small = words[kBigEffSmall], V = *vcount;
     const int64_t ss = start - big_before[t];
     if (na < 0 || ss < 0 || ss + na > k_small) {   // unreachable when the counts agree
-        if (lane == 0) __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    const int32_t *A = svals + ss;
     const int cam = camera_of_tile(cams, n_cams, t);
     const int local = t - cams[cam].tile_offset, tw = max(cams[cam].tiles_x, 1), tx = local % tw, ty = local / tw;
     const int64_t b0 = words[kBigCamStart + cam];
     const int n_cam = (int)(words[kBigCamStart + cam + 1] - b0);
-    if (na <= kMergeA) {   // wave-uniform: the small run in the wave's LDS
-        for (int x0 = lane; x0 < na; x0 += kWave * 8) {
-            int32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = A[min(x0 + u * kWave, na - 1)];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (x0 + u * kWave < na) sA_all[wave][x0 + u * kWave] = v[u];
-        }
-        merge_walk([&](int i) { return sA_all[wave][i]; }, na, sChunk_all[wave], t, tx, ty, start, end, b0, n_cam,
-                   big_rank, big_slot, big_box, rank_ids, V, ids, keys64, depth, n_splats, nb, err_flag);
-    } else {
-        merge_walk([&](int i) { return A[i]; }, na, sChunk_all[wave], t, tx, ty, start, end, b0, n_cam, big_rank,
-                   big_slot, big_box, rank_ids, V, ids, keys64, depth, n_splats, nb, err_flag);
-    }
+    merge_walk(lds[wave], svals + ss, na, t, tx, ty, start, end, b0, n_cam, big_rank, big_slot, big_box, rank_ids, V,
+               ids, keys64, depth, n_splats, nb, err_flag);
 }
 
 // Zeroes a[0, na) and b[0, nb) in one launch (grid-stride; consecutive threads take
@@ -2038,9 +2053,8 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     }
     rc = check_launch("tile sort");
     if (rc != GS_OK) return rc;
-    const unsigned g_big_tiles = grid_for(bins->n_tiles, kBigGroup);
     if (big_tiles)   // the big splats' tiles join the list lengths
-        hipLaunchKernelGGL(big_len_kernel, dim3(g_big_tiles), dim3(256), 0, st, cams, (int)n_cams, bins->n_tiles,
+        hipLaunchKernelGGL(big_len_kernel, dim3((unsigned)n_cams), dim3(kCountBlock), 0, st, cams, (int)n_cams,
                            (const int64_t *)big_words, (const uint2 *)big_box, tile_cnt, big_len,
                            (const int64_t *)err);
     // 5. ranges from the list lengths, when the list was built
