@@ -1160,7 +1160,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const int32_t *__restrict__ r
 // so the merge gives exactly the order of the full sort. Steps:
 //   big_count   per chunk of ranks: big splats per camera, and the sum of their tiles;
 //   big_scan    camera-major offsets of the big splats; K = small + big entries, overflow;
-//   big_scatter the big splats per camera in rank order (rank, camera-local box);
+//   big_scatter the big splats per camera in rank order (rank, slot, camera-local box);
 //   big_len     per tile, the big splats whose box contains it (added to the tile lengths;
 //               the ranges scan also gives big_before, the big entries of earlier tiles);
 //   merge       per tile, the merge of its small run with its filtered big splats, written
@@ -1183,9 +1183,11 @@ __device__ inline uint2 pack_box(const int4 &b)
     return make_uint2((uint32_t)b.x | ((uint32_t)b.y << 16), (uint32_t)b.z | ((uint32_t)b.w << 16));
 }
 
+// (all four compares evaluated: no branches between a load and its use)
 __device__ inline bool box_holds(const uint2 &b, int tx, int ty)
 {
-    return (int)(b.x & 0xffff) <= tx && tx <= (int)(b.y & 0xffff) && (int)(b.x >> 16) <= ty && ty <= (int)(b.y >> 16);
+    return ((int)(b.x & 0xffff) <= tx) & (tx <= (int)(b.y & 0xffff)) & ((int)(b.x >> 16) <= ty) &
+           (ty <= (int)(b.y >> 16));
 }
 
 constexpr uint2 kEmptyBox = {1u, 0u};   // x0 = 1 > x1 = 0: holds no tile
@@ -1294,9 +1296,7 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
                                                                  int big_tiles, const int4 *__restrict__ rect,
                                                                  const int32_t *__restrict__ mat, int64_t stride,
                                                                  const int64_t *__restrict__ words,
-                                                                 int32_t *__restrict__ big_rank,
-                                                                 int32_t *__restrict__ big_slot,
-                                                                 uint2 *__restrict__ big_box,
+                                                                 int4 *__restrict__ big_rec,
                                                                  int64_t *__restrict__ err_flag)
 {
     __shared__ int32_t lrank[kSortChunk];
@@ -1330,12 +1330,11 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
             const int64_t pos = (int64_t)cursor[cam] + __popcll(peers & lanemask_lt());
             __builtin_amdgcn_wave_barrier();
             if (ok && pos >= 0 && pos < n_big) {   // always true when the counts agree
-                big_rank[pos] = r;
-                big_slot[pos] = slot;
                 const int4 b = rect[slot];
                 if ((uint32_t)(b.x | b.y | b.z | b.w) > 0xffffu)
                     __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                big_box[pos] = pack_box(b);
+                const uint2 pb = pack_box(b);
+                big_rec[pos] = make_int4(r, slot, (int)pb.x, (int)pb.y);
             }
             if (ok && (peers & lanemask_lt()) == 0) cursor[cam] = (int)(pos + __popcll(peers));
             __builtin_amdgcn_wave_barrier();
@@ -1351,7 +1350,7 @@ __global__ __launch_bounds__(kSortBlock) void big_scatter_kernel(const int32_t *
 // box and band.
 __global__ __launch_bounds__(kCountBlock) void big_len_kernel(const gs_camera *__restrict__ cams, int n_cams,
                                                               const int64_t *__restrict__ words,
-                                                              const uint2 *__restrict__ big_box,
+                                                              const int4 *__restrict__ big_rec,
                                                               int32_t *__restrict__ cnt, int32_t *__restrict__ big_len,
                                                               const int64_t *__restrict__ err_flag)
 {
@@ -1370,7 +1369,8 @@ __global__ __launch_bounds__(kCountBlock) void big_len_kernel(const gs_camera *_
         for (int i = threadIdx.x; i < n; i += kCountBlock) cells[i] = 0;
         __syncthreads();
         for (int64_t k = b0 + threadIdx.x; k < b1; k += kCountBlock) {
-            const uint2 b = big_box[k];
+            const int4 rec = big_rec[k];
+            const uint2 b = make_uint2((uint32_t)rec.z, (uint32_t)rec.w);
             const int x0 = (int)(b.x & 0xffff), x1 = min((int)(b.y & 0xffff), W - 1);
             const int y0 = max((int)(b.x >> 16), yb), y1 = min((int)(b.y >> 16), H - 1);
             if (x0 > x1 || y0 > y1 || y0 >= yb + rows) continue;   // no tile of this band
@@ -1429,8 +1429,9 @@ struct MergeLds {
 };
 
 // Stages the small entries [w_hi, w_hi + kMergeFill) below na: ranks from the tile's small
-// run A, slots from rank_ids. Called only when w_hi - p < kWave (p: entries placed), so the
-// staged entries not yet placed, at most kWave + kMergeFill <= kMergeRing, stay in the ring.
+// run A, slots from rank_ids. Called only when w_hi < na and w_hi - p < kWave (p: entries
+// placed), so the staged entries not yet placed, at most kWave + kMergeFill <= kMergeRing,
+// stay in the ring.
 __device__ __forceinline__ void merge_fill(MergeLds &L, const int32_t *__restrict__ A, const int32_t *__restrict__ rank_ids,
                                   int64_t V, int na, int &w_hi)
 {
@@ -1438,15 +1439,9 @@ __device__ __forceinline__ void merge_fill(MergeLds &L, const int32_t *__restric
     const int lane = threadIdx.x & (kWave - 1);
     int32_t r[kPer], s[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int i = w_hi + u * kWave + lane;
-        r[u] = i < na ? A[i] : 0;
-    }
+    for (int u = 0; u < kPer; ++u) r[u] = A[min(w_hi + u * kWave + lane, na - 1)];   // w_hi < na
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int i = w_hi + u * kWave + lane;
-        s[u] = i < na ? rank_ids[(int64_t)(uint32_t)r[u] < V ? r[u] : 0] : 0;
-    }
+    for (int u = 0; u < kPer; ++u) s[u] = rank_ids[(int64_t)(uint32_t)r[u] < V ? r[u] : 0];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int i = w_hi + u * kWave + lane;
@@ -1466,11 +1461,12 @@ __device__ __forceinline__ int count_below64(const int32_t *arr, int32_t x)
     return arr[q] < x ? q + 1 : q;
 }
 
-// Writes list entry `at` (below `end`, the tile's range end; always, when the counts agree).
-__device__ inline void put_entry(int64_t at, int64_t end, int32_t id, int t, int32_t *__restrict__ ids,
+// Writes entry `at` of a tile's range (ids and keys64 point at its start; below n, its
+// length, always when the counts agree).
+__device__ inline void put_entry(int at, int n, int32_t id, int t, int32_t *__restrict__ ids,
                                  uint64_t *__restrict__ keys64, const float *__restrict__ depth, int64_t n_splats)
 {
-    if (at >= end) return;
+    if (at >= n) return;
     ids[at] = id;
     if (keys64)
         keys64[at] = ((uint64_t)(uint32_t)t << 32) |
@@ -1479,9 +1475,8 @@ __device__ inline void put_entry(int64_t at, int64_t end, int32_t id, int t, int
 
 // The walk of merge_kernel for one tile.
 __device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restrict__ A, int na, int t, int tx, int ty,
-                                  int64_t start, int64_t end, int64_t b0, int n_cam,
-                                  const int32_t *__restrict__ big_rank, const int32_t *__restrict__ big_slot,
-                                  const uint2 *__restrict__ big_box, const int32_t *__restrict__ rank_ids, int64_t V,
+                                  int n, int64_t b0, int n_cam,
+                                  const int4 *__restrict__ big_rec, const int32_t *__restrict__ rank_ids, int64_t V,
                                   int32_t *__restrict__ ids, uint64_t *__restrict__ keys64,
                                   const float *__restrict__ depth, int64_t n_splats, int nb,
                                   int64_t *__restrict__ err_flag)
@@ -1492,16 +1487,18 @@ __device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restric
     int w_hi = 0;   // small entries staged so far (p <= w_hi)
     const int n_chunks = (n_cam + kWave - 1) / kWave;
     for (int c0 = 0; c0 < n_chunks; c0 += kMergeUnroll) {
+        // every load of the group issued before any is used
+        int4 rec[kMergeUnroll];
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) rec[u] = big_rec[b0 + min((c0 + u) * kWave + lane, n_cam - 1)];
         bool in[kMergeUnroll];
         int32_t rk[kMergeUnroll], sl[kMergeUnroll];
 #pragma unroll
         for (int u = 0; u < kMergeUnroll; ++u) {
-            const int k = (c0 + u) * kWave + lane;
-            const bool ok = k < n_cam;
-            const int64_t kc = b0 + (ok ? k : 0);
-            in[u] = ok && box_holds(big_box[kc], tx, ty);
-            rk[u] = ok ? big_rank[kc] : INT32_MAX;
-            sl[u] = big_slot[kc];
+            const bool ok = (c0 + u) * kWave + lane < n_cam;
+            in[u] = ok & box_holds(make_uint2((uint32_t)rec[u].z, (uint32_t)rec[u].w), tx, ty);
+            rk[u] = ok ? rec[u].x : INT32_MAX;
+            sl[u] = rec[u].y;
         }
 #pragma unroll
         for (int u = 0; u < kMergeUnroll; ++u) {
@@ -1523,9 +1520,9 @@ __device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restric
                 if (cnt <= kMergeLoop) {   // uniform: one ballot per small entry
                     for (int s = 0; s < cnt; ++s) {
                         const int32_t vs = __builtin_amdgcn_readlane(e.x, s);
-                        const bool lo = rk[u] < vs;
-                        const int qs = __popcll(__ballot(lo) & m);
-                        below += lo ? 0 : 1;
+                        const bool gt = rk[u] > vs;   // ranks are distinct; INT32_MAX past the last
+                        below += gt;
+                        const int qs = __popcll(m & ~__ballot(gt));
                         q = lane == s ? qs : q;
                     }
                 } else {   // binary lifting, each side over the other's ranks in LDS
@@ -1539,12 +1536,12 @@ __device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restric
                     if (here) q = __popcll(m & ((1ull << count_below64(L.big, e.x)) - 1));   // below hi: < 64
                     __builtin_amdgcn_wave_barrier();   // grp is rewritten by the next group
                 }
-                if (here) put_entry(start + i + j + q, end, e.y, t, ids, keys64, depth, n_splats);
+                if (here) put_entry(i + j + q, n, e.y, t, ids, keys64, depth, n_splats);
                 p += cnt;
                 if (cnt < kWave) break;
             }
-            if (in[u]) put_entry(start + p0 + below + j + __popcll(m & lanemask_lt()), end, sl[u], t, ids, keys64,
-                                 depth, n_splats);
+            if (in[u]) put_entry(p0 + below + j + __popcll(m & lanemask_lt()), n, sl[u], t, ids, keys64, depth,
+                                 n_splats);
             j += __popcll(m);
         }
     }
@@ -1552,7 +1549,7 @@ __device__ __forceinline__ void merge_walk(MergeLds &L, const int32_t *__restric
     for (; p < na; p += kWave) {
         if (w_hi < na && w_hi < p + kWave) merge_fill(L, A, rank_ids, V, na, w_hi);
         const int i = p + lane;
-        if (i < na) put_entry(start + i + j, end, L.ring[i & (kMergeRing - 1)].y, t, ids, keys64, depth, n_splats);
+        if (i < na) put_entry(i + j, n, L.ring[i & (kMergeRing - 1)].y, t, ids, keys64, depth, n_splats);
     }
     if (lane == 0 && j != nb)   // unreachable: big_len counted the same boxes
         __hip_atomic_store(err_flag, (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1575,9 +1572,7 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
                                                             const int32_t *__restrict__ ranges,
                                                             const int32_t *__restrict__ big_len,
                                                             const int32_t *__restrict__ big_before,
-                                                            const int32_t *__restrict__ big_rank,
-                                                            const int32_t *__restrict__ big_slot,
-                                                            const uint2 *__restrict__ big_box,
+                                                            const int4 *__restrict__ big_rec,
                                                             const int32_t *__restrict__ svals,
                                                             const int32_t *__restrict__ rank_ids,
                                                             const int64_t *__restrict__ vcount,
@@ -1587,10 +1582,10 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
 {
     __shared__ MergeLds lds[kMergeWaves];
     if (!words[kBigOk] || *err_flag) return;   // uniform
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // uniform: scalar tile state
     const int t = (int)(blockIdx.x * kMergeWaves + wave);
     if (t >= n_tiles) return;   // wave-uniform; the waves of a block share no barrier
-    const int64_t start = ranges[2 * t], n = (int64_t)ranges[2 * t + 1] - start, end = start + n;
+    const int64_t start = ranges[2 * t], n = (int64_t)ranges[2 * t + 1] - start;
     if (n <= 0) return;
     const int nb = big_len[t], na = (int)n - nb;
     const int64_t k_small = words[kBigEffSmall], V = *vcount;
@@ -1604,8 +1599,8 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(const gs_camera *__r
     const int local = t - cams[cam].tile_offset, tw = max(cams[cam].tiles_x, 1), tx = local % tw, ty = local / tw;
     const int64_t b0 = words[kBigCamStart + cam];
     const int n_cam = (int)(words[kBigCamStart + cam + 1] - b0);
-    merge_walk(lds[wave], svals + ss, na, t, tx, ty, start, end, b0, n_cam, big_rank, big_slot, big_box, rank_ids, V,
-               ids, keys64, depth, n_splats, nb, err_flag);
+    merge_walk(lds[wave], svals + ss, na, t, tx, ty, (int)n, b0, n_cam, big_rec, rank_ids, V, ids + start,
+               keys64 ? keys64 + start : keys64, depth, n_splats, nb, err_flag);
 }
 
 // Zeroes a[0, na) and b[0, nb) in one launch (grid-stride; consecutive threads take
@@ -1747,7 +1742,7 @@ constexpr int kMaxTilePasses = 4;
 
 struct BinLayout {
     size_t dkeyA, dvalA, dkeyB, dvalB, dcount, offsets, chunk_cnt, chunk_sum, tkey, tval, chunk_rank;
-    size_t big_mat, big_rank, big_slot, big_box, big_len, big_before;
+    size_t big_mat, big_rec, big_len, big_before;
     size_t zero_begin, gdiff, stat_ranges, stat_depth, stat_tile, ghist_depth, ghist_tile;
     size_t big_words, err;
     size_t total;
@@ -1792,9 +1787,7 @@ static BinLayout bin_layout(int64_t n_splats, int64_t cap, int32_t n_tiles)
     // splats listed by the merge: each adds more than kBigMinTiles entries to a list that fits
     L.big_cap = min(n_splats, cap / (kBigMinTiles + 1));
     L.big_mat = o;     o += align256((size_t)L.depth_nb * kBigMaxCams * sizeof(int32_t));
-    L.big_rank = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
-    L.big_slot = o;    o += align256((size_t)L.big_cap * sizeof(int32_t));
-    L.big_box = o;     o += align256((size_t)L.big_cap * sizeof(uint2));
+    L.big_rec = o;     o += align256((size_t)L.big_cap * sizeof(int4));
     L.big_len = o;     o += align256((size_t)n_tiles * sizeof(int32_t));
     L.big_before = o;  o += align256((size_t)n_tiles * sizeof(int32_t));
     L.zero_begin = o;
@@ -1911,9 +1904,8 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     // splats with more than big_tiles tiles are listed by the per-tile merge (launch tuning;
     // calls with more cameras than the merge's table take the plain sort)
     const int big_tiles = (current_tuning().big_tiles > 0 && n_cams <= kBigMaxCams) ? current_tuning().big_tiles : 0;
-    int32_t *big_mat = (int32_t *)(ws + L.big_mat), *big_rank = (int32_t *)(ws + L.big_rank);
-    int32_t *big_slot = (int32_t *)(ws + L.big_slot);
-    uint2 *big_box = (uint2 *)(ws + L.big_box);
+    int32_t *big_mat = (int32_t *)(ws + L.big_mat);
+    int4 *big_rec = (int4 *)(ws + L.big_rec);
     int32_t *big_len = (int32_t *)(ws + L.big_len), *big_before = (int32_t *)(ws + L.big_before);
     int64_t *big_words = (int64_t *)(ws + L.big_words);
 
@@ -1988,7 +1980,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
         hipLaunchKernelGGL(big_scatter_kernel, dim3(g_chunks), dim3(kSortBlock), 0, st, rank_ids,
                            (const int32_t *)rank_tiles, (const int64_t *)dcount, cams, (int)n_cams, big_tiles,
                            (const int4 *)s->rect, (const int32_t *)big_mat, L.depth_nb, (const int64_t *)big_words,
-                           big_rank, big_slot, big_box, err);
+                           big_rec, err);
     }
     // entries the tile passes sort: all K (or none on overflow), or the small splats' ones
     const int64_t *sort_n = big_tiles ? (const int64_t *)(big_words + kBigEffSmall) : K;
@@ -2055,7 +2047,7 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
     if (rc != GS_OK) return rc;
     if (big_tiles)   // the big splats' tiles join the list lengths
         hipLaunchKernelGGL(big_len_kernel, dim3((unsigned)n_cams), dim3(kCountBlock), 0, st, cams, (int)n_cams,
-                           (const int64_t *)big_words, (const uint2 *)big_box, tile_cnt, big_len,
+                           (const int64_t *)big_words, (const int4 *)big_rec, tile_cnt, big_len,
                            (const int64_t *)err);
     // 5. ranges from the list lengths, when the list was built
     hipLaunchKernelGGL(ranges_kernel,
@@ -2067,8 +2059,8 @@ static int bin_and_sort_run(const gs_splats *s, int64_t n_splats, const gs_camer
         hipLaunchKernelGGL(merge_kernel, dim3(grid_for(bins->n_tiles, kMergeWaves)), dim3(kMergeBlock), 0, st, cams,
                            (int)n_cams,
                            bins->n_tiles, (const int64_t *)big_words, (const int32_t *)bins->ranges,
-                           (const int32_t *)big_len, (const int32_t *)big_before, (const int32_t *)big_rank,
-                           (const int32_t *)big_slot, (const uint2 *)big_box, (const int32_t *)vW, rank_ids,
+                           (const int32_t *)big_len, (const int32_t *)big_before, (const int4 *)big_rec,
+                           (const int32_t *)vW, rank_ids,
                            (const int64_t *)dcount, bins->ids, keys_final, s->depth, n_splats, err);
         rc = check_launch("merge");
         if (rc != GS_OK) return rc;
