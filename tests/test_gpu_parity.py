@@ -35,6 +35,10 @@ def _workloads():
         "wide_4k": synth.tiny_scene(42, n=500, width=4100, height=2000, f=2000.0, log_scale=(-2.0, 0.8)),
         # 16 orbit views inside the scene: splats near a camera cover most of its tiles
         "c4_20k": synth.make_config(4, n_override=20_000),
+        # 12 x 10 tiles, up to ~790 small entries per tile (more than the merge walk stages in
+        # LDS at once) under ~125 splats of more than 16 tiles
+        "dense_wrap": synth.tiny_scene(44, n=12_000, width=192, height=160, f=150.0, log_scale=(-3.0, 0.6),
+                                       spread=0.45),
     }
 
 
@@ -99,7 +103,7 @@ def _oracle_list(wl, r):
 
 
 @pytest.mark.parametrize("big_tiles", [16, 64, 1024])
-@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small", "wide_4k", "c4_20k"])
+@pytest.mark.parametrize("name", ["c1", "tiny_tilted", "c2_20k", "dense_small", "wide_4k", "c4_20k", "dense_wrap"])
 def test_bins_bit_exact_with_merge(name, big_tiles):
     """Splats with more than big_tiles tiles listed by the per-tile merge instead of the tile
     sort: keys, ids and ranges bit-exact, and the image as the oracle's."""
