@@ -437,12 +437,14 @@ class TrainStep:
         elif name == "l2_grad":
             abi.gs_l2_grad(r.image.data_ptr(), self.targets.data_ptr(), r.image.numel(), self.dL.data_ptr(), stream)
         elif name == "zero_grads":
-            # the slot gradients of the listed slots (the only ones the backward touches), and
-            # the scene gradients when this step owns them
-            abi.gs_zero_listed_slot_grads(r.splats.struct(P), P, gr["mean2d"].data_ptr(), gr["conic"].data_ptr(),
-                                          stream)
+            # every slot's gradients, with the scene gradients in the same fill when this step
+            # owns them (one allocation). Clearing only the listed slots writes as many lines
+            # where most 128-byte lines hold a listed slot, and its scattered partial-line
+            # writes are slower when the views see most of their scene.
             if self.owns_scene_grads:
-                abi.gs_zero(self.scene_flat.data_ptr(), self.scene_flat.numel() * 4, stream)
+                abi.gs_zero(self.grad_bytes.data_ptr(), self.grad_bytes.numel(), stream)
+            else:
+                abi.gs_zero(self.slot_flat.data_ptr(), self.slot_flat.numel() * 8, stream)
         elif name == "rasterize_bwd":
             abi.gs_rasterize_bwd(r.splats.struct(P), P, r.bins.struct(), cams.ptr, cams.n_cams, r.params,
                                  cams.n_pixels, self.dL.data_ptr(), r.T_final.data_ptr(), r.last.data_ptr(),
