@@ -132,3 +132,30 @@ def test_per_stage_culls_non_positive_depth():
     assert np.array_equal(tiles, two["tiles"])
     assert (tiles[vis[0::4]] == 0).all() and (tiles[vis[1::4]] == 0).all()
     assert st.K == int(two["tiles"].sum())
+
+
+def test_zero_listed_slot_grads_clears_listed_slots_only():
+    """gs_zero_listed_slot_grads: dL/dmu' [2][P] and dL/dY [3][P] become zero at every slot with
+    tiles_touched > 0 and keep their bytes elsewhere; gs_zero clears a whole range."""
+    import torch
+    from paper_2312_02121_amd import abi, pipeline
+    from gpu_helpers import gpu_forward
+    wl = synth.tiny_scene(45, n=300, width=96, height=64, spread=0.9)
+    r, _ = gpu_forward(wl)
+    P = r.cams.n_splats
+    tiles = r.splats.tiles[:P].cpu().numpy()
+    assert 0 < int((tiles > 0).sum()) < P   # some slots listed, some culled
+    dm = torch.full((2, P), 3.5, dtype=torch.float64, device="cuda")
+    dc = torch.full((3, P), -2.25, dtype=torch.float64, device="cuda")
+    st = pipeline.current_stream()
+    abi.gs_zero_listed_slot_grads(r.splats.struct(P), P, dm.data_ptr(), dc.data_ptr(), st)
+    torch.cuda.synchronize()
+    listed = tiles > 0
+    dmh, dch = dm.cpu().numpy(), dc.cpu().numpy()
+    assert np.all(dmh[:, listed] == 0.0) and np.all(dch[:, listed] == 0.0)
+    assert np.all(dmh[:, ~listed] == 3.5) and np.all(dch[:, ~listed] == -2.25)
+    buf = torch.full((1000,), 7, dtype=torch.uint8, device="cuda")
+    abi.gs_zero(buf.data_ptr() + 3, 990, st)   # unaligned head, 16-byte body, byte tail
+    torch.cuda.synchronize()
+    b = buf.cpu().numpy()
+    assert np.all(b[3:993] == 0) and np.all(b[:3] == 7) and np.all(b[993:] == 7)
