@@ -47,6 +47,38 @@ namespace gsx {
 
 constexpr int kScanBlock = 256;
 
+// The value of another lane through a DPP move (0 where the control names no source lane or
+// the row is masked off). Controls used: row_shr:n (0x110 + n, within rows of 16 lanes),
+// row_bcast:15 (0x142, lane 15 of each row to the next row) and row_bcast:31 (0x143, lane
+// 31 to rows 2 and 3).
+template <int Ctrl, int RowMask, typename T>
+__device__ inline T dpp_lane(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, false);
+    } else {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, Ctrl, RowMask, 0xf, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), Ctrl, RowMask, 0xf, false);
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: scans within rows of 16 lanes (shifts by
+// 1, 2, 4, 8), then each row's total carried into the rows above it (two row broadcasts).
+template <typename T>
+__device__ inline T wave_scan_incl(T v)
+{
+    v += dpp_lane<0x111, 0xf>(v);
+    v += dpp_lane<0x112, 0xf>(v);
+    v += dpp_lane<0x114, 0xf>(v);
+    v += dpp_lane<0x118, 0xf>(v);
+    v += dpp_lane<0x142, 0xa>(v);
+    v += dpp_lane<0x143, 0xc>(v);
+    return v;
+}
+
 // Block-wide exclusive scan of one value per thread; returns the exclusive prefix and the
 // block total through *total.
 template <typename T>
@@ -54,12 +86,7 @@ __device__ inline T block_exclusive_scan(T v, T *total)
 {
     __shared__ T wave_tot[kScanBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    T incl = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const T u = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += u;
-    }
+    const T incl = wave_scan_incl(v);
     if (lane == kWave - 1) wave_tot[wave] = incl;
     __syncthreads();
     T before = 0, all = 0;
@@ -916,16 +943,7 @@ __global__ __launch_bounds__(kCornerBlock) void tile_corner_kernel(const int32_t
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
-__device__ inline int wave_inclusive_scan(int v)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int u = __shfl_up(v, d, kWave);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
+__device__ inline int wave_inclusive_scan(int v) { return wave_scan_incl(v); }
 
 constexpr int kCountBlock = 1024;
 
